@@ -1,0 +1,624 @@
+/*
+ * Plain FP64 CPU oracle for Barnes-Hut gravitational potentials on an octree AMR
+ * mesh (Lukat & Banerjee, "A GPU accelerated Barnes-Hut Tree Code for FLASH4").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no code, header or table with the
+ * GPU path: it builds its own octree from the block list, computes every
+ * node's moments directly from the node's own cells, and walks each group with
+ * a per-cell opening test.  It is written to be checked by eye, not to be fast
+ * (OpenMP over independent targets is the only concession).
+ *
+ * What it computes (paper sections cited; readings of unclear passages noted):
+ *
+ *  O1 cells   - a leaf block of level L with lower corner lo has edge
+ *               Lb = box / (nbase 2^L); cell (i,j,k) has h = Lb/8, centre
+ *               lo + (i + 1/2) h and mass rho h^3 (cells act as point masses,
+ *               section 2, footnote on "particles").
+ *  O2 direct  - phi_i = -G sum_{j != i} m_j / |r_i - r_j|  (Eq. 2 of section 1,
+ *               read without its factor 1/2, which belongs to the energy).
+ *  O3 nodes   - every node is a cube with centre c and edge l; M = sum m,
+ *               X = sum m r / M (the centre-of-mass equation of the "Centers of
+ *               Gravitation" kernel section), traceless quadrupole about X,
+ *               Q = sum m (3 D D^T - |D|^2 I), D = r - X, and
+ *               delta = |X - c| (section 2, Eq. THETA2).  M = 0 gives X = c,
+ *               Q = 0, delta = 0.
+ *  O4 groups  - the cells of each leaf block, in Morton order (x bit lowest),
+ *               split into aligned runs of group_cells cells; each group has
+ *               its own opening angle theta_g.
+ *  O5 MAC     - node n is accepted for group g iff every cell i of g has
+ *               d^2 > s^2, d = |r_i - X_n|, s = l (1/theta_g) + delta
+ *               (Eq. THETA2 combined with the all() vote of the potential
+ *               kernel section; equality opens).
+ *  O6 walk    - depth-first from the root; accepted -> far list, rejected
+ *               bottom node (children are cells) -> near list, rejected
+ *               internal node -> visit its 8 children.  Zero-mass nodes are
+ *               skipped.
+ *  O7 sum     - phi_i = -G [ sum_far (M/d + R^T Q R / (2 d^5))
+ *                            + sum_{near cells j != i} m_j / |r_i - r_j| ],
+ *               R = r_i - X_n, with Neumaier-compensated sums.
+ *
+ * Tree shape: the box is the root (depth 0); log2(nbase) virtual levels lead
+ * down to the level-0 blocks; an AMR block of level L sits at depth
+ * log2(nbase) + L; a leaf block has 8 octant nodes (4^3 cells each) and 64
+ * bottom nodes (2^3 cells each) below it.  Node identity across
+ * implementations is the key (depth, ix, iy, iz) of the node's lower corner
+ * in units of its own edge.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NB 8
+#define NCB 512 /* cells per block */
+
+typedef struct {
+    int depth;
+    int64_t ix, iy, iz;
+    double c[3];
+    double l;
+    int bottom;     /* 1: children are the 8 cells below */
+    int child[8];   /* node ids (internal) */
+    int64_t cell[8]; /* canonical cell ids (bottom) */
+    double M, X[3], Q[6], delta; /* Q order: xx yy zz xy xz yz */
+} onode;
+
+typedef struct {
+    int n;
+    int cap;
+    int *v;
+} ivec;
+
+typedef struct otree {
+    int nblk, nbase, vlev;
+    double box_lo[3], box;
+    int nleaf;
+    int *leaf_of_block; /* block -> leaf ordinal or -1 */
+    double *leaf_h;     /* cell edge per leaf */
+    int *block_of_leaf;
+    int nnodes, capnodes;
+    onode *nodes;
+    int root;
+    /* cells, canonical order leaf*512 + z*64 + y*8 + x */
+    int64_t ncells;
+    double *cx, *cy, *cz, *cm;
+    /* sorted keys for lookup */
+    uint64_t *skeys;
+    int *sidx;
+    /* walk results */
+    int group_cells;
+    int64_t ngroups;
+    ivec *far, *near;
+    int64_t *counts; /* [g][4] visited, far, near, marginal */
+} otree;
+
+static void ivec_push(ivec *a, int x) {
+    if (a->n == a->cap) {
+        a->cap = a->cap ? 2 * a->cap : 64;
+        a->v = (int *)realloc(a->v, sizeof(int) * (size_t)a->cap);
+    }
+    a->v[a->n++] = x;
+}
+
+/* Neumaier compensated summation */
+typedef struct { double s, c; } nsum;
+static inline void nadd(nsum *a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static inline double nval(const nsum *a) { return a->s + a->c; }
+
+uint64_t ot_make_key(int depth, int64_t ix, int64_t iy, int64_t iz) {
+    return ((uint64_t)depth << 57) | ((uint64_t)ix << 38) | ((uint64_t)iy << 19) | (uint64_t)iz;
+}
+
+static int new_node(otree *t, int depth, int64_t ix, int64_t iy, int64_t iz) {
+    if (t->nnodes == t->capnodes) {
+        t->capnodes = t->capnodes ? 2 * t->capnodes : 1024;
+        t->nodes = (onode *)realloc(t->nodes, sizeof(onode) * (size_t)t->capnodes);
+    }
+    onode *n = &t->nodes[t->nnodes];
+    memset(n, 0, sizeof(*n));
+    n->depth = depth;
+    n->ix = ix; n->iy = iy; n->iz = iz;
+    n->l = t->box / (double)((int64_t)1 << depth);
+    n->c[0] = t->box_lo[0] + ((double)ix + 0.5) * n->l;
+    n->c[1] = t->box_lo[1] + ((double)iy + 0.5) * n->l;
+    n->c[2] = t->box_lo[2] + ((double)iz + 0.5) * n->l;
+    for (int o = 0; o < 8; o++) n->child[o] = -1;
+    return t->nnodes++;
+}
+
+/* in-block node of a leaf block: sub-level 1 = octant (4^3 cells), 2 = bottom (2^3 cells) */
+static int build_inblock(otree *t, int leaf, int depth, int64_t ix, int64_t iy, int64_t iz,
+                         int sub, int i0, int j0, int k0) {
+    int id = new_node(t, depth, ix, iy, iz);
+    int half = NB >> (sub + 1); /* cells per edge of each child */
+    if (sub == 2) {
+        t->nodes[id].bottom = 1;
+        for (int o = 0; o < 8; o++) {
+            int i = i0 + (o & 1), j = j0 + ((o >> 1) & 1), k = k0 + ((o >> 2) & 1);
+            t->nodes[id].cell[o] = (int64_t)leaf * NCB + (int64_t)k * 64 + j * 8 + i;
+        }
+        return id;
+    }
+    for (int o = 0; o < 8; o++) {
+        int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+        int c = build_inblock(t, leaf, depth + 1, 2 * ix + ox, 2 * iy + oy, 2 * iz + oz, sub + 1,
+                              i0 + ox * half, j0 + oy * half, k0 + oz * half);
+        t->nodes[id].child[o] = c;
+    }
+    return id;
+}
+
+static int build_block(otree *t, const int *child, int b, int depth, int64_t ix, int64_t iy, int64_t iz) {
+    if (t->leaf_of_block[b] >= 0) {
+        /* the leaf block itself is the sub-level-0 node */
+        int leaf = t->leaf_of_block[b];
+        int id = new_node(t, depth, ix, iy, iz);
+        for (int o = 0; o < 8; o++) {
+            int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+            int c = build_inblock(t, leaf, depth + 1, 2 * ix + ox, 2 * iy + oy, 2 * iz + oz, 1,
+                                  ox * 4, oy * 4, oz * 4);
+            t->nodes[id].child[o] = c;
+        }
+        return id;
+    }
+    int id = new_node(t, depth, ix, iy, iz);
+    for (int o = 0; o < 8; o++) {
+        int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+        int c = build_block(t, child, child[8 * b + o], depth + 1, 2 * ix + ox, 2 * iy + oy, 2 * iz + oz);
+        t->nodes[id].child[o] = c;
+    }
+    return id;
+}
+
+static int build_virtual(otree *t, const int *child, const int *base_at, int depth, int64_t ix, int64_t iy,
+                         int64_t iz) {
+    if (depth == t->vlev) {
+        int b = base_at[(iz * t->nbase + iy) * t->nbase + ix];
+        return build_block(t, child, b, depth, ix, iy, iz);
+    }
+    int id = new_node(t, depth, ix, iy, iz);
+    for (int o = 0; o < 8; o++) {
+        int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+        int c = build_virtual(t, child, base_at, depth + 1, 2 * ix + ox, 2 * iy + oy, 2 * iz + oz);
+        t->nodes[id].child[o] = c;
+    }
+    return id;
+}
+
+static uint64_t *g_sort_keys;
+static int cmp_by_key(const void *a, const void *b) {
+    uint64_t ka = g_sort_keys[*(const int *)a], kb = g_sort_keys[*(const int *)b];
+    return ka < kb ? -1 : (ka > kb ? 1 : 0);
+}
+
+/* The block list is assumed valid (the product library validates its input;
+ * the oracle only reads it). */
+otree *ot_create(int nblk, const int *level, const double *lo, const int *parent, const int *child,
+                 const unsigned char *is_leaf, const double *box_lo, double box, int nbase) {
+    (void)parent;
+    otree *t = (otree *)calloc(1, sizeof(otree));
+    t->nblk = nblk;
+    t->nbase = nbase;
+    t->vlev = 0;
+    while ((1 << t->vlev) < nbase) t->vlev++;
+    for (int d = 0; d < 3; d++) t->box_lo[d] = box_lo[d];
+    t->box = box;
+    t->leaf_of_block = (int *)malloc(sizeof(int) * (size_t)nblk);
+    t->nleaf = 0;
+    for (int b = 0; b < nblk; b++) t->leaf_of_block[b] = is_leaf[b] ? t->nleaf++ : -1;
+    t->block_of_leaf = (int *)malloc(sizeof(int) * (size_t)(t->nleaf > 0 ? t->nleaf : 1));
+    for (int b = 0; b < nblk; b++)
+        if (is_leaf[b]) t->block_of_leaf[t->leaf_of_block[b]] = b;
+    int *base_at = (int *)malloc(sizeof(int) * (size_t)(nbase * nbase * nbase));
+    double e0 = box / nbase;
+    for (int b = 0; b < nblk; b++) {
+        if (level[b] != 0) continue;
+        int ix = (int)llround((lo[3 * b] - box_lo[0]) / e0);
+        int iy = (int)llround((lo[3 * b + 1] - box_lo[1]) / e0);
+        int iz = (int)llround((lo[3 * b + 2] - box_lo[2]) / e0);
+        base_at[(iz * nbase + iy) * nbase + ix] = b;
+    }
+    t->root = build_virtual(t, child, base_at, 0, 0, 0, 0);
+    free(base_at);
+    /* cell geometry (O1) */
+    t->ncells = (int64_t)t->nleaf * NCB;
+    t->cx = (double *)malloc(sizeof(double) * (size_t)t->ncells);
+    t->cy = (double *)malloc(sizeof(double) * (size_t)t->ncells);
+    t->cz = (double *)malloc(sizeof(double) * (size_t)t->ncells);
+    t->cm = (double *)calloc((size_t)t->ncells, sizeof(double));
+    t->leaf_h = (double *)malloc(sizeof(double) * (size_t)(t->nleaf > 0 ? t->nleaf : 1));
+    for (int f = 0; f < t->nleaf; f++) {
+        int b = t->block_of_leaf[f];
+        double Lb = box / ((double)nbase * (double)((int64_t)1 << level[b]));
+        double h = Lb / NB;
+        t->leaf_h[f] = h;
+        for (int k = 0; k < NB; k++)
+            for (int j = 0; j < NB; j++)
+                for (int i = 0; i < NB; i++) {
+                    int64_t c = (int64_t)f * NCB + k * 64 + j * 8 + i;
+                    t->cx[c] = lo[3 * b] + (i + 0.5) * h;
+                    t->cy[c] = lo[3 * b + 1] + (j + 0.5) * h;
+                    t->cz[c] = lo[3 * b + 2] + (k + 0.5) * h;
+                }
+    }
+    /* key lookup table */
+    t->skeys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)t->nnodes);
+    t->sidx = (int *)malloc(sizeof(int) * (size_t)t->nnodes);
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)t->nnodes);
+    for (int n = 0; n < t->nnodes; n++) {
+        keys[n] = ot_make_key(t->nodes[n].depth, t->nodes[n].ix, t->nodes[n].iy, t->nodes[n].iz);
+        t->sidx[n] = n;
+    }
+    g_sort_keys = keys;
+    qsort(t->sidx, (size_t)t->nnodes, sizeof(int), cmp_by_key);
+    for (int n = 0; n < t->nnodes; n++) t->skeys[n] = keys[t->sidx[n]];
+    free(keys);
+    return t;
+}
+
+static void free_walk(otree *t) {
+    if (t->far) {
+        for (int64_t g = 0; g < t->ngroups; g++) { free(t->far[g].v); free(t->near[g].v); }
+        free(t->far); free(t->near); free(t->counts);
+    }
+    t->far = t->near = NULL;
+    t->counts = NULL;
+    t->ngroups = 0;
+}
+
+void ot_destroy(otree *t) {
+    if (!t) return;
+    free_walk(t);
+    free(t->leaf_of_block); free(t->block_of_leaf); free(t->leaf_h); free(t->nodes);
+    free(t->cx); free(t->cy); free(t->cz); free(t->cm);
+    free(t->skeys); free(t->sidx);
+    free(t);
+}
+
+int ot_num_nodes(const otree *t) { return t->nnodes; }
+int64_t ot_num_cells(const otree *t) { return t->ncells; }
+int ot_num_leaves(const otree *t) { return t->nleaf; }
+
+/* node i's key, depth, bottom flag, centre and edge */
+void ot_node_info(const otree *t, uint64_t *key, int *depth, int *bottom, double *centre, double *edge) {
+    for (int n = 0; n < t->nnodes; n++) {
+        const onode *a = &t->nodes[n];
+        key[n] = ot_make_key(a->depth, a->ix, a->iy, a->iz);
+        depth[n] = a->depth;
+        bottom[n] = a->bottom;
+        for (int d = 0; d < 3; d++) centre[3 * n + d] = a->c[d];
+        edge[n] = a->l;
+    }
+}
+
+int ot_lookup(const otree *t, uint64_t key) {
+    int lo = 0, hi = t->nnodes - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        if (t->skeys[mid] == key) return t->sidx[mid];
+        if (t->skeys[mid] < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* O1: masses from densities (rho in caller layout [leaf][z][y][x]) */
+void ot_set_density(otree *t, const double *rho) {
+    for (int f = 0; f < t->nleaf; f++) {
+        double h = t->leaf_h[f];
+        double vol = h * h * h;
+        for (int c = 0; c < NCB; c++) t->cm[(int64_t)f * NCB + c] = rho[(int64_t)f * NCB + c] * vol;
+    }
+}
+
+/* enumerate the cells below node n */
+typedef void (*cell_fn)(const otree *, int64_t, void *);
+static void for_cells(const otree *t, int n, cell_fn fn, void *ctx) {
+    const onode *a = &t->nodes[n];
+    if (a->bottom) {
+        for (int o = 0; o < 8; o++) fn(t, a->cell[o], ctx);
+        return;
+    }
+    for (int o = 0; o < 8; o++) for_cells(t, a->child[o], fn, ctx);
+}
+
+typedef struct { nsum m, sx, sy, sz; } acc1;
+static void acc1_fn(const otree *t, int64_t c, void *p) {
+    acc1 *a = (acc1 *)p;
+    double m = t->cm[c];
+    nadd(&a->m, m);
+    nadd(&a->sx, m * t->cx[c]);
+    nadd(&a->sy, m * t->cy[c]);
+    nadd(&a->sz, m * t->cz[c]);
+}
+typedef struct { double X[3]; nsum q[6]; } acc2;
+static void acc2_fn(const otree *t, int64_t c, void *p) {
+    acc2 *a = (acc2 *)p;
+    double m = t->cm[c];
+    double dx = t->cx[c] - a->X[0], dy = t->cy[c] - a->X[1], dz = t->cz[c] - a->X[2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    nadd(&a->q[0], m * (3.0 * dx * dx - r2));
+    nadd(&a->q[1], m * (3.0 * dy * dy - r2));
+    nadd(&a->q[2], m * (3.0 * dz * dz - r2));
+    nadd(&a->q[3], m * (3.0 * dx * dy));
+    nadd(&a->q[4], m * (3.0 * dx * dz));
+    nadd(&a->q[5], m * (3.0 * dy * dz));
+}
+
+/* O3: every node's moments straight from its own cells */
+void ot_moments(otree *t) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int n = 0; n < t->nnodes; n++) {
+        onode *a = &t->nodes[n];
+        acc1 s1;
+        memset(&s1, 0, sizeof(s1));
+        for_cells(t, n, acc1_fn, &s1);
+        double M = nval(&s1.m);
+        a->M = M;
+        if (M > 0.0) {
+            a->X[0] = nval(&s1.sx) / M;
+            a->X[1] = nval(&s1.sy) / M;
+            a->X[2] = nval(&s1.sz) / M;
+            acc2 s2;
+            memset(&s2, 0, sizeof(s2));
+            for (int d = 0; d < 3; d++) s2.X[d] = a->X[d];
+            for_cells(t, n, acc2_fn, &s2);
+            for (int q = 0; q < 6; q++) a->Q[q] = nval(&s2.q[q]);
+            double ex = a->X[0] - a->c[0], ey = a->X[1] - a->c[1], ez = a->X[2] - a->c[2];
+            a->delta = sqrt(ex * ex + ey * ey + ez * ez);
+        } else {
+            for (int d = 0; d < 3; d++) a->X[d] = a->c[d];
+            for (int q = 0; q < 6; q++) a->Q[q] = 0.0;
+            a->delta = 0.0;
+        }
+    }
+}
+
+void ot_get_moments(const otree *t, double *M, double *X, double *Q, double *delta) {
+    for (int n = 0; n < t->nnodes; n++) {
+        const onode *a = &t->nodes[n];
+        M[n] = a->M;
+        for (int d = 0; d < 3; d++) X[3 * n + d] = a->X[d];
+        for (int q = 0; q < 6; q++) Q[6 * n + q] = a->Q[q];
+        delta[n] = a->delta;
+    }
+}
+
+/* Morton decode of a 9-bit in-block index: bit 3p is x, 3p+1 is y, 3p+2 is z */
+static void morton_decode(int m, int *i, int *j, int *k) {
+    *i = *j = *k = 0;
+    for (int p = 0; p < 3; p++) {
+        *i |= ((m >> (3 * p)) & 1) << p;
+        *j |= ((m >> (3 * p + 1)) & 1) << p;
+        *k |= ((m >> (3 * p + 2)) & 1) << p;
+    }
+}
+
+/* canonical cell ids of group g (O4) */
+static void group_cells_of(const otree *t, int64_t g, int G, int64_t *out) {
+    (void)t;
+    int per = NCB / G;
+    int64_t leaf = g / per;
+    int s = (int)(g % per);
+    for (int q = 0; q < G; q++) {
+        int i, j, k;
+        morton_decode(s * G + q, &i, &j, &k);
+        out[q] = leaf * NCB + k * 64 + j * 8 + i;
+    }
+}
+
+typedef struct {
+    const otree *t;
+    const int64_t *cells;
+    int G;
+    double inv_theta;
+    double tau;
+    ivec *far, *near;
+    int64_t visited, marginal;
+} walkctx;
+
+/* O5 + O6 */
+static void walk_node(walkctx *w, int n) {
+    const otree *t = w->t;
+    const onode *a = &t->nodes[n];
+    if (a->M == 0.0) return;
+    w->visited++;
+    double s = a->l * w->inv_theta + a->delta;
+    double s2 = s * s;
+    int accept = 1;
+    double dmin2 = INFINITY;
+    for (int q = 0; q < w->G; q++) {
+        int64_t c = w->cells[q];
+        double dx = t->cx[c] - a->X[0];
+        double dy = t->cy[c] - a->X[1];
+        double dz = t->cz[c] - a->X[2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 > s2)) accept = 0;
+        if (d2 < dmin2) dmin2 = d2;
+    }
+    if (fabs(dmin2 - s2) <= w->tau * s2) w->marginal++;
+    if (accept) {
+        ivec_push(w->far, n);
+    } else if (a->bottom) {
+        ivec_push(w->near, n);
+    } else {
+        for (int o = 0; o < 8; o++) walk_node(w, a->child[o]);
+    }
+}
+
+/* Walk every group; theta_group[g] per group (canonical group order:
+ * leaf-major, then Morton run).  Returns the number of groups. */
+int64_t ot_walk(otree *t, int group_cells, const double *theta_group, double tau) {
+    free_walk(t);
+    int G = group_cells;
+    t->group_cells = G;
+    t->ngroups = (int64_t)t->nleaf * (NCB / G);
+    t->far = (ivec *)calloc((size_t)t->ngroups, sizeof(ivec));
+    t->near = (ivec *)calloc((size_t)t->ngroups, sizeof(ivec));
+    t->counts = (int64_t *)calloc((size_t)t->ngroups * 4, sizeof(int64_t));
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)G);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t g = 0; g < t->ngroups; g++) {
+            group_cells_of(t, g, G, cells);
+            walkctx w;
+            w.t = t; w.cells = cells; w.G = G;
+            w.inv_theta = 1.0 / theta_group[g];
+            w.tau = tau;
+            w.far = &t->far[g]; w.near = &t->near[g];
+            w.visited = 0; w.marginal = 0;
+            walk_node(&w, t->root);
+            t->counts[4 * g + 0] = w.visited;
+            t->counts[4 * g + 1] = t->far[g].n;
+            t->counts[4 * g + 2] = t->near[g].n;
+            t->counts[4 * g + 3] = w.marginal;
+        }
+        free(cells);
+    }
+    return t->ngroups;
+}
+
+void ot_walk_sizes(const otree *t, int64_t *total_far, int64_t *total_near) {
+    int64_t a = 0, b = 0;
+    for (int64_t g = 0; g < t->ngroups; g++) { a += t->far[g].n; b += t->near[g].n; }
+    *total_far = a;
+    *total_near = b;
+}
+
+void ot_walk_export(const otree *t, int64_t *far_off, uint64_t *far_keys, int64_t *near_off, uint64_t *near_keys,
+                    int64_t *counts) {
+    int64_t a = 0, b = 0;
+    for (int64_t g = 0; g < t->ngroups; g++) {
+        far_off[g] = a;
+        near_off[g] = b;
+        for (int q = 0; q < t->far[g].n; q++) {
+            const onode *n = &t->nodes[t->far[g].v[q]];
+            far_keys[a++] = ot_make_key(n->depth, n->ix, n->iy, n->iz);
+        }
+        for (int q = 0; q < t->near[g].n; q++) {
+            const onode *n = &t->nodes[t->near[g].v[q]];
+            near_keys[b++] = ot_make_key(n->depth, n->ix, n->iy, n->iz);
+        }
+    }
+    far_off[t->ngroups] = a;
+    near_off[t->ngroups] = b;
+    memcpy(counts, t->counts, sizeof(int64_t) * 4 * (size_t)t->ngroups);
+}
+
+/* O7 for one group given its lists (node ids) */
+static void sum_group(const otree *t, int64_t g, int G, const int *far, int nfar, const int *near, int nnear,
+                      double Gc, int order, double *phi, int64_t *cells) {
+    group_cells_of(t, g, G, cells);
+    for (int q = 0; q < G; q++) {
+        int64_t i = cells[q];
+        double xi = t->cx[i], yi = t->cy[i], zi = t->cz[i];
+        nsum acc = {0.0, 0.0};
+        for (int f = 0; f < nfar; f++) {
+            const onode *a = &t->nodes[far[f]];
+            double rx = xi - a->X[0], ry = yi - a->X[1], rz = zi - a->X[2];
+            double d2 = rx * rx + ry * ry + rz * rz;
+            double d = sqrt(d2);
+            double rqr = a->Q[0] * rx * rx + a->Q[1] * ry * ry + a->Q[2] * rz * rz
+                         + 2.0 * (a->Q[3] * rx * ry + a->Q[4] * rx * rz + a->Q[5] * ry * rz);
+            nadd(&acc, a->M / d);
+            if (order >= 2) nadd(&acc, rqr / (2.0 * d2 * d2 * d));
+        }
+        for (int b = 0; b < nnear; b++) {
+            const onode *a = &t->nodes[near[b]];
+            for (int o = 0; o < 8; o++) {
+                int64_t j = a->cell[o];
+                if (j == i) continue;
+                double rx = xi - t->cx[j], ry = yi - t->cy[j], rz = zi - t->cz[j];
+                nadd(&acc, t->cm[j] / sqrt(rx * rx + ry * ry + rz * rz));
+            }
+        }
+        phi[i] = -Gc * nval(&acc);
+    }
+}
+
+/* O7 using the lists of the last ot_walk; phi in caller layout.
+ * order 2 = monopole + quadrupole (the method), 0 = monopole only (the
+ * paper's own far field, kept for the convergence-order checks). */
+void ot_potential(const otree *t, double Gc, int order, double *phi) {
+    int G = t->group_cells;
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)G);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t g = 0; g < t->ngroups; g++)
+            sum_group(t, g, G, t->far[g].v, t->far[g].n, t->near[g].v, t->near[g].n, Gc, order, phi, cells);
+        free(cells);
+    }
+}
+
+/* O7 on externally supplied lists (node keys, CSR per group): evaluates
+ * another implementation's interaction lists in FP64.  Returns 0, or -1 if a
+ * key names no node, or -2 if a near key is not a bottom node. */
+int ot_potential_lists(const otree *t, int group_cells, const int64_t *far_off, const uint64_t *far_keys,
+                       const int64_t *near_off, const uint64_t *near_keys, double Gc, int order, double *phi) {
+    int G = group_cells;
+    int64_t ng = (int64_t)t->nleaf * (NCB / G);
+    int err = 0;
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)G);
+        int *fl = NULL, *nl = NULL;
+        int fcap = 0, ncap = 0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t g = 0; g < ng; g++) {
+            int nf = (int)(far_off[g + 1] - far_off[g]);
+            int nn = (int)(near_off[g + 1] - near_off[g]);
+            if (nf > fcap) { fcap = nf; fl = (int *)realloc(fl, sizeof(int) * (size_t)fcap); }
+            if (nn > ncap) { ncap = nn; nl = (int *)realloc(nl, sizeof(int) * (size_t)ncap); }
+            int bad = 0;
+            for (int q = 0; q < nf; q++) {
+                fl[q] = ot_lookup(t, far_keys[far_off[g] + q]);
+                if (fl[q] < 0) bad = -1;
+            }
+            for (int q = 0; q < nn; q++) {
+                nl[q] = ot_lookup(t, near_keys[near_off[g] + q]);
+                if (nl[q] < 0) bad = -1;
+                else if (!t->nodes[nl[q]].bottom) bad = -2;
+            }
+            if (bad) {
+#pragma omp critical
+                err = bad;
+                continue;
+            }
+            sum_group(t, g, G, fl, nf, nl, nn, Gc, order, phi, cells);
+        }
+        free(fl); free(nl); free(cells);
+    }
+    return err;
+}
+
+/* O2 for selected targets (canonical cell ids) */
+void ot_direct(const otree *t, const int64_t *targets, int64_t ntargets, double Gc, double *phi) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t q = 0; q < ntargets; q++) {
+        int64_t i = targets[q];
+        double xi = t->cx[i], yi = t->cy[i], zi = t->cz[i];
+        nsum acc = {0.0, 0.0};
+        for (int64_t j = 0; j < t->ncells; j++) {
+            if (j == i) continue;
+            double rx = xi - t->cx[j], ry = yi - t->cy[j], rz = zi - t->cz[j];
+            nadd(&acc, t->cm[j] / sqrt(rx * rx + ry * ry + rz * rz));
+        }
+        phi[q] = -Gc * nval(&acc);
+    }
+}
+
+/* cell geometry as the oracle sees it (for tests) */
+void ot_cells(const otree *t, double *x, double *y, double *z, double *m) {
+    memcpy(x, t->cx, sizeof(double) * (size_t)t->ncells);
+    memcpy(y, t->cy, sizeof(double) * (size_t)t->ncells);
+    memcpy(z, t->cz, sizeof(double) * (size_t)t->ncells);
+    memcpy(m, t->cm, sizeof(double) * (size_t)t->ncells);
+}
