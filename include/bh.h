@@ -1,0 +1,184 @@
+/*
+ * bh.h -- C ABI of the MI355X (gfx950) Barnes-Hut gravitational potential
+ * library for block-structured octree AMR meshes.
+ *
+ * The library computes, for every cell of an AMR mesh of 8^3-cell blocks, the
+ * potential phi_i = -G sum_{j != i} m_j / |r_i - r_j| (Eq. 2 of the paper's
+ * introduction, without its factor 1/2) approximated by the Barnes-Hut method
+ * of section 2: an octree whose nodes carry mass, centre of mass and (beyond
+ * the paper) a traceless quadrupole; a node is used as a whole when
+ * d > l/theta + delta (Eq. THETA2) holds for every cell of a group of
+ * neighbouring cells (the all() vote of the potential-kernel section).
+ *
+ * Calls in the order the method runs:
+ *   bh_ctx_create -> bh_grid_create -> bh_build_moments -> bh_walk
+ *   -> bh_potential  (bh_direct for the exact O(N^2) reference)
+ *
+ * Conventions for every entry point
+ *  - Return value: BH_OK (0) or a negative BH_E* code; the message of the last
+ *    failure on a context is returned by bh_last_error().  Nothing is thrown
+ *    across the ABI.
+ *  - Pointers named *_dev are device pointers on the context's GPU; every
+ *    other pointer is host memory.  The caller owns all buffers it passes and
+ *    the HIP stream; the library owns its opaque handles and their device
+ *    workspaces, which bh_*_destroy releases.
+ *  - Work is enqueued on the context's stream and is asynchronous unless the
+ *    description says that the call synchronises.
+ *  - Cell-field layout ("caller layout"): fp64 [n_leaf][8][8][8] indexed
+ *    [leaf][z][y][x] (x fastest), leaves numbered in the order they appear in
+ *    the block list.  Canonical cell id = leaf*512 + z*64 + y*8 + x.
+ *  - Group order ("canonical group order"): leaf-major, then the aligned
+ *    Morton runs of group_cells cells inside the block (Morton bit 0 = x).
+ *  - Results are deterministic for a fixed grid, input and parameter set.
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BH_OK 0
+#define BH_EINVAL (-1)     /* invalid argument or malformed grid */
+#define BH_ENOMEM (-2)     /* host or device allocation failed */
+#define BH_EDEVICE (-3)    /* a HIP runtime call failed (message has the hipError_t) */
+#define BH_ECAPACITY (-4)  /* a fixed-size structure would overflow (message says which) */
+#define BH_ESTATE (-5)     /* call out of order (e.g. moments of another grid) */
+
+/* arithmetic of the walk and of the pair sums */
+#define BH_FP64 0 /* everything in fp64 */
+#define BH_FP32 1 /* fp32 opening tests and pair terms, fp64 accumulation per cell */
+
+typedef struct bh_ctx bh_ctx;
+typedef struct bh_grid bh_grid;
+typedef struct bh_moments bh_moments;
+typedef struct bh_lists bh_lists;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  device = -1 creates a host-only
+ * context: grids can be built and inspected (topology only), every GPU entry
+ * point then fails with BH_ESTATE.  Errors: BH_EINVAL (bad device),
+ * BH_EDEVICE, BH_ENOMEM. */
+int bh_ctx_create(bh_ctx **ctx, int device, void *hip_stream);
+/* Replace the stream used by later calls (the caller keeps ownership). */
+int bh_ctx_set_stream(bh_ctx *ctx, void *hip_stream);
+int bh_ctx_destroy(bh_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char *bh_last_error(const bh_ctx *ctx);
+/* Message of the last failed bh_ctx_create in this process. */
+const char *bh_create_error(void);
+
+/* ---------------------------------------------------------------- grid (topology) */
+
+/* Build the octree topology of an AMR mesh (section 3.2.1: data collected per
+ * block, cells treated as point masses; tree nodes down to the cells as in
+ * section 2).  Host arrays, all copied:
+ *   level[n]      AMR level, 0 for the base blocks
+ *   lo[n][3]      lower corner (fp64)
+ *   parent[n]     parent block or -1 (base blocks)
+ *   child[n][8]   children by octant o = ox + 2 oy + 4 oz, -1 for leaves
+ *   is_leaf[n]    1 for leaf blocks (the ones carrying cells)
+ * The base blocks must tile the box [box_lo, box_lo + box_size]^3 as an
+ * nbase^3 lattice with nbase a power of two; log2(nbase) virtual levels join
+ * them under one root.  nb must be 8 (cells per block edge).  group_cells is
+ * the number of neighbouring cells sharing one opening vote and one
+ * interaction list; this build supports 64 (a 4x4x4 Morton sub-cube, one
+ * wavefront).  Errors: BH_EINVAL with the first inconsistency found
+ * (parent/child mismatch, level, position off the lattice, missing base block,
+ * duplicate block, tree deeper than 18 levels), BH_ENOMEM, BH_EDEVICE. */
+int bh_grid_create(bh_ctx *ctx, bh_grid **grid, int n_blocks, int nb, const int32_t *level, const double *lo,
+                   const int32_t *parent, const int32_t *child, const uint8_t *is_leaf, const double box_lo[3],
+                   double box_size, int group_cells);
+int bh_grid_destroy(bh_grid *grid);
+
+typedef struct {
+    int64_t n_nodes;    /* octree nodes: virtual + blocks + in-block (octant, bottom) */
+    int64_t n_leaf;     /* leaf blocks */
+    int64_t n_cells;    /* 512 * n_leaf */
+    int64_t n_groups;   /* n_cells / group_cells */
+    int32_t group_cells;
+    int32_t nbase;      /* base blocks per dimension */
+    int32_t max_depth;  /* depth of the deepest bottom node (root = 0) */
+    int32_t n_levels;   /* AMR levels present (max level + 1) */
+} bh_grid_info_t;
+
+int bh_grid_info(const bh_grid *grid, bh_grid_info_t *info);
+/* Node identity shared with any other implementation: key = depth << 57 |
+ * ix << 38 | iy << 19 | iz, with (ix, iy, iz) the node's lower corner in units
+ * of its own edge box_size / 2^depth.  keys[n_nodes], indexed by node id. */
+int bh_grid_node_keys(const bh_grid *grid, uint64_t *keys);
+
+/* ---------------------------------------------------------------- moments */
+
+/* Upward pass (section 3.2.2 "Centers of Gravitation" kernel, extended to
+ * quadrupoles): cell masses m = rho h^3 at the cell centres, then for every
+ * node its mass M, centre of mass X = sum m r / M (Eq. R), traceless
+ * quadrupole about X, Q = sum m (3 D D^T - |D|^2 I) (combined bottom-up with
+ * the parallel-axis rule), and delta = |X - geometric centre| (Eq. THETA2).
+ * Zero-mass nodes get X = centre, Q = 0, delta = 0 and are skipped by the walk.
+ * rho_dev: fp64 caller layout, read only.  *m is created on first use (pass
+ * *m == NULL) and reused when non-NULL (it must belong to `grid`).
+ * Densities must be finite and >= 0: a violation is detected on the device;
+ * bh_walk (or bh_moments_check) then fails with BH_EINVAL. */
+int bh_build_moments(bh_ctx *ctx, const bh_grid *grid, const double *rho_dev, bh_moments **m);
+/* Synchronise and report whether the densities seen by the last
+ * bh_build_moments were valid (BH_OK) or not (BH_EINVAL). */
+int bh_moments_check(bh_ctx *ctx, const bh_moments *m);
+/* Synchronising host copy, by node id: M[n], X[n][3], Q[n][6] (xx yy zz xy xz
+ * yz), delta[n].  Any pointer may be NULL. */
+int bh_moments_export(bh_ctx *ctx, const bh_moments *m, double *M, double *X, double *Q, double *delta);
+int bh_moments_destroy(bh_moments *m);
+
+/* ---------------------------------------------------------------- walk */
+
+/* Group tree walk (section 3.2.3 potential kernel: depth-first traversal with
+ * the all() vote over a group of neighbouring cells, Eq. THETA2 test
+ * d^2 > (l/theta + delta)^2 at every cell of the group, equality opens).
+ * Accepted nodes form the group's far list; rejected bottom nodes (2^3 cells)
+ * its near list; other rejected nodes are opened.
+ * theta: used for every group when theta_group_dev is NULL; must be in (0, 1].
+ * theta_group_dev: NULL or fp32 [n_groups] in canonical group order, each in
+ * (0, 1] (values outside are clamped into [1e-3, 1]).
+ * precision: BH_FP64 or BH_FP32 arithmetic for the opening test.
+ * *lists is created on first use and reused (grown as needed) when non-NULL.
+ * Synchronises once (to size the lists).  Errors: BH_EINVAL (theta,
+ * precision, or invalid densities seen by bh_build_moments), BH_ECAPACITY
+ * (traversal stack), BH_ESTATE (m not built for grid), BH_ENOMEM, BH_EDEVICE. */
+int bh_walk(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, double theta, const float *theta_group_dev,
+            int precision, bh_lists **lists);
+/* Totals of the last walk: far entries, near entries (bottom nodes). */
+int bh_lists_info(const bh_lists *lists, int64_t *n_far, int64_t *n_near);
+/* Synchronising host copy in canonical group order: far_off[n_groups + 1],
+ * far_node[n_far], near_off[n_groups + 1], near_node[n_near] (node ids, see
+ * bh_grid_node_keys).  Lists of one group keep the walk's order. */
+int bh_lists_export(bh_ctx *ctx, const bh_lists *lists, int64_t *far_off, int32_t *far_node, int64_t *near_off,
+                    int32_t *near_node);
+int bh_lists_destroy(bh_lists *lists);
+
+/* ---------------------------------------------------------------- sums */
+
+/* Potential from the lists (section 3.2.3 accumulation, with quadrupoles):
+ * phi_i = -G [ sum_far (M/d + R^T Q R / (2 d^5)) + sum_{near cells j != i} m_j / d ],
+ * R = r_i - X.  precision BH_FP64: fp64 throughout; BH_FP32: fp32 pair terms
+ * summed in fp32 over tiles of at most 64 nodes / 64 cells, tiles accumulated
+ * in fp64.  phi_dev: fp64 caller layout, fully overwritten. */
+int bh_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_lists *lists, double G,
+                 int precision, double *phi_dev);
+
+/* Exact direct sum (Eq. 2) in fp64 at n_targets canonical cell ids
+ * targets_dev[n] (int64, device); phi_dev[n] receives -G sum_{j != i} m_j/|r_ij|.
+ * Uses the cell masses of the last bh_build_moments on m.  Errors: BH_EINVAL
+ * (n_targets < 0), BH_ESTATE. */
+int bh_direct(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const int64_t *targets_dev,
+              int64_t n_targets, double G, double *phi_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BH_H */

@@ -1,0 +1,230 @@
+"""Thin ctypes binding of libbh.so (C ABI in include/bh.h).
+
+Functions keep the C names and only marshal arguments: torch tensors are
+passed by device pointer, the HIP stream is torch's current stream, results
+stay in caller-owned tensors.  Every step of the method runs in the HIP
+kernels of the library; if the library is missing this module raises on
+import -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbh.so")
+
+BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_ECAPACITY, BH_ESTATE = 0, -1, -2, -3, -4, -5
+BH_FP64, BH_FP32 = 0, 1
+_CODES = {BH_EINVAL: "BH_EINVAL", BH_ENOMEM: "BH_ENOMEM", BH_EDEVICE: "BH_EDEVICE", BH_ECAPACITY: "BH_ECAPACITY",
+          BH_ESTATE: "BH_ESTATE"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libbh.so is not built (run `python -m paper_1509_07370_amd.build`); "
+                      "the Barnes-Hut path has no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [("n_nodes", i64), ("n_leaf", i64), ("n_cells", i64), ("n_groups", i64), ("group_cells", i32),
+                ("nbase", i32), ("max_depth", i32), ("n_levels", i32)]
+
+
+_SIGS = {
+    "bh_ctx_create": (ctypes.c_int, [PP, ctypes.c_int, P]),
+    "bh_ctx_set_stream": (ctypes.c_int, [P, P]),
+    "bh_ctx_destroy": (ctypes.c_int, [P]),
+    "bh_last_error": (ctypes.c_char_p, [P]),
+    "bh_create_error": (ctypes.c_char_p, []),
+    "bh_grid_create": (ctypes.c_int, [P, PP, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, f64, ctypes.c_int]),
+    "bh_grid_destroy": (ctypes.c_int, [P]),
+    "bh_grid_info": (ctypes.c_int, [P, ctypes.POINTER(GridInfo)]),
+    "bh_grid_node_keys": (ctypes.c_int, [P, P]),
+    "bh_build_moments": (ctypes.c_int, [P, P, P, PP]),
+    "bh_moments_check": (ctypes.c_int, [P, P]),
+    "bh_moments_export": (ctypes.c_int, [P, P, P, P, P, P]),
+    "bh_moments_destroy": (ctypes.c_int, [P]),
+    "bh_walk": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, PP]),
+    "bh_lists_info": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+    "bh_lists_export": (ctypes.c_int, [P, P, P, P, P, P]),
+    "bh_lists_destroy": (ctypes.c_int, [P]),
+    "bh_potential": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
+    "bh_direct": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class BHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_CODES.get(code, code), msg))
+        self.code = code
+
+
+def _check(rc, ctx):
+    if rc != BH_OK:
+        msg = _lib.bh_last_error(ctx).decode() if ctx else _lib.bh_create_error().decode()
+        raise BHError(rc, msg)
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev(t, dtype_name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError("tensor must be %s, got %s" % (dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ context
+
+def bh_ctx_create(device: int = 0, stream=None):
+    """device -1 gives a host-only context (topology only)."""
+    h = ctypes.c_void_p()
+    if stream is None and device >= 0:
+        import torch
+        torch.cuda.set_device(device)
+        stream = _current_stream()
+    _check(_lib.bh_ctx_create(ctypes.byref(h), int(device), stream), None)
+    return h
+
+
+def bh_ctx_set_stream(ctx, stream=None):
+    _check(_lib.bh_ctx_set_stream(ctx, _current_stream() if stream is None else stream), ctx)
+
+
+def bh_ctx_destroy(ctx):
+    _lib.bh_ctx_destroy(ctx)
+
+
+def bh_last_error(ctx) -> str:
+    return _lib.bh_last_error(ctx).decode()
+
+
+# ------------------------------------------------------------------ grid
+
+def bh_grid_create(ctx, level, lo, parent, child, is_leaf, box_lo, box_size, group_cells=64, nb=8):
+    arrs = [_np(level, np.int32), _np(lo, np.float64), _np(parent, np.int32), _np(child, np.int32),
+            _np(is_leaf, np.uint8), _np(box_lo, np.float64)]
+    h = ctypes.c_void_p()
+    _check(_lib.bh_grid_create(ctx, ctypes.byref(h), int(arrs[0].size), int(nb), *[_ptr(a) for a in arrs],
+                               float(box_size), int(group_cells)), ctx)
+    return h
+
+
+def bh_grid_create_from(ctx, grid, group_cells=64):
+    """bh_grid_create from an object with level/lo/parent/child/is_leaf/box_lo/box_size attributes."""
+    return bh_grid_create(ctx, grid.level, grid.lo, grid.parent, grid.child, grid.is_leaf, grid.box_lo,
+                          grid.box_size, group_cells)
+
+
+def bh_grid_destroy(grid):
+    _lib.bh_grid_destroy(grid)
+
+
+def bh_grid_info(grid) -> dict:
+    info = GridInfo()
+    _check(_lib.bh_grid_info(grid, ctypes.byref(info)), None)
+    return {name: getattr(info, name) for name, _ in GridInfo._fields_}
+
+
+def bh_grid_node_keys(grid) -> np.ndarray:
+    n = bh_grid_info(grid)["n_nodes"]
+    keys = np.empty(n, np.uint64)
+    _check(_lib.bh_grid_node_keys(grid, _ptr(keys)), None)
+    return keys
+
+
+# ------------------------------------------------------------------ moments
+
+def bh_build_moments(ctx, grid, rho, m=None):
+    """rho: float64 CUDA tensor [n_leaf, 8, 8, 8].  Returns the moments handle."""
+    h = m if m is not None else ctypes.c_void_p()
+    _check(_lib.bh_build_moments(ctx, grid, _dev(rho, "float64"), ctypes.byref(h)), ctx)
+    return h
+
+
+def bh_moments_check(ctx, m):
+    _check(_lib.bh_moments_check(ctx, m), ctx)
+
+
+def bh_moments_export(ctx, m, n_nodes):
+    M = np.empty(n_nodes)
+    X = np.empty((n_nodes, 3))
+    Q = np.empty((n_nodes, 6))
+    d = np.empty(n_nodes)
+    _check(_lib.bh_moments_export(ctx, m, _ptr(M), _ptr(X), _ptr(Q), _ptr(d)), ctx)
+    return dict(M=M, X=X, Q=Q, delta=d)
+
+
+def bh_moments_destroy(m):
+    _lib.bh_moments_destroy(m)
+
+
+# ------------------------------------------------------------------ walk
+
+def bh_walk(ctx, grid, m, theta=0.5, theta_group=None, precision=BH_FP32, lists=None):
+    h = lists if lists is not None else ctypes.c_void_p()
+    tg = _dev(theta_group, "float32") if theta_group is not None else None
+    _check(_lib.bh_walk(ctx, grid, m, float(theta), tg, int(precision), ctypes.byref(h)), ctx)
+    return h
+
+
+def bh_lists_info(lists):
+    a, b = i64(), i64()
+    _check(_lib.bh_lists_info(lists, ctypes.byref(a), ctypes.byref(b)), None)
+    return a.value, b.value
+
+
+def bh_lists_export(ctx, lists, n_groups):
+    nf, nn = bh_lists_info(lists)
+    fo = np.empty(n_groups + 1, np.int64)
+    no = np.empty(n_groups + 1, np.int64)
+    fa = np.empty(max(nf, 1), np.int32)
+    na = np.empty(max(nn, 1), np.int32)
+    _check(_lib.bh_lists_export(ctx, lists, _ptr(fo), _ptr(fa), _ptr(no), _ptr(na)), ctx)
+    return dict(far_off=fo, far_node=fa[:nf], near_off=no, near_node=na[:nn])
+
+
+def bh_lists_destroy(lists):
+    _lib.bh_lists_destroy(lists)
+
+
+# ------------------------------------------------------------------ sums
+
+def bh_potential(ctx, grid, m, lists, G, precision, phi):
+    _check(_lib.bh_potential(ctx, grid, m, lists, float(G), int(precision), _dev(phi, "float64")), ctx)
+    return phi
+
+
+def bh_direct(ctx, grid, m, targets, G, phi):
+    n = int(targets.numel())
+    _check(_lib.bh_direct(ctx, grid, m, _dev(targets, "int64"), n, float(G), _dev(phi, "float64")), ctx)
+    return phi

@@ -1,0 +1,137 @@
+// Internal declarations of the Barnes-Hut library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bh.h"
+
+namespace bh {
+
+constexpr int kNB = 8;          // cells per block edge
+constexpr int kCellsPerBlock = 512;
+constexpr int kGroupCells = 64;  // cells per group = lanes per wavefront
+constexpr int kWalkStackCap = 256;  // LDS stack entries per wavefront (sibling sets)
+constexpr int kMaxDepth = 18;
+
+enum NodeFlags : int { FLAG_BOTTOM = 1, FLAG_EMPTY = 2 };
+
+// Walk record, fp32: centre of mass, delta, edge, first child (node id for
+// internal nodes, first internal cell id for bottom nodes), flags.  32 bytes.
+struct alignas(16) WalkRec32 {
+    float x, y, z, delta;
+    float l;
+    int child;
+    int flags;
+    int pad;
+};
+// Walk record, fp64.  48 bytes.
+struct alignas(16) WalkRec64 {
+    double x, y, z, delta;
+    double l;
+    int child;
+    int flags;
+};
+// Far-field record, fp32: COM, mass and the quadrupole pre-scaled for
+// R^T Q R / 2 = a x^2 + b y^2 + f z^2 + c xy + d xz + e yz
+// (a = Qxx/2, b = Qyy/2, f = Qzz/2, c = Qxy, d = Qxz, e = Qyz).  48 bytes.
+struct alignas(16) FarRec32 {
+    float x, y, z, m;
+    float a, b, f, c;
+    float d, e, pad0, pad1;
+};
+// fp64 node moments, 12 doubles per node:
+//   0 X, 1 Y, 2 Z, 3 M, 4 Qxx, 5 Qyy, 6 Qzz, 7 Qxy, 8 Qxz, 9 Qyz, 10 delta, 11 unused
+constexpr int kMom = 12;
+
+// Per leaf block, internal (Morton) order.  48 bytes.
+struct alignas(16) LeafInfo {
+    double lo[3];
+    double h;         // cell edge
+    int canon;        // leaf ordinal in the caller's block list
+    int block_node;   // node id of the block
+    int oct_first;    // node id of octant 0 (8 consecutive)
+    int bot_first;    // node id of bottom node 0 (64 consecutive, Morton order)
+};
+
+// Host-side octree topology built from the block list.
+struct Topology {
+    int nbase = 0, vlev = 0, nblocks = 0, n_levels = 0, max_depth = 0, root = 0;
+    int64_t n_nodes = 0;
+    std::vector<uint64_t> key;        // [n_nodes]
+    std::vector<double> geom;         // [n_nodes][4]: centre x, y, z, edge
+    std::vector<int32_t> child;       // [n_nodes]
+    std::vector<int32_t> flags;       // [n_nodes] static FLAG_BOTTOM
+    std::vector<LeafInfo> leaves;     // internal leaf order
+    std::vector<int32_t> internal_of_canon;  // canonical leaf -> internal leaf
+    std::vector<int32_t> combine_nodes;      // virtual + parent-block nodes, deepest depth first
+    std::vector<int64_t> combine_off;        // per depth bucket (deepest first), size n_buckets + 1
+};
+
+// Returns "" on success, else the reason the block list is rejected.
+std::string build_topology(Topology &t, int n_blocks, const int32_t *level, const double *lo,
+                           const int32_t *parent, const int32_t *child, const uint8_t *is_leaf,
+                           const double box_lo[3], double box_size);
+
+}  // namespace bh
+
+struct bh_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+struct bh_grid {
+    bh_ctx *ctx = nullptr;
+    bh::Topology topo;
+    int group_cells = bh::kGroupCells;
+    int64_t n_groups = 0;
+    int64_t n_cells = 0;
+    // device copies of the static topology
+    double *d_geom = nullptr;            // [n_nodes][4]
+    int32_t *d_child = nullptr;          // [n_nodes]
+    int32_t *d_flags = nullptr;          // [n_nodes]
+    bh::LeafInfo *d_leaves = nullptr;    // [n_leaf]
+    int32_t *d_internal_of_canon = nullptr;
+    int32_t *d_combine = nullptr;
+};
+
+struct bh_moments {
+    const bh_grid *grid = nullptr;
+    double *d_mom = nullptr;              // [n_nodes][kMom]
+    bh::WalkRec32 *d_w32 = nullptr;
+    bh::WalkRec64 *d_w64 = nullptr;
+    bh::FarRec32 *d_f32 = nullptr;
+    double4 *d_cell64 = nullptr;          // [n_cells] x, y, z, m (internal order)
+    float4 *d_cell32 = nullptr;
+    int *d_err = nullptr;                 // density check flag
+};
+
+struct bh_lists {
+    const bh_grid *grid = nullptr;
+    int64_t cap_far = 0, cap_near = 0;
+    int64_t n_far = 0, n_near = 0;
+    int32_t *d_far = nullptr, *d_near = nullptr;         // node ids
+    int64_t *d_far_off = nullptr, *d_near_off = nullptr;  // [n_groups + 1], internal group order
+    int32_t *d_far_cnt = nullptr, *d_near_cnt = nullptr;  // [n_groups]
+    int64_t *d_partials = nullptr;                        // scan block sums
+    int64_t *h_totals = nullptr;                          // pinned [2]
+    int *d_err = nullptr;                                 // stack overflow flag
+    int precision = BH_FP32;
+};
+
+namespace bh {
+// kernel launchers (bh_kernels.hip); all enqueue on `s`.
+hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s);
+hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
+                       int precision, bool fill, hipStream_t s);
+hipError_t launch_scan(const bh_grid *g, bh_lists *L, hipStream_t s);
+hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_lists *L, double G, int precision,
+                            double *phi, hipStream_t s);
+hipError_t launch_direct(const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,
+                         double *phi, hipStream_t s);
+int walk_k8_threshold(int max_depth);
+}  // namespace bh

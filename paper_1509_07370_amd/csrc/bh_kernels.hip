@@ -1,0 +1,806 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the Barnes-Hut potential path.
+//
+//   moments_leaf_kernel    one workgroup per leaf block: cells -> 64 bottom nodes
+//                          -> 8 octants -> block node, in LDS (fp64)
+//   moments_combine_kernel one thread per parent/virtual node, one launch per
+//                          tree depth, deepest first (parallel-axis rule)
+//   walk_kernel            one wavefront per 64-cell group: breadth-limited
+//                          depth-first traversal with an LDS stack of sibling
+//                          sets; 64 lanes test 8 sibling sets at once, the
+//                          group vote is exact and O(1) per node (see below)
+//   scan kernels           CSR offsets of the interaction lists
+//   potential kernels      one wavefront per group, one lane per cell; far
+//                          nodes and near cells staged through LDS in tiles of
+//                          64 and read back as wave-wide broadcasts
+//   direct_kernel          exact fp64 O(N^2) reference
+#include <hip/hip_runtime.h>
+
+#include "bh_internal.h"
+
+namespace bh {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int morton9(int i, int j, int k) {
+    int m = 0;
+#pragma unroll
+    for (int p = 0; p < 3; p++)
+        m |= (((i >> p) & 1) << (3 * p)) | (((j >> p) & 1) << (3 * p + 1)) | (((k >> p) & 1) << (3 * p + 2));
+    return m;
+}
+
+__device__ __forceinline__ void demorton9(int m, int &i, int &j, int &k) {
+    i = j = k = 0;
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+        i |= ((m >> (3 * p)) & 1) << p;
+        j |= ((m >> (3 * p + 1)) & 1) << p;
+        k |= ((m >> (3 * p + 2)) & 1) << p;
+    }
+}
+
+// LDS written by one wavefront and read back by the same wavefront: DS
+// instructions of a wave execute in order, so only the compiler must be kept
+// from moving accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_prefix(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+struct MomOut {
+    double *mom;
+    WalkRec32 *w32;
+    WalkRec64 *w64;
+    FarRec32 *f32;
+};
+
+// Write every derived record of node `id` from its fp64 moments.
+__device__ void store_node(const MomOut &o, int id, double M, double X, double Y, double Z, const double *Q,
+                           const double *geom, int child, int sflags) {
+#pragma clang fp contract(off)
+    double cx = geom[0], cy = geom[1], cz = geom[2], l = geom[3];
+    double q[6];
+    double delta;
+    int flags = sflags;
+    if (M > 0.0) {
+        double ex = X - cx, ey = Y - cy, ez = Z - cz;
+        delta = sqrt(ex * ex + ey * ey + ez * ez);
+        for (int c = 0; c < 6; c++) q[c] = Q[c];
+    } else {
+        X = cx;
+        Y = cy;
+        Z = cz;
+        delta = 0.0;
+        for (int c = 0; c < 6; c++) q[c] = 0.0;
+        flags |= FLAG_EMPTY;
+        M = 0.0;
+    }
+    double *mo = o.mom + (int64_t)id * kMom;
+    mo[0] = X;
+    mo[1] = Y;
+    mo[2] = Z;
+    mo[3] = M;
+    for (int c = 0; c < 6; c++) mo[4 + c] = q[c];
+    mo[10] = delta;
+    mo[11] = 0.0;
+    WalkRec32 w;
+    w.x = (float)X;
+    w.y = (float)Y;
+    w.z = (float)Z;
+    w.delta = (float)delta;
+    w.l = (float)l;
+    w.child = child;
+    w.flags = flags;
+    w.pad = 0;
+    o.w32[id] = w;
+    WalkRec64 w2;
+    w2.x = X;
+    w2.y = Y;
+    w2.z = Z;
+    w2.delta = delta;
+    w2.l = l;
+    w2.child = child;
+    w2.flags = flags;
+    o.w64[id] = w2;
+    FarRec32 f;
+    f.x = (float)X;
+    f.y = (float)Y;
+    f.z = (float)Z;
+    f.m = (float)M;
+    f.a = (float)(0.5 * q[0]);
+    f.b = (float)(0.5 * q[1]);
+    f.f = (float)(0.5 * q[2]);
+    f.c = (float)q[3];
+    f.d = (float)q[4];
+    f.e = (float)q[5];
+    f.pad0 = 0.f;
+    f.pad1 = 0.f;
+    o.f32[id] = f;
+}
+
+// Parallel-axis combination of 8 children (masses Mc, centres of mass Xc,
+// quadrupoles Qc about their own centres of mass) into the parent moments.
+__device__ void combine8(const double *Mc, const double *Xc, const double *Yc, const double *Zc,
+                         const double (*Qc)[6], double &M, double &X, double &Y, double &Z, double *Q) {
+#pragma clang fp contract(off)
+    M = 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int c = 0; c < 8; c++) {
+        M += Mc[c];
+        sx += Mc[c] * Xc[c];
+        sy += Mc[c] * Yc[c];
+        sz += Mc[c] * Zc[c];
+    }
+    for (int c = 0; c < 6; c++) Q[c] = 0.0;
+    X = Y = Z = 0.0;
+    if (!(M > 0.0)) return;
+    X = sx / M;
+    Y = sy / M;
+    Z = sz / M;
+    for (int c = 0; c < 8; c++) {
+        double m = Mc[c];
+        double dx = Xc[c] - X, dy = Yc[c] - Y, dz = Zc[c] - Z;
+        double r2 = dx * dx + dy * dy + dz * dz;
+        Q[0] += Qc[c][0] + m * (3.0 * dx * dx - r2);
+        Q[1] += Qc[c][1] + m * (3.0 * dy * dy - r2);
+        Q[2] += Qc[c][2] + m * (3.0 * dz * dz - r2);
+        Q[3] += Qc[c][3] + m * (3.0 * dx * dy);
+        Q[4] += Qc[c][4] + m * (3.0 * dx * dz);
+        Q[5] += Qc[c][5] + m * (3.0 * dy * dz);
+    }
+}
+
+// ---------------------------------------------------------------- moments
+
+__global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restrict__ rho,
+                                                           const LeafInfo *__restrict__ leaves,
+                                                           const double *__restrict__ geom,
+                                                           const int32_t *__restrict__ child_arr, MomOut out,
+                                                           double4 *__restrict__ cell64, float4 *__restrict__ cell32,
+                                                           int *__restrict__ err) {
+#pragma clang fp contract(off)
+    __shared__ double sm[512], sx[512], sy[512], sz[512];
+    __shared__ double bM[64], bX[64], bY[64], bZ[64], bQ[64][6];
+    __shared__ double oM[8], oX[8], oY[8], oZ[8], oQ[8][6];
+    const int f = blockIdx.x;
+    const int t = threadIdx.x;
+    const LeafInfo L = leaves[f];
+    const int i = t & 7, j = (t >> 3) & 7, k = t >> 6;
+    const double r = rho[(int64_t)L.canon * kCellsPerBlock + t];
+    if (!(r >= 0.0) || !isfinite(r)) atomicOr(err, 1);
+    const double h = L.h;
+    const double vol = h * h * h;
+    const double mass = r * vol;
+    const double x = L.lo[0] + (i + 0.5) * h;
+    const double y = L.lo[1] + (j + 0.5) * h;
+    const double z = L.lo[2] + (k + 0.5) * h;
+    const int m = morton9(i, j, k);
+    const int64_t c = (int64_t)f * kCellsPerBlock + m;
+    cell64[c] = make_double4(x, y, z, mass);
+    cell32[c] = make_float4((float)x, (float)y, (float)z, (float)mass);
+    sm[m] = mass;
+    sx[m] = x;
+    sy[m] = y;
+    sz[m] = z;
+    __syncthreads();
+    if (t < 64) {
+        double M = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+        for (int q = 0; q < 8; q++) {
+            int s = 8 * t + q;
+            M += sm[s];
+            ax += sm[s] * sx[s];
+            ay += sm[s] * sy[s];
+            az += sm[s] * sz[s];
+        }
+        double X = 0.0, Y = 0.0, Z = 0.0, Q[6] = {0, 0, 0, 0, 0, 0};
+        if (M > 0.0) {
+            X = ax / M;
+            Y = ay / M;
+            Z = az / M;
+            for (int q = 0; q < 8; q++) {
+                int s = 8 * t + q;
+                double dx = sx[s] - X, dy = sy[s] - Y, dz = sz[s] - Z;
+                double r2 = dx * dx + dy * dy + dz * dz;
+                Q[0] += sm[s] * (3.0 * dx * dx - r2);
+                Q[1] += sm[s] * (3.0 * dy * dy - r2);
+                Q[2] += sm[s] * (3.0 * dz * dz - r2);
+                Q[3] += sm[s] * (3.0 * dx * dy);
+                Q[4] += sm[s] * (3.0 * dx * dz);
+                Q[5] += sm[s] * (3.0 * dy * dz);
+            }
+        }
+        int id = L.bot_first + t;
+        store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], FLAG_BOTTOM);
+        bM[t] = M;
+        bX[t] = M > 0.0 ? X : geom[4 * (int64_t)id + 0];
+        bY[t] = M > 0.0 ? Y : geom[4 * (int64_t)id + 1];
+        bZ[t] = M > 0.0 ? Z : geom[4 * (int64_t)id + 2];
+        for (int q = 0; q < 6; q++) bQ[t][q] = Q[q];
+    }
+    __syncthreads();
+    if (t < 8) {
+        double M, X, Y, Z, Q[6];
+        combine8(bM + 8 * t, bX + 8 * t, bY + 8 * t, bZ + 8 * t, bQ + 8 * t, M, X, Y, Z, Q);
+        int id = L.oct_first + t;
+        store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], 0);
+        oM[t] = M;
+        oX[t] = M > 0.0 ? X : geom[4 * (int64_t)id + 0];
+        oY[t] = M > 0.0 ? Y : geom[4 * (int64_t)id + 1];
+        oZ[t] = M > 0.0 ? Z : geom[4 * (int64_t)id + 2];
+        for (int q = 0; q < 6; q++) oQ[t][q] = Q[q];
+    }
+    __syncthreads();
+    if (t == 0) {
+        double M, X, Y, Z, Q[6];
+        combine8(oM, oX, oY, oZ, oQ, M, X, Y, Z, Q);
+        int id = L.block_node;
+        store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], 0);
+    }
+}
+
+__global__ __launch_bounds__(256) void moments_combine_kernel(const int32_t *__restrict__ nodes, int64_t count,
+                                                              const double *__restrict__ geom,
+                                                              const int32_t *__restrict__ child_arr, MomOut out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const int id = nodes[q];
+    const int first = child_arr[id];
+    double Mc[8], Xc[8], Yc[8], Zc[8], Qc[8][6];
+    for (int c = 0; c < 8; c++) {
+        const double *mo = out.mom + (int64_t)(first + c) * kMom;
+        Mc[c] = mo[3];
+        Xc[c] = mo[0];
+        Yc[c] = mo[1];
+        Zc[c] = mo[2];
+        for (int k = 0; k < 6; k++) Qc[c][k] = mo[4 + k];
+    }
+    double M, X, Y, Z, Q[6];
+    combine8(Mc, Xc, Yc, Zc, Qc, M, X, Y, Z, Q);
+    store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, first, 0);
+}
+
+hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s) {
+    MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32};
+    hipError_t e = hipMemsetAsync(m->d_err, 0, sizeof(int), s);
+    if (e != hipSuccess) return e;
+    const int nleaf = (int)g->topo.leaves.size();
+    hipLaunchKernelGGL(moments_leaf_kernel, dim3(nleaf), dim3(512), 0, s, rho, g->d_leaves, g->d_geom, g->d_child, o,
+                       m->d_cell64, m->d_cell32, m->d_err);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const auto &off = g->topo.combine_off;
+    for (size_t b = 0; b + 1 < off.size(); b++) {
+        int64_t cnt = off[b + 1] - off[b];
+        int blocks = (int)((cnt + 255) / 256);
+        hipLaunchKernelGGL(moments_combine_kernel, dim3(blocks), dim3(256), 0, s, g->d_combine + off[b], cnt,
+                           g->d_geom, g->d_child, o);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------- walk
+
+template <typename real>
+struct WalkRecOf;
+template <>
+struct WalkRecOf<float> {
+    using type = WalkRec32;
+};
+template <>
+struct WalkRecOf<double> {
+    using type = WalkRec64;
+};
+
+// min over k in [0, n) of |fl(x0 + k h - X)|.  x0 + k h is exact (dyadic), and
+// fl(a - X) is monotone in a, so the minimum sits at one of the two lattice
+// points around X; both are evaluated exactly as a per-cell test would.
+template <typename real>
+__device__ __forceinline__ real nearest_gap(real x0, real h, real X, int n) {
+#pragma clang fp contract(off)
+    real t = (X - x0) / h;
+    int k = (int)floor(t);
+    k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+    int k2 = k + 1 > n - 1 ? n - 1 : k + 1;
+    real d1 = (x0 + (real)k * h) - X;
+    real d2 = (x0 + (real)k2 * h) - X;
+    d1 = d1 < 0 ? -d1 : d1;
+    d2 = d2 < 0 ? -d2 : d2;
+    return d1 < d2 ? d1 : d2;
+}
+
+struct WalkArgs {
+    const void *nodes;
+    const LeafInfo *leaves;
+    const float *theta_group;
+    double theta;
+    int64_t n_groups;
+    int root;
+    int k8_threshold;
+    int32_t *far_cnt, *near_cnt;
+    const int64_t *far_off, *near_off;
+    int32_t *far_out, *near_out;
+    int *err;
+};
+
+// The group vote of the potential kernel (all lanes accept) needs, per node,
+// min over the group's cells of d^2.  The group is an axis-aligned 4x4x4
+// lattice of cell centres, so that minimum separates per axis: the cell whose
+// per-axis gaps are each minimal has the smallest rounded d^2 too (rounding is
+// monotone).  One lane therefore decides one node exactly as 64 per-cell tests
+// would, and the wave tests 64 nodes (8 sibling sets) per step.
+template <typename real, bool FILL>
+__global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
+    using Rec = typename WalkRecOf<real>::type;
+    __shared__ int stack[4][kWalkStackCap];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    int *stk = stack[w];
+    const Rec *nodes = (const Rec *)a.nodes;
+    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const LeafInfo L = a.leaves[f];
+    const int i0 = (sub & 1) * 4, j0 = ((sub >> 1) & 1) * 4, k0 = ((sub >> 2) & 1) * 4;
+    const real h = (real)L.h;
+    const real x0 = (real)(L.lo[0] + (i0 + 0.5) * L.h);
+    const real y0 = (real)(L.lo[1] + (j0 + 0.5) * L.h);
+    const real z0 = (real)(L.lo[2] + (k0 + 0.5) * L.h);
+    real inv;
+    if (a.theta_group) {
+        float th = a.theta_group[(int64_t)L.canon * 8 + sub];
+        th = th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
+        if (!(th == th)) th = 1e-3f;
+        inv = (real)1 / (real)th;
+    } else {
+        inv = (real)(1.0 / a.theta);
+        if (sizeof(real) == 4) inv = (real)(1.0f / (float)a.theta);
+    }
+    int64_t fbase = 0, nbase = 0;
+    if (FILL) {
+        fbase = a.far_off[g];
+        nbase = a.near_off[g];
+    }
+    int size = 0;
+    {
+        const Rec root = nodes[a.root];
+        if (!(root.flags & FLAG_EMPTY)) {
+            if (lane == 0) stk[0] = root.child;
+            size = 1;
+        }
+    }
+    wave_lds_sync();
+    int nf = 0, nn = 0;
+    bool overflow = false;
+    while (size > 0) {
+        const int k = size <= a.k8_threshold ? (size < 8 ? size : 8) : 1;
+        const int slot = lane >> 3;
+        const bool active = slot < k;
+        int id = 0;
+        if (active) id = stk[size - 1 - slot] + (lane & 7);
+        size -= k;
+        wave_lds_sync();
+        bool acc = false, nr = false, op = false;
+        int ch = 0;
+        if (active) {
+            const Rec r = nodes[id];
+            if (!(r.flags & FLAG_EMPTY)) {
+#pragma clang fp contract(off)
+                real dx = nearest_gap<real>(x0, h, r.x, 4);
+                real dy = nearest_gap<real>(y0, h, r.y, 4);
+                real dz = nearest_gap<real>(z0, h, r.z, 4);
+                real d2 = dx * dx + dy * dy + dz * dz;
+                real s = r.l * inv + r.delta;
+                acc = d2 > s * s;
+                if (!acc) {
+                    if (r.flags & FLAG_BOTTOM)
+                        nr = true;
+                    else {
+                        op = true;
+                        ch = r.child;
+                    }
+                }
+            }
+        }
+        const uint64_t mf = __ballot(acc);
+        const uint64_t mn = __ballot(nr);
+        const uint64_t mo = __ballot(op);
+        if (FILL) {
+            if (acc) a.far_out[fbase + nf + lane_prefix(mf)] = id;
+            if (nr) a.near_out[nbase + nn + lane_prefix(mn)] = id;
+        }
+        nf += __popcll(mf);
+        nn += __popcll(mn);
+        if (op) {
+            int p = size + lane_prefix(mo);
+            if (p < kWalkStackCap)
+                stk[p] = ch;
+            else
+                overflow = true;
+        }
+        size += __popcll(mo);
+        if (size > kWalkStackCap) {
+            overflow = true;
+            size = 0;
+        }
+        wave_lds_sync();
+    }
+    if (__ballot(overflow) != 0 && lane == 0) atomicOr(a.err, 1);
+    if (!FILL && lane == 0) {
+        a.far_cnt[g] = nf;
+        a.near_cnt[g] = nn;
+    }
+}
+
+int walk_k8_threshold(int max_depth) { return kWalkStackCap - 64 - 7 * (max_depth + 1) - 8; }
+
+hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
+                       int precision, bool fill, hipStream_t s) {
+    WalkArgs a;
+    a.nodes = precision == BH_FP64 ? (const void *)m->d_w64 : (const void *)m->d_w32;
+    a.leaves = g->d_leaves;
+    a.theta_group = theta_group;
+    a.theta = theta;
+    a.n_groups = g->n_groups;
+    a.root = g->topo.root;
+    a.k8_threshold = walk_k8_threshold(g->topo.max_depth);
+    a.far_cnt = L->d_far_cnt;
+    a.near_cnt = L->d_near_cnt;
+    a.far_off = L->d_far_off;
+    a.near_off = L->d_near_off;
+    a.far_out = L->d_far;
+    a.near_out = L->d_near;
+    a.err = L->d_err;
+    const int blocks = (int)((g->n_groups + 3) / 4);
+    if (precision == BH_FP64) {
+        if (fill)
+            hipLaunchKernelGGL((walk_kernel<double, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_kernel<double, false>), dim3(blocks), dim3(256), 0, s, a);
+    } else {
+        if (fill)
+            hipLaunchKernelGGL((walk_kernel<float, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_kernel<float, false>), dim3(blocks), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scan
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t &total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        int64_t add = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[kScanBlock - 1];
+    int64_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(const int32_t *__restrict__ a,
+                                                                 const int32_t *__restrict__ b, int64_t n,
+                                                                 int64_t *__restrict__ partials, int nblocks) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t sa = 0, sb = 0;
+    for (int q = 0; q < kScanItems; q++) {
+        if (base + q < n) {
+            sa += a[base + q];
+            sb += b[base + q];
+        }
+    }
+    int64_t ta, tb;
+    block_exclusive_scan(sa, sh, ta);
+    block_exclusive_scan(sb, sh, tb);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = ta;
+        partials[nblocks + blockIdx.x] = tb;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_partials_kernel(int64_t *__restrict__ partials, int nblocks,
+                                                                   int64_t *__restrict__ totals_a,
+                                                                   int64_t *__restrict__ totals_b) {
+    __shared__ int64_t sh[kScanBlock];
+    for (int which = 0; which < 2; which++) {
+        int64_t *p = partials + (int64_t)which * nblocks;
+        int64_t carry = 0;
+        for (int base = 0; base < nblocks; base += kScanBlock) {
+            int idx = base + threadIdx.x;
+            int64_t v = idx < nblocks ? p[idx] : 0;
+            int64_t tot;
+            int64_t ex = block_exclusive_scan(v, sh, tot);
+            if (idx < nblocks) p[idx] = ex + carry;
+            carry += tot;
+        }
+        if (threadIdx.x == 0) *(which == 0 ? totals_a : totals_b) = carry;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const int32_t *__restrict__ a,
+                                                                const int32_t *__restrict__ b, int64_t n,
+                                                                const int64_t *__restrict__ partials, int nblocks,
+                                                                int64_t *__restrict__ oa, int64_t *__restrict__ ob) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t va[kScanItems], vb[kScanItems];
+    int64_t sa = 0, sb = 0;
+    for (int q = 0; q < kScanItems; q++) {
+        va[q] = base + q < n ? a[base + q] : 0;
+        vb[q] = base + q < n ? b[base + q] : 0;
+        sa += va[q];
+        sb += vb[q];
+    }
+    int64_t ta, tb;
+    int64_t ea = block_exclusive_scan(sa, sh, ta) + partials[blockIdx.x];
+    int64_t eb = block_exclusive_scan(sb, sh, tb) + partials[nblocks + blockIdx.x];
+    for (int q = 0; q < kScanItems; q++) {
+        if (base + q < n) {
+            oa[base + q] = ea;
+            ob[base + q] = eb;
+        }
+        ea += va[q];
+        eb += vb[q];
+    }
+}
+
+hipError_t launch_scan(const bh_grid *g, bh_lists *L, hipStream_t s) {
+    const int64_t n = g->n_groups;
+    const int nblocks = (int)((n + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, L->d_far_cnt, L->d_near_cnt, n,
+                       L->d_partials, nblocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, L->d_partials, nblocks,
+                       L->d_far_off + n, L->d_near_off + n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, L->d_far_cnt, L->d_near_cnt, n,
+                       L->d_partials, nblocks, L->d_far_off, L->d_near_off);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- potential
+
+struct PotArgs {
+    const int64_t *far_off, *near_off;
+    const int32_t *far_idx, *near_idx;
+    const void *far_rec;         // FarRec32 (fp32) or fp64 moments (kMom doubles)
+    const int32_t *child;        // node -> first internal cell (bottom nodes)
+    const void *cells;           // float4 / double4, internal order
+    const LeafInfo *leaves;
+    int64_t n_groups;
+    double G;
+    double *phi;
+};
+
+__device__ __forceinline__ int64_t phi_index(const LeafInfo &L, int sub, int lane) {
+    int i, j, k;
+    demorton9(sub * 64 + lane, i, j, k);
+    return (int64_t)L.canon * kCellsPerBlock + k * 64 + j * 8 + i;
+}
+
+__global__ __launch_bounds__(256) void potential32_kernel(PotArgs a) {
+    __shared__ float4 tile[4][64 * 3];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    float4 *T = tile[w];
+    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const float4 *cells = (const float4 *)a.cells;
+    const float4 me = cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
+    double acc = 0.0;
+    // far field: monopole + quadrupole
+    {
+        const int64_t b0 = a.far_off[g], e0 = a.far_off[g + 1];
+        const float4 *rec = (const float4 *)a.far_rec;
+        for (int64_t b = b0; b < e0; b += 64) {
+            const int n = (int)(e0 - b < 64 ? e0 - b : 64);
+            if (lane < n) {
+                const int64_t id = a.far_idx[b + lane];
+                T[3 * lane + 0] = rec[3 * id + 0];
+                T[3 * lane + 1] = rec[3 * id + 1];
+                T[3 * lane + 2] = rec[3 * id + 2];
+            }
+            wave_lds_sync();
+            float part = 0.f;
+            for (int j = 0; j < n; j++) {
+                const float4 p = T[3 * j + 0];
+                const float4 q = T[3 * j + 1];
+                const float4 u = T[3 * j + 2];
+                const float dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
+                const float x2 = dx * dx, y2 = dy * dy, z2 = dz * dz;
+                const float r2 = x2 + y2 + z2;
+                const float ri = rsqrtf(r2);
+                const float ri2 = ri * ri;
+                // q = (a, b, f, c), u = (d, e, -, -)
+                float quad = q.x * x2 + q.y * y2 + q.z * z2;
+                quad += dx * (q.w * dy + u.x * dz) + u.y * dy * dz;
+                part += p.w * ri + quad * (ri2 * ri2 * ri);
+            }
+            acc += (double)part;
+            wave_lds_sync();
+        }
+    }
+    // near field: cells of the near bottom nodes, self pair excluded (r2 == 0)
+    {
+        const int64_t b0 = a.near_off[g], e0 = a.near_off[g + 1];
+        for (int64_t b = b0; b < e0; b += 8) {
+            const int n = (int)(e0 - b < 8 ? e0 - b : 8);
+            if (lane < 8 * n) {
+                const int id = a.near_idx[b + (lane >> 3)];
+                T[lane] = cells[(int64_t)a.child[id] + (lane & 7)];
+            }
+            wave_lds_sync();
+            float part = 0.f;
+            for (int j = 0; j < 8 * n; j++) {
+                const float4 s = T[j];
+                const float dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float t = s.w * rsqrtf(r2);
+                part += r2 > 0.f ? t : 0.f;
+            }
+            acc += (double)part;
+            wave_lds_sync();
+        }
+    }
+    a.phi[phi_index(a.leaves[f], sub, lane)] = -a.G * acc;
+}
+
+__global__ __launch_bounds__(256) void potential64_kernel(PotArgs a) {
+    __shared__ double4 tile[4][64 * 3];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    double4 *T = tile[w];
+    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const double4 *cells = (const double4 *)a.cells;
+    const double4 me = cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
+    double acc = 0.0;
+    {
+        const int64_t b0 = a.far_off[g], e0 = a.far_off[g + 1];
+        const double4 *rec = (const double4 *)a.far_rec;  // kMom = 12 doubles = 3 double4
+        for (int64_t b = b0; b < e0; b += 64) {
+            const int n = (int)(e0 - b < 64 ? e0 - b : 64);
+            if (lane < n) {
+                const int64_t id = a.far_idx[b + lane];
+                T[3 * lane + 0] = rec[3 * id + 0];
+                T[3 * lane + 1] = rec[3 * id + 1];
+                T[3 * lane + 2] = rec[3 * id + 2];
+            }
+            wave_lds_sync();
+            double part = 0.0;
+            for (int j = 0; j < n; j++) {
+                const double4 p = T[3 * j + 0];  // X Y Z M
+                const double4 q = T[3 * j + 1];  // Qxx Qyy Qzz Qxy
+                const double4 u = T[3 * j + 2];  // Qxz Qyz delta -
+                const double dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double d = sqrt(r2);
+                const double ri = 1.0 / d;
+                const double ri2 = ri * ri;
+                const double quad = 0.5 * (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) +
+                                    (q.w * dx * dy + u.x * dx * dz + u.y * dy * dz);
+                part += p.w * ri + quad * (ri2 * ri2 * ri);
+            }
+            acc += part;
+            wave_lds_sync();
+        }
+    }
+    {
+        const int64_t b0 = a.near_off[g], e0 = a.near_off[g + 1];
+        for (int64_t b = b0; b < e0; b += 8) {
+            const int n = (int)(e0 - b < 8 ? e0 - b : 8);
+            if (lane < 8 * n) {
+                const int id = a.near_idx[b + (lane >> 3)];
+                T[lane] = cells[(int64_t)a.child[id] + (lane & 7)];
+            }
+            wave_lds_sync();
+            double part = 0.0;
+            for (int j = 0; j < 8 * n; j++) {
+                const double4 s = T[j];
+                const double dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 > 0.0) part += s.w / sqrt(r2);
+            }
+            acc += part;
+            wave_lds_sync();
+        }
+    }
+    a.phi[phi_index(a.leaves[f], sub, lane)] = -a.G * acc;
+}
+
+hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_lists *L, double G, int precision,
+                            double *phi, hipStream_t s) {
+    PotArgs a;
+    a.far_off = L->d_far_off;
+    a.near_off = L->d_near_off;
+    a.far_idx = L->d_far;
+    a.near_idx = L->d_near;
+    a.child = g->d_child;
+    a.leaves = g->d_leaves;
+    a.n_groups = g->n_groups;
+    a.G = G;
+    a.phi = phi;
+    const int blocks = (int)((g->n_groups + 3) / 4);
+    if (precision == BH_FP64) {
+        a.far_rec = m->d_mom;
+        a.cells = m->d_cell64;
+        hipLaunchKernelGGL(potential64_kernel, dim3(blocks), dim3(256), 0, s, a);
+    } else {
+        a.far_rec = m->d_f32;
+        a.cells = m->d_cell32;
+        hipLaunchKernelGGL(potential32_kernel, dim3(blocks), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- direct
+
+__global__ __launch_bounds__(256) void direct_kernel(const int64_t *__restrict__ targets, int64_t n,
+                                                     const double4 *__restrict__ cells, int64_t ncells,
+                                                     const int32_t *__restrict__ internal_of_canon, double G,
+                                                     double *__restrict__ phi) {
+    __shared__ double4 tile[256];
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = t < n;
+    int64_t self = -1;
+    bool ok = false;
+    double4 me = make_double4(0, 0, 0, 0);
+    if (valid) {
+        const int64_t cid = targets[t];
+        if (cid >= 0 && cid < ncells) {
+            const int64_t leaf = cid / kCellsPerBlock;
+            const int local = (int)(cid % kCellsPerBlock);
+            const int f = internal_of_canon[leaf];
+            self = (int64_t)f * kCellsPerBlock + morton9(local & 7, (local >> 3) & 7, local >> 6);
+            me = cells[self];
+            ok = true;
+        }
+    }
+    double acc = 0.0;
+    for (int64_t base = 0; base < ncells; base += 256) {
+        __syncthreads();
+        tile[threadIdx.x] = cells[base + threadIdx.x];  // ncells is a multiple of 512
+        __syncthreads();
+        double part = 0.0;
+        for (int j = 0; j < 256; j++) {
+            const double4 s = tile[j];
+            const double dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (base + j != self) part += s.w / sqrt(r2);
+        }
+        acc += part;
+    }
+    if (valid) phi[t] = ok ? -G * acc : __builtin_nan("");
+}
+
+hipError_t launch_direct(const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,
+                         double *phi, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(direct_kernel, dim3(blocks), dim3(256), 0, s, targets, n, m->d_cell64, g->n_cells,
+                       g->d_internal_of_canon, G, phi);
+    return hipGetLastError();
+}
+
+}  // namespace bh
