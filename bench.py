@@ -7,8 +7,8 @@ of eccentricity 0.9 and semi-major axis 0.25 in the unit box, rho = 1 inside and
 (2752 leaf blocks, 1,409,024 cells), group size 64, G = 1.
 
 One step = the whole hot path with the densities already in HBM:
-moments upward pass -> group walk (count pass, list offsets, fill pass) ->
-far + near potential sums.  The metric is whole-step throughput in Mcells/s at
+moments upward pass -> group walk fused with the far + near potential sums
+(bh_walk_potential; the list API path is timed beside it in the sweep).  The metric is whole-step throughput in Mcells/s at
 the largest theta of {0.3, 0.5, 0.7} whose RMS relative error against the
 exact direct sum (computed on the GPU in fp64, outside the timed region) is at
 most 1e-3.
@@ -40,11 +40,11 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_flops(lists_host):
-    """35 per cell-node far interaction + 11 per near cell pair (self excluded)."""
-    fo, no = lists_host["far_off"], lists_host["near_off"]
-    n_far = np.diff(fo).astype(np.int64)
-    n_near = np.diff(no).astype(np.int64)
+def algorithmic_flops(n_far, n_near):
+    """35 per cell-node far interaction + 11 per near cell pair (self excluded);
+    n_far / n_near: far nodes and near bottom nodes per 64-cell group."""
+    n_far = np.asarray(n_far, np.int64)
+    n_near = np.asarray(n_near, np.int64)
     far_int = 64 * int(n_far.sum())
     near_pairs = int((512 * n_near - 64).clip(min=0).sum())
     return F_FAR * far_int + F_NEAR * near_pairs, far_int, near_pairs
@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the accuracy sweep and CPU baseline (for profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -71,6 +73,16 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB three times (reads %d KiB and writes %d KiB per copy)" % (
+            args.copy_calibration, args.copy_calibration * 1024, args.copy_calibration * 1024))
+        return
     t0 = time.time()
     grid = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
     log("workload: %d leaf blocks, %d cells (%.1f s to generate)" % (grid.nleaf, grid.ncells, time.time() - t0))
@@ -81,7 +93,15 @@ def main():
     phi = torch.empty_like(rho)
     ncells = grid.ncells
 
+    counts = torch.zeros((bh.info["n_groups"], 2), dtype=torch.int32, device=dev)
+
     def step(theta, prec):
+        """one pass of the hot path: moments, then the fused walk + far/near sums"""
+        bh.build_moments(rho)
+        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, theta, None, prec, 1.0, phi, None)
+
+    def step_lists(theta, prec):
+        """the same pass through the list API (walk count + scan + fill, then sums)"""
         bh.build_moments(rho)
         bh.walk(theta, None, prec)
         bh.potential(phi, 1.0, prec)
@@ -108,12 +128,17 @@ def main():
                     step(th, prec)
                 torch.cuda.synchronize()
                 ms = (time.perf_counter() - t0) * 1e3 / 5
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    step_lists(th, prec)
+                torch.cuda.synchronize()
+                ms_lists = (time.perf_counter() - t0) * 1e3 / 5
                 nf, nn = B.bh_lists_info(bh.lists)
                 sweep.append(dict(theta=th, precision="fp32" if prec == B.BH_FP32 else "fp64", rms_rel_err=rms,
                                   max_rel_err=mx, ms_per_step=ms, mcells_per_s=ncells / ms / 1e3,
-                                  far_entries=nf, near_entries=nn))
-                log("sweep %s theta=%.1f rms=%.2e max=%.2e %.3f ms %.1f Mcells/s" % (
-                    sweep[-1]["precision"], th, rms, mx, ms, ncells / ms / 1e3))
+                                  ms_per_step_list_api=ms_lists, far_entries=nf, near_entries=nn))
+                log("sweep %s theta=%.1f rms=%.2e max=%.2e fused %.3f ms (%.1f Mcells/s), lists %.3f ms" % (
+                    sweep[-1]["precision"], th, rms, mx, ms, ncells / ms / 1e3, ms_lists))
         ok = [s["theta"] for s in sweep if s["precision"] == "fp32" and s["rms_rel_err"] <= RMS_GATE]
         head_theta = max(ok) if ok else min(thetas)
     prec = B.BH_FP32
@@ -129,20 +154,23 @@ def main():
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     log("timed %d steps at theta=%.1f: %.3f ms/step" % (args.steps, head_theta, ms_step))
 
-    # ---- dominant kernel: far+near potential sums, timed with events on the library's stream
+    bh.check()
+
+    # ---- dominant kernel: fused walk + far/near sums, timed with events on the library's stream
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     nrep = max(args.steps, 10)
     ev0.record(stream)
     for _ in range(nrep):
-        bh.potential(phi, 1.0, prec)
+        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, head_theta, None, prec, 1.0, phi, None)
     ev1.record(stream)
     torch.cuda.synchronize()
     pot_ms = ev0.elapsed_time(ev1) / nrep
-    lists_host = bh.lists_host()
-    flops, far_int, near_pairs = algorithmic_flops(lists_host)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, head_theta, None, prec, 1.0, phi, counts)
+    c = counts.cpu().numpy().astype(np.int64)
+    flops, far_int, near_pairs = algorithmic_flops(c[:, 0], c[:, 1])
     achieved = flops / (pot_ms * 1e-3) / 1e12
-    log("potential kernel %.4f ms, %.3e flop -> %.2f TFLOP/s" % (pot_ms, flops, achieved))
+    log("walk+potential kernel %.4f ms, %.3e flop -> %.2f TFLOP/s" % (pot_ms, flops, achieved))
 
     cpu = None
     if not args.no_cpu_baseline and not args.profile_only:
@@ -179,7 +207,7 @@ def main():
                    "precision": "fp32-walk/fp64-accumulate"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "potential32_kernel", "kernel_ms": pot_ms, "flop_per_launch": flops,
+                     "kernel": "walk_potential_kernel<float>", "kernel_ms": pot_ms, "flop_per_launch": flops,
                      "far_interactions": far_int, "near_pairs": near_pairs},
         "cpu_baseline": cpu,
         "topology_ms": topo_ms,

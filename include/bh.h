@@ -127,8 +127,9 @@ int bh_grid_node_keys(const bh_grid *grid, uint64_t *keys);
  * Densities must be finite and >= 0: a violation is detected on the device;
  * bh_walk (or bh_moments_check) then fails with BH_EINVAL. */
 int bh_build_moments(bh_ctx *ctx, const bh_grid *grid, const double *rho_dev, bh_moments **m);
-/* Synchronise and report whether the densities seen by the last
- * bh_build_moments were valid (BH_OK) or not (BH_EINVAL). */
+/* Synchronise and report device-side conditions: BH_EINVAL if the densities
+ * seen by the last bh_build_moments were invalid, BH_ECAPACITY if the last walk
+ * on these moments overflowed its traversal stack, else BH_OK. */
 int bh_moments_check(bh_ctx *ctx, const bh_moments *m);
 /* Synchronising host copy, by node id: M[n], X[n][3], Q[n][6] (xx yy zz xy xz
  * yz), delta[n].  Any pointer may be NULL. */
@@ -170,6 +171,18 @@ int bh_lists_destroy(bh_lists *lists);
  * in fp64.  phi_dev: fp64 caller layout, fully overwritten. */
 int bh_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_lists *lists, double G,
                  int precision, double *phi_dev);
+
+/* Walk and potential in one pass (the same method and the same tiles, in the
+ * same order, as bh_walk followed by bh_potential, hence the same bits), without
+ * materialising the interaction lists and without synchronising: accepted
+ * nodes and near bottom nodes are buffered per group in on-chip memory and
+ * summed tile by tile as the traversal produces them.  Arguments as for
+ * bh_walk / bh_potential.  counts_dev: NULL or int32 [n_groups][2] receiving
+ * each group's far-node and near-bottom-node counts (canonical group order).
+ * Device-side conditions (invalid densities, traversal stack overflow) are
+ * reported by a later bh_moments_check. */
+int bh_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, double theta,
+                      const float *theta_group_dev, int precision, double G, double *phi_dev, int32_t *counts_dev);
 
 /* Exact direct sum (Eq. 2) in fp64 at n_targets canonical cell ids
  * targets_dev[n] (int64, device); phi_dev[n] receives -G sum_{j != i} m_j/|r_ij|.

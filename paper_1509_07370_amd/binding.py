@@ -55,6 +55,7 @@ _SIGS = {
     "bh_lists_export": (ctypes.c_int, [P, P, P, P, P, P]),
     "bh_lists_destroy": (ctypes.c_int, [P]),
     "bh_potential": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
+    "bh_walk_potential": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P]),
     "bh_direct": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -221,6 +222,14 @@ def bh_lists_destroy(lists):
 
 def bh_potential(ctx, grid, m, lists, G, precision, phi):
     _check(_lib.bh_potential(ctx, grid, m, lists, float(G), int(precision), _dev(phi, "float64")), ctx)
+    return phi
+
+
+def bh_walk_potential(ctx, grid, m, theta, theta_group, precision, G, phi, counts=None):
+    tg = _dev(theta_group, "float32") if theta_group is not None else None
+    cn = _dev(counts, "int32") if counts is not None else None
+    _check(_lib.bh_walk_potential(ctx, grid, m, float(theta), tg, int(precision), float(G), _dev(phi, "float64"), cn),
+           ctx)
     return phi
 
 

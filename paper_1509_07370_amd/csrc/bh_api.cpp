@@ -57,8 +57,10 @@ void free_grid_device(bh_grid *g) {
     hfree(g->d_leaves);
     hfree(g->d_internal_of_canon);
     hfree(g->d_combine);
+    hfree(g->d_combine_off);
     g->d_geom = nullptr;
     g->d_child = g->d_flags = g->d_internal_of_canon = g->d_combine = nullptr;
+    g->d_combine_off = nullptr;
     g->d_leaves = nullptr;
 }
 
@@ -158,7 +160,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
             (e = dalloc(&g->d_flags, t.flags.size())) != hipSuccess ||
             (e = dalloc(&g->d_leaves, t.leaves.size())) != hipSuccess ||
             (e = dalloc(&g->d_internal_of_canon, t.internal_of_canon.size())) != hipSuccess ||
-            (e = dalloc(&g->d_combine, t.combine_nodes.size())) != hipSuccess) {
+            (e = dalloc(&g->d_combine, t.combine_nodes.size())) != hipSuccess ||
+            (e = dalloc(&g->d_combine_off, t.combine_off.size())) != hipSuccess) {
             free_grid_device(g);
             delete g;
             return hip_fail(ctx, e, "device allocation of the grid topology");
@@ -172,7 +175,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
                   {g->d_flags, t.flags.data(), t.flags.size() * sizeof(int32_t)},
                   {g->d_leaves, t.leaves.data(), t.leaves.size() * sizeof(bh::LeafInfo)},
                   {g->d_internal_of_canon, t.internal_of_canon.data(), t.internal_of_canon.size() * sizeof(int32_t)},
-                  {g->d_combine, t.combine_nodes.data(), t.combine_nodes.size() * sizeof(int32_t)}};
+                  {g->d_combine, t.combine_nodes.data(), t.combine_nodes.size() * sizeof(int32_t)},
+                  {g->d_combine_off, t.combine_off.data(), t.combine_off.size() * sizeof(int64_t)}};
         for (auto &u : up) {
             if (u.n == 0) continue;
             e = hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice);
@@ -227,7 +231,7 @@ int bh_moments_destroy(bh_moments *m) {
     hfree(m->d_f32);
     hfree(m->d_cell64);
     hfree(m->d_cell32);
-    hfree(m->d_err);
+    hfree(m->d_flags);
     delete m;
     return BH_OK;
 }
@@ -248,7 +252,8 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
         if ((e = dalloc(&m->d_mom, (size_t)nn * bh::kMom)) != hipSuccess ||
             (e = dalloc(&m->d_w32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_w64, (size_t)nn)) != hipSuccess ||
             (e = dalloc(&m->d_f32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_cell64, (size_t)nc)) != hipSuccess ||
-            (e = dalloc(&m->d_cell32, (size_t)nc)) != hipSuccess || (e = dalloc(&m->d_err, 1)) != hipSuccess) {
+            (e = dalloc(&m->d_cell32, (size_t)nc)) != hipSuccess || (e = dalloc(&m->d_flags, 2)) != hipSuccess ||
+            (e = hipMemset(m->d_flags, 0, 2 * sizeof(int))) != hipSuccess) {
             bh_moments_destroy(m);
             return hip_fail(ctx, e, "device allocation of the moments");
         }
@@ -262,10 +267,11 @@ int bh_moments_check(bh_ctx *ctx, const bh_moments *m) {
     int rc = require_gpu(ctx);
     if (rc) return rc;
     if (!m) return fail(ctx, BH_EINVAL, "moments handle is NULL");
-    int flag = 0;
-    HIPX(ctx, hipMemcpyAsync(&flag, m->d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "copy check flag");
+    int flags[2] = {0, 0};
+    HIPX(ctx, hipMemcpyAsync(flags, m->d_flags, sizeof(flags), hipMemcpyDeviceToHost, ctx->stream), "copy flags");
     HIPX(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-    if (flag) return fail(ctx, BH_EINVAL, "densities must be finite and >= 0");
+    if (m->mom_epoch > 0 && flags[0] == m->mom_epoch) return fail(ctx, BH_EINVAL, "densities must be finite and >= 0");
+    if (m->walk_epoch > 0 && flags[1] == m->walk_epoch) return fail(ctx, BH_ECAPACITY, "walk stack overflow");
     return BH_OK;
 }
 
@@ -308,8 +314,8 @@ int bh_lists_destroy(bh_lists *L) {
     hfree(L->d_far_cnt);
     hfree(L->d_near_cnt);
     hfree(L->d_partials);
-    hfree(L->d_err);
-    if (L->h_totals) (void)hipHostFree(L->h_totals);
+    hfree(L->d_status);
+    if (L->h_status) (void)hipHostFree(L->h_status);
     delete L;
     return BH_OK;
 }
@@ -336,8 +342,8 @@ int bh_walk(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double theta, co
             (e = dalloc(&L->d_far_cnt, (size_t)ng)) != hipSuccess ||
             (e = dalloc(&L->d_near_cnt, (size_t)ng)) != hipSuccess ||
             (e = dalloc(&L->d_partials, (size_t)2 * nblocks)) != hipSuccess ||
-            (e = dalloc(&L->d_err, 1)) != hipSuccess ||
-            (e = hipHostMalloc((void **)&L->h_totals, 4 * sizeof(int64_t), hipHostMallocDefault)) != hipSuccess) {
+            (e = dalloc(&L->d_status, 4)) != hipSuccess ||
+            (e = hipHostMalloc((void **)&L->h_status, 4 * sizeof(int64_t), hipHostMallocDefault)) != hipSuccess) {
             bh_lists_destroy(L);
             return hip_fail(ctx, e, "allocation of the list offsets");
         }
@@ -345,18 +351,15 @@ int bh_walk(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double theta, co
     }
     L->precision = precision;
     hipStream_t s = ctx->stream;
-    HIPX(ctx, hipMemsetAsync(L->d_err, 0, sizeof(int), s), "clear walk flag");
+    m->walk_epoch++;
     HIPX(ctx, bh::launch_walk(g, m, L, theta, theta_group, precision, false, s), "walk (count pass)");
-    HIPX(ctx, bh::launch_scan(g, L, s), "list offsets");
-    HIPX(ctx, hipMemcpyAsync(L->h_totals, L->d_far_off + ng, sizeof(int64_t), hipMemcpyDeviceToHost, s), "totals");
-    HIPX(ctx, hipMemcpyAsync(L->h_totals + 1, L->d_near_off + ng, sizeof(int64_t), hipMemcpyDeviceToHost, s), "totals");
-    int *flags = (int *)(L->h_totals + 2);
-    HIPX(ctx, hipMemcpyAsync(flags, L->d_err, sizeof(int), hipMemcpyDeviceToHost, s), "walk flag");
-    HIPX(ctx, hipMemcpyAsync(flags + 1, m->d_err, sizeof(int), hipMemcpyDeviceToHost, s), "density flag");
+    HIPX(ctx, bh::launch_scan(g, m, L, s), "list offsets");
+    HIPX(ctx, hipMemcpyAsync(L->h_status, L->d_status, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "status");
     HIPX(ctx, hipStreamSynchronize(s), "synchronise after the count pass");
-    if (flags[1]) return fail(ctx, BH_EINVAL, "densities must be finite and >= 0");
-    if (flags[0]) return fail(ctx, BH_ECAPACITY, "walk stack overflow");
-    const int64_t nf = L->h_totals[0], nn = L->h_totals[1];
+    if (m->mom_epoch > 0 && L->h_status[3] == m->mom_epoch)
+        return fail(ctx, BH_EINVAL, "densities must be finite and >= 0");
+    if (L->h_status[2] == m->walk_epoch) return fail(ctx, BH_ECAPACITY, "walk stack overflow");
+    const int64_t nf = L->h_status[0], nn = L->h_status[1];
     if (nf > L->cap_far) {
         hfree(L->d_far);
         L->d_far = nullptr;
@@ -438,6 +441,21 @@ int bh_potential(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const bh_li
     if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
     if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
     HIPX(ctx, bh::launch_potential(g, m, L, G, precision, phi, ctx->stream), "potential kernel");
+    return BH_OK;
+}
+
+int bh_walk_potential(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                      int precision, double G, double *phi, int32_t *counts) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!g || !m || !phi) return fail(ctx, BH_EINVAL, "grid, moments or phi_dev is NULL");
+    if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
+    if (!theta_group && !(theta > 0.0 && theta <= 1.0)) return fail(ctx, BH_EINVAL, "theta must be in (0, 1]");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    m->walk_epoch++;
+    HIPX(ctx, bh::launch_walk_potential(g, m, theta, theta_group, precision, G, phi, counts, ctx->stream),
+         "fused walk + potential kernel");
     return BH_OK;
 }
 

@@ -97,6 +97,7 @@ struct bh_grid {
     bh::LeafInfo *d_leaves = nullptr;    // [n_leaf]
     int32_t *d_internal_of_canon = nullptr;
     int32_t *d_combine = nullptr;
+    int64_t *d_combine_off = nullptr;
 };
 
 struct bh_moments {
@@ -107,7 +108,12 @@ struct bh_moments {
     bh::FarRec32 *d_f32 = nullptr;
     double4 *d_cell64 = nullptr;          // [n_cells] x, y, z, m (internal order)
     float4 *d_cell32 = nullptr;
-    int *d_err = nullptr;                 // density check flag
+    // d_flags[0]: epoch of the last moments build that saw an invalid density;
+    // d_flags[1]: epoch of the last walk whose traversal stack overflowed.
+    // Epoch stamps (atomicMax) replace clearing the flags before every call.
+    int *d_flags = nullptr;
+    int mom_epoch = 0;
+    mutable int walk_epoch = 0;
 };
 
 struct bh_lists {
@@ -118,8 +124,8 @@ struct bh_lists {
     int64_t *d_far_off = nullptr, *d_near_off = nullptr;  // [n_groups + 1], internal group order
     int32_t *d_far_cnt = nullptr, *d_near_cnt = nullptr;  // [n_groups]
     int64_t *d_partials = nullptr;                        // scan block sums
-    int64_t *h_totals = nullptr;                          // pinned [2]
-    int *d_err = nullptr;                                 // stack overflow flag
+    int64_t *d_status = nullptr;  // [4]: far total, near total, walk flag, density flag
+    int64_t *h_status = nullptr;  // pinned copy of d_status
     int precision = BH_FP32;
 };
 
@@ -128,7 +134,9 @@ namespace bh {
 hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s);
 hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
                        int precision, bool fill, hipStream_t s);
-hipError_t launch_scan(const bh_grid *g, bh_lists *L, hipStream_t s);
+hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipStream_t s);
+hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                                 int precision, double G, double *phi, int32_t *counts, hipStream_t s);
 hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_lists *L, double G, int precision,
                             double *phi, hipStream_t s);
 hipError_t launch_direct(const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,

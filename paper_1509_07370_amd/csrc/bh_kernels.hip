@@ -162,7 +162,7 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
                                                            const double *__restrict__ geom,
                                                            const int32_t *__restrict__ child_arr, MomOut out,
                                                            double4 *__restrict__ cell64, float4 *__restrict__ cell32,
-                                                           int *__restrict__ err) {
+                                                           int *__restrict__ flags, int epoch) {
 #pragma clang fp contract(off)
     __shared__ double sm[512], sx[512], sy[512], sz[512];
     __shared__ double bM[64], bX[64], bY[64], bZ[64], bQ[64][6];
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
     const LeafInfo L = leaves[f];
     const int i = t & 7, j = (t >> 3) & 7, k = t >> 6;
     const double r = rho[(int64_t)L.canon * kCellsPerBlock + t];
-    if (!(r >= 0.0) || !isfinite(r)) atomicOr(err, 1);
+    if (!(r >= 0.0) || !isfinite(r)) atomicMax(flags, epoch);
     const double h = L.h;
     const double vol = h * h * h;
     const double mass = r * vol;
@@ -243,12 +243,8 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
     }
 }
 
-__global__ __launch_bounds__(256) void moments_combine_kernel(const int32_t *__restrict__ nodes, int64_t count,
-                                                              const double *__restrict__ geom,
-                                                              const int32_t *__restrict__ child_arr, MomOut out) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= count) return;
-    const int id = nodes[q];
+__device__ __forceinline__ void combine_node(int id, const double *__restrict__ geom,
+                                             const int32_t *__restrict__ child_arr, const MomOut &out) {
     const int first = child_arr[id];
     double Mc[8], Xc[8], Yc[8], Zc[8], Qc[8][6];
     for (int c = 0; c < 8; c++) {
@@ -264,17 +260,46 @@ __global__ __launch_bounds__(256) void moments_combine_kernel(const int32_t *__r
     store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, first, 0);
 }
 
+// One tree depth of parent-block / virtual nodes (used when there are many).
+__global__ __launch_bounds__(256) void moments_combine_kernel(const int32_t *__restrict__ nodes, int64_t count,
+                                                              const double *__restrict__ geom,
+                                                              const int32_t *__restrict__ child_arr, MomOut out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    combine_node(nodes[q], geom, child_arr, out);
+}
+
+// All depths in one workgroup, deepest first, a barrier between depths (the
+// usual case: a few hundred to a few thousand nodes above the leaf blocks).
+__global__ __launch_bounds__(1024) void moments_levels_kernel(const int32_t *__restrict__ nodes,
+                                                              const int64_t *__restrict__ off, int nbuckets,
+                                                              const double *__restrict__ geom,
+                                                              const int32_t *__restrict__ child_arr, MomOut out) {
+    for (int b = 0; b < nbuckets; b++) {
+        for (int64_t q = off[b] + threadIdx.x; q < off[b + 1]; q += blockDim.x) combine_node(nodes[q], geom, child_arr, out);
+        __syncthreads();
+    }
+}
+
+constexpr int64_t kSingleWorkgroupCombine = 16384;
+
 hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s) {
     MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32};
-    hipError_t e = hipMemsetAsync(m->d_err, 0, sizeof(int), s);
-    if (e != hipSuccess) return e;
     const int nleaf = (int)g->topo.leaves.size();
+    const int epoch = ++m->mom_epoch;
     hipLaunchKernelGGL(moments_leaf_kernel, dim3(nleaf), dim3(512), 0, s, rho, g->d_leaves, g->d_geom, g->d_child, o,
-                       m->d_cell64, m->d_cell32, m->d_err);
-    e = hipGetLastError();
+                       m->d_cell64, m->d_cell32, m->d_flags, epoch);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const auto &off = g->topo.combine_off;
-    for (size_t b = 0; b + 1 < off.size(); b++) {
+    const int nb = (int)off.size() - 1;
+    if (nb <= 0) return hipSuccess;
+    if (off[nb] <= kSingleWorkgroupCombine) {
+        hipLaunchKernelGGL(moments_levels_kernel, dim3(1), dim3(1024), 0, s, g->d_combine, g->d_combine_off, nb,
+                           g->d_geom, g->d_child, o);
+        return hipGetLastError();
+    }
+    for (int b = 0; b < nb; b++) {
         int64_t cnt = off[b + 1] - off[b];
         int blocks = (int)((cnt + 255) / 256);
         hipLaunchKernelGGL(moments_combine_kernel, dim3(blocks), dim3(256), 0, s, g->d_combine + off[b], cnt,
@@ -288,14 +313,16 @@ hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hi
 // ---------------------------------------------------------------- walk
 
 template <typename real>
-struct WalkRecOf;
+struct Prec;
 template <>
-struct WalkRecOf<float> {
-    using type = WalkRec32;
+struct Prec<float> {
+    using Rec = WalkRec32;
+    using V4 = float4;
 };
 template <>
-struct WalkRecOf<double> {
-    using type = WalkRec64;
+struct Prec<double> {
+    using Rec = WalkRec64;
+    using V4 = double4;
 };
 
 // min over k in [0, n) of |fl(x0 + k h - X)|.  x0 + k h is exact (dyadic), and
@@ -323,70 +350,83 @@ struct WalkArgs {
     int64_t n_groups;
     int root;
     int k8_threshold;
+    int epoch;
+    int *flags;  // flags[1] <- epoch on stack overflow
+    // list mode
     int32_t *far_cnt, *near_cnt;
     const int64_t *far_off, *near_off;
     int32_t *far_out, *near_out;
-    int *err;
+    // fused mode
+    const void *far_rec;
+    const int32_t *child;
+    const void *cells;
+    double G;
+    double *phi;
+    int32_t *counts;
 };
 
-// The group vote of the potential kernel (all lanes accept) needs, per node,
-// min over the group's cells of d^2.  The group is an axis-aligned 4x4x4
-// lattice of cell centres, so that minimum separates per axis: the cell whose
-// per-axis gaps are each minimal has the smallest rounded d^2 too (rounding is
-// monotone).  One lane therefore decides one node exactly as 64 per-cell tests
-// would, and the wave tests 64 nodes (8 sibling sets) per step.
-template <typename real, bool FILL>
-__global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
-    using Rec = typename WalkRecOf<real>::type;
-    __shared__ int stack[4][kWalkStackCap];
-    const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
-    int *stk = stack[w];
-    const Rec *nodes = (const Rec *)a.nodes;
-    const int f = (int)(g >> 3), sub = (int)(g & 7);
-    const LeafInfo L = a.leaves[f];
-    const int i0 = (sub & 1) * 4, j0 = ((sub >> 1) & 1) * 4, k0 = ((sub >> 2) & 1) * 4;
-    const real h = (real)L.h;
-    const real x0 = (real)(L.lo[0] + (i0 + 0.5) * L.h);
-    const real y0 = (real)(L.lo[1] + (j0 + 0.5) * L.h);
-    const real z0 = (real)(L.lo[2] + (k0 + 0.5) * L.h);
-    real inv;
-    if (a.theta_group) {
-        float th = a.theta_group[(int64_t)L.canon * 8 + sub];
-        th = th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
-        if (!(th == th)) th = 1e-3f;
-        inv = (real)1 / (real)th;
-    } else {
-        inv = (real)(1.0 / a.theta);
-        if (sizeof(real) == 4) inv = (real)(1.0f / (float)a.theta);
-    }
-    int64_t fbase = 0, nbase = 0;
-    if (FILL) {
-        fbase = a.far_off[g];
-        nbase = a.near_off[g];
-    }
-    int size = 0;
-    {
+// Group walk state of one wavefront.  The group vote of the potential kernel
+// (all lanes accept) needs, per node, the minimum over the group's cells of
+// d^2.  The group is an axis-aligned 4x4x4 lattice of cell centres, so that
+// minimum separates per axis: the cell whose per-axis gaps are each minimal
+// has the smallest rounded d^2 too (rounding is monotone).  One lane therefore
+// decides one node exactly as 64 per-cell tests would, and a step tests the 64
+// children of up to 8 opened nodes.  The LDS stack holds the first-child ids
+// of opened nodes; it pops 8 entries while it is short and 1 entry (plain
+// depth-first order, growth <= 7 per level) once it passes k8_threshold, so it
+// never exceeds k8_threshold + 56 + 7 (max_depth + 1) + 1 < kWalkStackCap.
+template <typename real>
+struct Walker {
+    using Rec = typename Prec<real>::Rec;
+    const Rec *nodes;
+    int *stk;
+    int size;
+    int k8;
+    real x0, y0, z0, h, inv;
+    bool overflow;
+
+    __device__ void init(const WalkArgs &a, const LeafInfo &L, int sub, int *stack, int lane) {
+        nodes = (const Rec *)a.nodes;
+        stk = stack;
+        k8 = a.k8_threshold;
+        overflow = false;
+        const int i0 = (sub & 1) * 4, j0 = ((sub >> 1) & 1) * 4, k0 = ((sub >> 2) & 1) * 4;
+        h = (real)L.h;
+        x0 = (real)(L.lo[0] + (i0 + 0.5) * L.h);
+        y0 = (real)(L.lo[1] + (j0 + 0.5) * L.h);
+        z0 = (real)(L.lo[2] + (k0 + 0.5) * L.h);
+        if (a.theta_group) {
+            float th = a.theta_group[(int64_t)L.canon * 8 + sub];
+            if (!(th == th)) th = 1e-3f;
+            th = th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
+            inv = (real)1 / (real)th;
+        } else if (sizeof(real) == 4) {
+            inv = (real)(1.0f / (float)a.theta);
+        } else {
+            inv = (real)(1.0 / a.theta);
+        }
+        size = 0;
         const Rec root = nodes[a.root];
         if (!(root.flags & FLAG_EMPTY)) {
             if (lane == 0) stk[0] = root.child;
             size = 1;
         }
+        wave_lds_sync();
     }
-    wave_lds_sync();
-    int nf = 0, nn = 0;
-    bool overflow = false;
-    while (size > 0) {
-        const int k = size <= a.k8_threshold ? (size < 8 ? size : 8) : 1;
+
+    // One step.  Per lane: id of the tested node, and whether it was accepted
+    // (far) or is a rejected bottom node (near).  Opened nodes are pushed.
+    __device__ void step(int lane, int &id, bool &acc, bool &nr) {
+        const int k = size <= k8 ? (size < 8 ? size : 8) : 1;
         const int slot = lane >> 3;
         const bool active = slot < k;
-        int id = 0;
+        id = 0;
         if (active) id = stk[size - 1 - slot] + (lane & 7);
         size -= k;
         wave_lds_sync();
-        bool acc = false, nr = false, op = false;
+        acc = false;
+        nr = false;
+        bool op = false;
         int ch = 0;
         if (active) {
             const Rec r = nodes[id];
@@ -408,15 +448,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
                 }
             }
         }
-        const uint64_t mf = __ballot(acc);
-        const uint64_t mn = __ballot(nr);
         const uint64_t mo = __ballot(op);
-        if (FILL) {
-            if (acc) a.far_out[fbase + nf + lane_prefix(mf)] = id;
-            if (nr) a.near_out[nbase + nn + lane_prefix(mn)] = id;
-        }
-        nf += __popcll(mf);
-        nn += __popcll(mn);
         if (op) {
             int p = size + lane_prefix(mo);
             if (p < kWalkStackCap)
@@ -431,7 +463,43 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
         }
         wave_lds_sync();
     }
-    if (__ballot(overflow) != 0 && lane == 0) atomicOr(a.err, 1);
+
+    __device__ void finish(const WalkArgs &a, int lane) {
+        if (__ballot(overflow) != 0 && lane == 0) atomicMax(a.flags + 1, a.epoch);
+    }
+};
+
+template <typename real, bool FILL>
+__global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
+    __shared__ int stack[4][kWalkStackCap];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const LeafInfo L = a.leaves[f];
+    Walker<real> W;
+    W.init(a, L, sub, stack[w], lane);
+    int64_t fbase = 0, nbase = 0;
+    if (FILL) {
+        fbase = a.far_off[g];
+        nbase = a.near_off[g];
+    }
+    int nf = 0, nn = 0;
+    while (W.size > 0) {
+        int id;
+        bool acc, nr;
+        W.step(lane, id, acc, nr);
+        const uint64_t mf = __ballot(acc);
+        const uint64_t mn = __ballot(nr);
+        if (FILL) {
+            if (acc) a.far_out[fbase + nf + lane_prefix(mf)] = id;
+            if (nr) a.near_out[nbase + nn + lane_prefix(mn)] = id;
+        }
+        nf += __popcll(mf);
+        nn += __popcll(mn);
+    }
+    W.finish(a, lane);
     if (!FILL && lane == 0) {
         a.far_cnt[g] = nf;
         a.near_cnt[g] = nn;
@@ -440,9 +508,9 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
 
 int walk_k8_threshold(int max_depth) { return kWalkStackCap - 64 - 7 * (max_depth + 1) - 8; }
 
-hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
-                       int precision, bool fill, hipStream_t s) {
-    WalkArgs a;
+static WalkArgs walk_args(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                          int precision, int epoch) {
+    WalkArgs a{};
     a.nodes = precision == BH_FP64 ? (const void *)m->d_w64 : (const void *)m->d_w32;
     a.leaves = g->d_leaves;
     a.theta_group = theta_group;
@@ -450,13 +518,21 @@ hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, doubl
     a.n_groups = g->n_groups;
     a.root = g->topo.root;
     a.k8_threshold = walk_k8_threshold(g->topo.max_depth);
+    a.epoch = epoch;
+    a.flags = m->d_flags;
+    a.child = g->d_child;
+    return a;
+}
+
+hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
+                       int precision, bool fill, hipStream_t s) {
+    WalkArgs a = walk_args(g, m, theta, theta_group, precision, m->walk_epoch);
     a.far_cnt = L->d_far_cnt;
     a.near_cnt = L->d_near_cnt;
     a.far_off = L->d_far_off;
     a.near_off = L->d_near_off;
     a.far_out = L->d_far;
     a.near_out = L->d_near;
-    a.err = L->d_err;
     const int blocks = (int)((g->n_groups + 3) / 4);
     if (precision == BH_FP64) {
         if (fill)
@@ -515,9 +591,13 @@ __global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(const int32_t *
     }
 }
 
+// Scans the block sums, writes both list totals (end offsets) and gathers the
+// walk and density flags into status[] for one host copy.
 __global__ __launch_bounds__(kScanBlock) void scan_partials_kernel(int64_t *__restrict__ partials, int nblocks,
-                                                                   int64_t *__restrict__ totals_a,
-                                                                   int64_t *__restrict__ totals_b) {
+                                                                   int64_t *__restrict__ end_a,
+                                                                   int64_t *__restrict__ end_b,
+                                                                   const int *__restrict__ flags,
+                                                                   int64_t *__restrict__ status) {
     __shared__ int64_t sh[kScanBlock];
     for (int which = 0; which < 2; which++) {
         int64_t *p = partials + (int64_t)which * nblocks;
@@ -530,7 +610,14 @@ __global__ __launch_bounds__(kScanBlock) void scan_partials_kernel(int64_t *__re
             if (idx < nblocks) p[idx] = ex + carry;
             carry += tot;
         }
-        if (threadIdx.x == 0) *(which == 0 ? totals_a : totals_b) = carry;
+        if (threadIdx.x == 0) {
+            *(which == 0 ? end_a : end_b) = carry;
+            status[which] = carry;
+        }
+    }
+    if (threadIdx.x == 0) {
+        status[2] = flags[1];
+        status[3] = flags[0];
     }
 }
 
@@ -561,7 +648,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_apply_kernel(const int32_t *_
     }
 }
 
-hipError_t launch_scan(const bh_grid *g, bh_lists *L, hipStream_t s) {
+hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipStream_t s) {
     const int64_t n = g->n_groups;
     const int nblocks = (int)((n + kScanTile - 1) / kScanTile);
     hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, L->d_far_cnt, L->d_near_cnt, n,
@@ -569,7 +656,7 @@ hipError_t launch_scan(const bh_grid *g, bh_lists *L, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, L->d_partials, nblocks,
-                       L->d_far_off + n, L->d_near_off + n);
+                       L->d_far_off + n, L->d_near_off + n, m->d_flags, L->d_status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_apply_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, L->d_far_cnt, L->d_near_cnt, n,
@@ -577,7 +664,125 @@ hipError_t launch_scan(const bh_grid *g, bh_lists *L, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- potential
+// ---------------------------------------------------------------- pair sums
+
+// 1/sqrt(x) in fp64: hardware estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2, each step roughly doubling the correct bits.
+__device__ __forceinline__ double rsqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// fp32 far term of one node for one cell, added to `part`:
+//   M/d + R^T Q R / (2 d^5) = (M + qd / d^4) / d,  qd = R^T (Q/2) R,
+// with the node record p = (X, Y, Z, M), q = (Qxx/2, Qyy/2, Qzz/2, Qxy),
+// u = (Qxz, Qyz, -, -).  v_rsq_f32 is used bare: d^2 >= (h/2)^2 is far from
+// the denormal range, so the library guard around it is not needed.
+__device__ __forceinline__ float far_term(float px, float py, float pz, const float4 p, const float4 q,
+                                          const float4 u, float part) {
+    const float dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+    const float x2 = dx * dx, y2 = dy * dy, z2 = dz * dz;
+    const float r2 = (x2 + y2) + z2;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    float qd = q.x * x2;
+    qd = fmaf(q.y, y2, qd);
+    qd = fmaf(q.z, z2, qd);
+    float t = q.w * dy;
+    t = fmaf(u.x, dz, t);
+    qd = fmaf(t, dx, qd);
+    qd = fmaf(u.y * dy, dz, qd);
+    const float ri2 = ri * ri;
+    t = qd * ri2;
+    t = fmaf(t, ri2, p.w);
+    return fmaf(t, ri, part);
+}
+
+// fp64 far term; the record is the fp64 moments row:
+// p = (X, Y, Z, M), q = (Qxx, Qyy, Qzz, Qxy), u = (Qxz, Qyz, delta, -).
+__device__ __forceinline__ double far_term(double px, double py, double pz, const double4 p, const double4 q,
+                                           const double4 u, double part) {
+    const double dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double ri = rsqrt64(r2);
+    const double ri2 = ri * ri;
+    const double quad = 0.5 * (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) +
+                        (q.w * dx * dy + u.x * dx * dz + u.y * dy * dz);
+    return part + (p.w * ri + quad * (ri2 * ri2 * ri));
+}
+
+__device__ __forceinline__ float near_pair(float px, float py, float pz, const float4 s, float part) {
+    const float dx = px - s.x, dy = py - s.y, dz = pz - s.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    return fmaf(s.w, __builtin_amdgcn_rsqf(r2), part);
+}
+__device__ __forceinline__ float near_pair_self(float px, float py, float pz, const float4 s, float part) {
+    const float dx = px - s.x, dy = py - s.y, dz = pz - s.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    return fmaf(r2 > 0.f ? s.w : 0.f, r2 > 0.f ? ri : 0.f, part);
+}
+__device__ __forceinline__ double near_pair(double px, double py, double pz, const double4 s, double part) {
+    const double dx = px - s.x, dy = py - s.y, dz = pz - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    return part + s.w * rsqrt64(r2);
+}
+__device__ __forceinline__ double near_pair_self(double px, double py, double pz, const double4 s, double part) {
+    const double dx = px - s.x, dy = py - s.y, dz = pz - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    return r2 > 0.0 ? part + s.w * rsqrt64(r2) : part;
+}
+
+// Per-wavefront tile evaluation.  Far tile: up to 64 node records (3 x V4
+// each) staged in T by lane, then read back by every lane as broadcasts.
+// Near tile: up to 8 bottom nodes = 64 cells.  Each tile is summed in `real`
+// and added to an fp64 accumulator (separate for far and near, so that every
+// path that forms the same tiles in the same order gives identical bits).
+template <typename real>
+struct Tiles {
+    using V4 = typename Prec<real>::V4;
+    V4 *T;
+    const V4 *rec;
+    const V4 *cells;
+    const int32_t *child;
+    V4 me;
+    int own_lo;
+    double acc_far, acc_near;
+
+    __device__ void stage_far(int lane, int n, int id) {
+        if (lane < n) {
+            T[3 * lane + 0] = rec[3 * (int64_t)id + 0];
+            T[3 * lane + 1] = rec[3 * (int64_t)id + 1];
+            T[3 * lane + 2] = rec[3 * (int64_t)id + 2];
+        }
+        wave_lds_sync();
+    }
+    __device__ void sum_far(int n) {
+        real part = 0;
+        for (int j = 0; j < n; j++) part = far_term(me.x, me.y, me.z, T[3 * j], T[3 * j + 1], T[3 * j + 2], part);
+        acc_far += (double)part;
+        wave_lds_sync();
+    }
+    // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]
+    __device__ void near_tile(int lane, int n, int id) {
+        bool own = false;
+        if (lane < 8 * n) {
+            own = (unsigned)(id - own_lo) < 8u;
+            T[lane] = cells[(int64_t)child[id] + (lane & 7)];
+        }
+        const bool any_own = __ballot(own) != 0;
+        wave_lds_sync();
+        real part = 0;
+        if (!any_own)
+            for (int j = 0; j < 8 * n; j++) part = near_pair(me.x, me.y, me.z, T[j], part);
+        else
+            for (int j = 0; j < 8 * n; j++) part = near_pair_self(me.x, me.y, me.z, T[j], part);
+        acc_near += (double)part;
+        wave_lds_sync();
+    }
+};
 
 struct PotArgs {
     const int64_t *far_off, *near_off;
@@ -597,136 +802,37 @@ __device__ __forceinline__ int64_t phi_index(const LeafInfo &L, int sub, int lan
     return (int64_t)L.canon * kCellsPerBlock + k * 64 + j * 8 + i;
 }
 
-__global__ __launch_bounds__(256) void potential32_kernel(PotArgs a) {
-    __shared__ float4 tile[4][64 * 3];
+template <typename real>
+__global__ __launch_bounds__(256) void potential_kernel(PotArgs a) {
+    using V4 = typename Prec<real>::V4;
+    __shared__ V4 tile[4][64 * 3];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t g = (int64_t)blockIdx.x * 4 + w;
     if (g >= a.n_groups) return;
-    float4 *T = tile[w];
     const int f = (int)(g >> 3), sub = (int)(g & 7);
-    const float4 *cells = (const float4 *)a.cells;
-    const float4 me = cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
-    double acc = 0.0;
-    // far field: monopole + quadrupole
-    {
-        const int64_t b0 = a.far_off[g], e0 = a.far_off[g + 1];
-        const float4 *rec = (const float4 *)a.far_rec;
-        for (int64_t b = b0; b < e0; b += 64) {
-            const int n = (int)(e0 - b < 64 ? e0 - b : 64);
-            if (lane < n) {
-                const int64_t id = a.far_idx[b + lane];
-                T[3 * lane + 0] = rec[3 * id + 0];
-                T[3 * lane + 1] = rec[3 * id + 1];
-                T[3 * lane + 2] = rec[3 * id + 2];
-            }
-            wave_lds_sync();
-            float part = 0.f;
-            for (int j = 0; j < n; j++) {
-                const float4 p = T[3 * j + 0];
-                const float4 q = T[3 * j + 1];
-                const float4 u = T[3 * j + 2];
-                const float dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
-                const float x2 = dx * dx, y2 = dy * dy, z2 = dz * dz;
-                const float r2 = x2 + y2 + z2;
-                const float ri = rsqrtf(r2);
-                const float ri2 = ri * ri;
-                // q = (a, b, f, c), u = (d, e, -, -)
-                float quad = q.x * x2 + q.y * y2 + q.z * z2;
-                quad += dx * (q.w * dy + u.x * dz) + u.y * dy * dz;
-                part += p.w * ri + quad * (ri2 * ri2 * ri);
-            }
-            acc += (double)part;
-            wave_lds_sync();
-        }
+    const LeafInfo L = a.leaves[f];
+    Tiles<real> S;
+    S.T = tile[w];
+    S.rec = (const V4 *)a.far_rec;
+    S.cells = (const V4 *)a.cells;
+    S.child = a.child;
+    S.own_lo = L.bot_first + sub * 8;
+    S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
+    S.acc_far = 0.0;
+    S.acc_near = 0.0;
+    const int64_t fb = a.far_off[g], fe = a.far_off[g + 1];
+    for (int64_t b = fb; b < fe; b += 64) {
+        const int n = (int)(fe - b < 64 ? fe - b : 64);
+        S.stage_far(lane, n, lane < n ? a.far_idx[b + lane] : 0);
+        S.sum_far(n);
     }
-    // near field: cells of the near bottom nodes, self pair excluded (r2 == 0)
-    {
-        const int64_t b0 = a.near_off[g], e0 = a.near_off[g + 1];
-        for (int64_t b = b0; b < e0; b += 8) {
-            const int n = (int)(e0 - b < 8 ? e0 - b : 8);
-            if (lane < 8 * n) {
-                const int id = a.near_idx[b + (lane >> 3)];
-                T[lane] = cells[(int64_t)a.child[id] + (lane & 7)];
-            }
-            wave_lds_sync();
-            float part = 0.f;
-            for (int j = 0; j < 8 * n; j++) {
-                const float4 s = T[j];
-                const float dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float t = s.w * rsqrtf(r2);
-                part += r2 > 0.f ? t : 0.f;
-            }
-            acc += (double)part;
-            wave_lds_sync();
-        }
+    const int64_t nb = a.near_off[g], ne = a.near_off[g + 1];
+    for (int64_t b = nb; b < ne; b += 8) {
+        const int n = (int)(ne - b < 8 ? ne - b : 8);
+        S.near_tile(lane, n, lane < 8 * n ? a.near_idx[b + (lane >> 3)] : 0);
     }
-    a.phi[phi_index(a.leaves[f], sub, lane)] = -a.G * acc;
-}
-
-__global__ __launch_bounds__(256) void potential64_kernel(PotArgs a) {
-    __shared__ double4 tile[4][64 * 3];
-    const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
-    double4 *T = tile[w];
-    const int f = (int)(g >> 3), sub = (int)(g & 7);
-    const double4 *cells = (const double4 *)a.cells;
-    const double4 me = cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
-    double acc = 0.0;
-    {
-        const int64_t b0 = a.far_off[g], e0 = a.far_off[g + 1];
-        const double4 *rec = (const double4 *)a.far_rec;  // kMom = 12 doubles = 3 double4
-        for (int64_t b = b0; b < e0; b += 64) {
-            const int n = (int)(e0 - b < 64 ? e0 - b : 64);
-            if (lane < n) {
-                const int64_t id = a.far_idx[b + lane];
-                T[3 * lane + 0] = rec[3 * id + 0];
-                T[3 * lane + 1] = rec[3 * id + 1];
-                T[3 * lane + 2] = rec[3 * id + 2];
-            }
-            wave_lds_sync();
-            double part = 0.0;
-            for (int j = 0; j < n; j++) {
-                const double4 p = T[3 * j + 0];  // X Y Z M
-                const double4 q = T[3 * j + 1];  // Qxx Qyy Qzz Qxy
-                const double4 u = T[3 * j + 2];  // Qxz Qyz delta -
-                const double dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double d = sqrt(r2);
-                const double ri = 1.0 / d;
-                const double ri2 = ri * ri;
-                const double quad = 0.5 * (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) +
-                                    (q.w * dx * dy + u.x * dx * dz + u.y * dy * dz);
-                part += p.w * ri + quad * (ri2 * ri2 * ri);
-            }
-            acc += part;
-            wave_lds_sync();
-        }
-    }
-    {
-        const int64_t b0 = a.near_off[g], e0 = a.near_off[g + 1];
-        for (int64_t b = b0; b < e0; b += 8) {
-            const int n = (int)(e0 - b < 8 ? e0 - b : 8);
-            if (lane < 8 * n) {
-                const int id = a.near_idx[b + (lane >> 3)];
-                T[lane] = cells[(int64_t)a.child[id] + (lane & 7)];
-            }
-            wave_lds_sync();
-            double part = 0.0;
-            for (int j = 0; j < 8 * n; j++) {
-                const double4 s = T[j];
-                const double dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 > 0.0) part += s.w / sqrt(r2);
-            }
-            acc += part;
-            wave_lds_sync();
-        }
-    }
-    a.phi[phi_index(a.leaves[f], sub, lane)] = -a.G * acc;
+    a.phi[phi_index(L, sub, lane)] = -a.G * (S.acc_far + S.acc_near);
 }
 
 hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_lists *L, double G, int precision,
@@ -745,12 +851,108 @@ hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_list
     if (precision == BH_FP64) {
         a.far_rec = m->d_mom;
         a.cells = m->d_cell64;
-        hipLaunchKernelGGL(potential64_kernel, dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(potential_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
     } else {
         a.far_rec = m->d_f32;
         a.cells = m->d_cell32;
-        hipLaunchKernelGGL(potential32_kernel, dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(potential_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fused walk + sums
+
+// Walk and sum in one pass, without materialising the lists: accepted nodes
+// and near bottom nodes are buffered in LDS in walk order and summed as soon
+// as a full tile (64 far nodes / 8 bottom nodes) is available, so the tiles
+// are exactly those the list path forms, in the same order.
+template <typename real>
+__global__ __launch_bounds__(256) void walk_potential_kernel(WalkArgs a) {
+    using V4 = typename Prec<real>::V4;
+    __shared__ int stack[4][kWalkStackCap];
+    __shared__ int fbuf[4][128];
+    __shared__ int nbuf[4][72];
+    __shared__ V4 tile[4][64 * 3];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const LeafInfo L = a.leaves[f];
+    Walker<real> W;
+    W.init(a, L, sub, stack[w], lane);
+    Tiles<real> S;
+    S.T = tile[w];
+    S.rec = (const V4 *)a.far_rec;
+    S.cells = (const V4 *)a.cells;
+    S.child = a.child;
+    S.own_lo = L.bot_first + sub * 8;
+    S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
+    S.acc_far = 0.0;
+    S.acc_near = 0.0;
+    int *FB = fbuf[w];
+    int *NB = nbuf[w];
+    int fcnt = 0, ncnt = 0, ftot = 0, ntot = 0;
+    while (W.size > 0) {
+        int id;
+        bool acc, nr;
+        W.step(lane, id, acc, nr);
+        const uint64_t mf = __ballot(acc);
+        const uint64_t mn = __ballot(nr);
+        if (acc) FB[fcnt + lane_prefix(mf)] = id;
+        if (nr) NB[ncnt + lane_prefix(mn)] = id;
+        fcnt += __popcll(mf);
+        ncnt += __popcll(mn);
+        ftot += __popcll(mf);
+        ntot += __popcll(mn);
+        wave_lds_sync();
+        if (fcnt >= 64) {
+            S.stage_far(lane, 64, FB[lane]);
+            S.sum_far(64);
+            const int rest = fcnt - 64;
+            int v = lane < rest ? FB[64 + lane] : 0;
+            wave_lds_sync();
+            if (lane < rest) FB[lane] = v;
+            fcnt = rest;
+            wave_lds_sync();
+        }
+        while (ncnt >= 8) {
+            S.near_tile(lane, 8, NB[lane >> 3]);
+            const int rest = ncnt - 8;
+            int v = lane < rest ? NB[8 + lane] : 0;
+            wave_lds_sync();
+            if (lane < rest) NB[lane] = v;
+            ncnt = rest;
+            wave_lds_sync();
+        }
+    }
+    W.finish(a, lane);
+    if (fcnt > 0) {
+        S.stage_far(lane, fcnt, lane < fcnt ? FB[lane] : 0);
+        S.sum_far(fcnt);
+    }
+    if (ncnt > 0) S.near_tile(lane, ncnt, lane < 8 * ncnt ? NB[lane >> 3] : 0);
+    a.phi[phi_index(L, sub, lane)] = -a.G * (S.acc_far + S.acc_near);
+    if (a.counts && lane == 0) {
+        const int64_t cg = (int64_t)L.canon * 8 + sub;
+        a.counts[2 * cg + 0] = ftot;
+        a.counts[2 * cg + 1] = ntot;
+    }
+}
+
+hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                                 int precision, double G, double *phi, int32_t *counts, hipStream_t s) {
+    WalkArgs a = walk_args(g, m, theta, theta_group, precision, m->walk_epoch);
+    a.far_rec = precision == BH_FP64 ? (const void *)m->d_mom : (const void *)m->d_f32;
+    a.cells = precision == BH_FP64 ? (const void *)m->d_cell64 : (const void *)m->d_cell32;
+    a.G = G;
+    a.phi = phi;
+    a.counts = counts;
+    const int blocks = (int)((g->n_groups + 3) / 4);
+    if (precision == BH_FP64)
+        hipLaunchKernelGGL(walk_potential_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(walk_potential_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -59,12 +59,25 @@ class BarnesHut:
         return B.bh_potential(self.ctx, self.grid, self.m, self.lists, G, precision, phi)
 
     def solve(self, rho: torch.Tensor, theta=0.5, theta_group=None, precision=B.BH_FP32, G=1.0, phi=None):
+        """moments -> walk (lists) -> potential."""
         if phi is None:
             phi = torch.empty_like(rho)
         self.build_moments(rho)
         self.walk(theta, theta_group, precision)
         self.potential(phi, G, precision)
         return phi
+
+    def solve_fused(self, rho: torch.Tensor, theta=0.5, theta_group=None, precision=B.BH_FP32, G=1.0, phi=None,
+                    counts=None):
+        """moments -> fused walk + potential (no lists, no host synchronisation)."""
+        if phi is None:
+            phi = torch.empty_like(rho)
+        self.build_moments(rho)
+        B.bh_walk_potential(self.ctx, self.grid, self.m, theta, theta_group, precision, G, phi, counts)
+        return phi
+
+    def check(self):
+        B.bh_moments_check(self.ctx, self.m)
 
     def direct(self, targets: torch.Tensor, G=1.0, out=None):
         if out is None:

@@ -213,3 +213,45 @@ def test_invalid_inputs_raise():
     with pytest.raises(TypeError):
         bh.build_moments(rho.float())
     bh.close()
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+@pytest.mark.parametrize("precision", [B.BH_FP64, B.BH_FP32])
+@pytest.mark.parametrize("theta", [0.3, 0.7])
+def test_fused_walk_potential_equals_list_path(name, precision, theta):
+    """bh_walk_potential forms the same tiles in the same order: identical bits."""
+    g, bh, rho, t, keys = setup(name)
+    bh.walk(theta, None, precision)
+    ref = torch.empty_like(rho)
+    bh.potential(ref, 1.0, precision)
+    got = torch.empty_like(rho)
+    counts = torch.zeros((bh.info["n_groups"], 2), dtype=torch.int32, device="cuda")
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, theta, None, precision, 1.0, got, counts)
+    bh.check()
+    assert torch.equal(got, ref)
+    L = bh.lists_host()
+    c = counts.cpu().numpy()
+    assert np.array_equal(c[:, 0], np.diff(L["far_off"]))
+    assert np.array_equal(c[:, 1], np.diff(L["near_off"]))
+
+
+def test_fused_per_group_theta_and_invalid_density():
+    g, bh, rho, t, keys = setup("random_amr")
+    ng = bh.info["n_groups"]
+    th = torch.tensor(np.random.default_rng(4).uniform(0.2, 1.0, ng).astype(np.float32), device="cuda")
+    bh.walk(0.5, th, B.BH_FP32)
+    ref = torch.empty_like(rho)
+    bh.potential(ref, 2.5, B.BH_FP32)
+    got = torch.empty_like(rho)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, th, B.BH_FP32, 2.5, got, None)
+    assert torch.equal(got, ref)
+    bad = rho.clone()
+    bad[1, 0, 0, 0] = -2.0
+    bh.build_moments(bad)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, None, B.BH_FP32, 1.0, got, None)
+    with pytest.raises(B.BHError) as ei:
+        bh.check()
+    assert ei.value.code == B.BH_EINVAL
+    bh.build_moments(rho)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, None, B.BH_FP32, 1.0, got, None)
+    bh.check()
