@@ -40,6 +40,24 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def profiled_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "walk_potential_fp32_maclaurin_1p4M.md")
+    src = os.path.join(ROOT, "paper_1509_07370_amd", "csrc", "bh_kernels.hip")
+    try:
+        text = open(path).read()
+        want = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("traffic_bytes_per_launch:",
+                                                                                  "source_sha256:")))
+    if fields.get("source_sha256", "").strip() != want:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def algorithmic_flops(n_far, n_near):
     """35 per cell-node far interaction + 11 per near cell pair (self excluded);
     n_far / n_near: far nodes and near bottom nodes per 64-cell group."""
@@ -206,7 +224,7 @@ def main():
                    "cells": ncells, "theta": head_theta, "group_cells": 64, "theta_mode": "fixed",
                    "precision": "fp32-walk/fp64-accumulate"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
                      "kernel": "walk_potential_kernel<float>", "kernel_ms": pot_ms, "flop_per_launch": flops,
                      "far_interactions": far_int, "near_pairs": near_pairs},
         "cpu_baseline": cpu,

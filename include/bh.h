@@ -76,7 +76,7 @@ const char *bh_create_error(void);
 
 /* ---------------------------------------------------------------- grid (topology) */
 
-/* Build the octree topology of an AMR mesh (section 3.2.1: data collected per
+/* Build the octree topology of an AMR mesh (section 3.1.1: cell data collected per
  * block, cells treated as point masses; tree nodes down to the cells as in
  * section 2).  Host arrays, all copied:
  *   level[n]      AMR level, 0 for the base blocks
@@ -116,7 +116,7 @@ int bh_grid_node_keys(const bh_grid *grid, uint64_t *keys);
 
 /* ---------------------------------------------------------------- moments */
 
-/* Upward pass (section 3.2.2 "Centers of Gravitation" kernel, extended to
+/* Upward pass (section 3.2.3, the centers-of-gravitation kernel, extended to
  * quadrupoles): cell masses m = rho h^3 at the cell centres, then for every
  * node its mass M, centre of mass X = sum m r / M (Eq. R), traceless
  * quadrupole about X, Q = sum m (3 D D^T - |D|^2 I) (combined bottom-up with
@@ -138,7 +138,7 @@ int bh_moments_destroy(bh_moments *m);
 
 /* ---------------------------------------------------------------- walk */
 
-/* Group tree walk (section 3.2.3 potential kernel: depth-first traversal with
+/* Group tree walk (section 3.3, the potential kernel: depth-first traversal with
  * the all() vote over a group of neighbouring cells, Eq. THETA2 test
  * d^2 > (l/theta + delta)^2 at every cell of the group, equality opens).
  * Accepted nodes form the group's far list; rejected bottom nodes (2^3 cells)
@@ -164,7 +164,7 @@ int bh_lists_destroy(bh_lists *lists);
 
 /* ---------------------------------------------------------------- sums */
 
-/* Potential from the lists (section 3.2.3 accumulation, with quadrupoles):
+/* Potential from the lists (section 3.3 accumulation, with quadrupoles):
  * phi_i = -G [ sum_far (M/d + R^T Q R / (2 d^5)) + sum_{near cells j != i} m_j / d ],
  * R = r_i - X.  precision BH_FP64: fp64 throughout; BH_FP32: fp32 pair terms
  * summed in fp32 over tiles of at most 64 nodes / 64 cells, tiles accumulated

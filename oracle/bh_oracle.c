@@ -19,8 +19,8 @@
  *  O2 direct  - phi_i = -G sum_{j != i} m_j / |r_i - r_j|  (Eq. 2 of section 1,
  *               read without its factor 1/2, which belongs to the energy).
  *  O3 nodes   - every node is a cube with centre c and edge l; M = sum m,
- *               X = sum m r / M (the centre-of-mass equation of the "Centers of
- *               Gravitation" kernel section), traceless quadrupole about X,
+ *               X = sum m r / M (the centre-of-mass equation of section 3.2.3,
+ *               the centers-of-gravitation kernel), traceless quadrupole about X,
  *               Q = sum m (3 D D^T - |D|^2 I), D = r - X, and
  *               delta = |X - c| (section 2, Eq. THETA2).  M = 0 gives X = c,
  *               Q = 0, delta = 0.
@@ -30,7 +30,7 @@
  *  O5 MAC     - node n is accepted for group g iff every cell i of g has
  *               d^2 > s^2, d = |r_i - X_n|, s = l (1/theta_g) + delta
  *               (Eq. THETA2 combined with the all() vote of the potential
- *               kernel section; equality opens).
+ *               kernel, section 3.3; equality opens).
  *  O6 walk    - depth-first from the root; accepted -> far list, rejected
  *               bottom node (children are cells) -> near list, rejected
  *               internal node -> visit its 8 children.  Zero-mass nodes are

@@ -182,7 +182,7 @@ def test_error_grows_with_theta_percent_level_at_one():
     quad = [e for th, o, e in errs if o == 2]
     assert all(a < b for a, b in zip(mono, mono[1:]))
     assert all(a < b for a, b in zip(quad, quad[1:]))
-    # theta = 1 monopole-only: "errors around 1%" (section 2)
+    # theta = 1, monopole only: percent-level error (section 2)
     assert 1e-3 < mono[-1] < 3e-2
     # the quadrupole improves every theta
     assert all(q < mo for q, mo in zip(quad, mono))
