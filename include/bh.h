@@ -57,6 +57,7 @@ typedef struct bh_ctx bh_ctx;
 typedef struct bh_grid bh_grid;
 typedef struct bh_moments bh_moments;
 typedef struct bh_lists bh_lists;
+typedef struct bh_mlp bh_mlp;
 
 /* ---------------------------------------------------------------- context */
 
@@ -190,6 +191,53 @@ int bh_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, dou
  * (n_targets < 0), BH_ESTATE. */
 int bh_direct(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const int64_t *targets_dev,
               int64_t n_targets, double G, double *phi_dev);
+
+/* ---------------------------------------------------------------- learned theta
+ *
+ * Beyond the paper (which uses one runtime theta): a small network predicts,
+ * per group, the largest opening angle that keeps that group's RMS relative
+ * potential error under a target; its output feeds theta_group_dev of
+ * bh_walk / bh_walk_potential.
+ *
+ * Features (fp32 [n_groups][BH_MLP_INPUTS], canonical group order):
+ *   0 log2(group cells); 1 log(M_group / M_root); 2 log(group edge / box);
+ *   3 AMR level of the leaf block; 4 log(max / mean cell mass in the group);
+ *   5, 6 log(delta/l + 1e-6) and log(|Q|_F / (M l^2) + 1e-6) of the group's own
+ *   node; 7, 8 the same for its leaf block; 9, 10 for the block's parent node;
+ *   11 log(mean group density / mean density of the leaf block).
+ * Network: x' = (x - mean) * scale; h1 = tanh(W1 x' + b1) (64);
+ *   h2 = tanh(W2 h1 + b2) (64); z = W3 . h2 + b3; theta = 0.2 + 0.8 sigmoid(z).
+ * Parameter vector (fp32, BH_MLP_PARAMS): W1[64][12] | b1[64] | W2[64][64] |
+ *   b2[64] | W3[64] | b3.  Initial values are supplied by the caller. */
+#define BH_MLP_INPUTS 12
+#define BH_MLP_HIDDEN 64
+#define BH_MLP_PARAMS 5057
+
+/* Group features from the moments of the last bh_build_moments on m.
+ * feat_dev: fp32 [n_groups][12] (device), fully overwritten. */
+int bh_group_features(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, float *feat_dev);
+/* Per-group RMS of the relative error of phi against ref (both fp64 caller
+ * layout, device): rms_dev[g] = sqrt(mean over the group's cells of
+ * ((phi - ref) / ref)^2), fp32 [n_groups], canonical group order. */
+int bh_group_rms_error(bh_ctx *ctx, const bh_grid *grid, const double *phi_dev, const double *ref_dev,
+                       float *rms_dev);
+/* Create a network from host parameters (BH_MLP_PARAMS floats, copied) and the
+ * input normalisation mean[12], scale[12] (copied).  Adam state starts at 0. */
+int bh_mlp_create(bh_ctx *ctx, bh_mlp **net, const float *params, const float *mean, const float *scale);
+int bh_mlp_set_params(bh_ctx *ctx, bh_mlp *net, const float *params);
+/* Synchronising host copy of the parameters. */
+int bh_mlp_get_params(bh_ctx *ctx, const bh_mlp *net, float *params);
+/* theta_dev[n] = network(feat_dev[n][12]).  bf16 = 1: bf16 weights, inputs
+ * and hidden activations with fp32 accumulation; bf16 = 0: fp32. */
+int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat_dev, int64_t n, int bf16, float *theta_dev);
+/* Gradient of L = (1/n) sum (theta(x_s) - label_s)^2 with respect to the
+ * parameters (fp32, deterministic order).  grad_dev: fp32 [BH_MLP_PARAMS];
+ * loss_dev: NULL or fp32 [1] receiving L. */
+int bh_mlp_grad(bh_ctx *ctx, bh_mlp *net, const float *feat_dev, const float *label_dev, int64_t n, float *grad_dev,
+                float *loss_dev);
+/* One Adam step (Kingma & Ba) on the parameters with gradient grad_dev. */
+int bh_mlp_adam_step(bh_ctx *ctx, bh_mlp *net, const float *grad_dev, float lr, float beta1, float beta2, float eps);
+int bh_mlp_destroy(bh_mlp *net);
 
 #ifdef __cplusplus
 }

@@ -57,7 +57,17 @@ _SIGS = {
     "bh_potential": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
     "bh_walk_potential": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P]),
     "bh_direct": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
+    "bh_group_features": (ctypes.c_int, [P, P, P, P]),
+    "bh_group_rms_error": (ctypes.c_int, [P, P, P, P, P]),
+    "bh_mlp_create": (ctypes.c_int, [P, PP, P, P, P]),
+    "bh_mlp_set_params": (ctypes.c_int, [P, P, P]),
+    "bh_mlp_get_params": (ctypes.c_int, [P, P, P]),
+    "bh_mlp_forward": (ctypes.c_int, [P, P, P, i64, ctypes.c_int, P]),
+    "bh_mlp_grad": (ctypes.c_int, [P, P, P, P, i64, P, P]),
+    "bh_mlp_adam_step": (ctypes.c_int, [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "bh_mlp_destroy": (ctypes.c_int, [P]),
 }
+MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
@@ -237,3 +247,60 @@ def bh_direct(ctx, grid, m, targets, G, phi):
     n = int(targets.numel())
     _check(_lib.bh_direct(ctx, grid, m, _dev(targets, "int64"), n, float(G), _dev(phi, "float64")), ctx)
     return phi
+
+
+# ------------------------------------------------------------------ learned theta
+
+def bh_group_features(ctx, grid, m, feat):
+    """feat: float32 CUDA tensor [n_groups, 12]."""
+    _check(_lib.bh_group_features(ctx, grid, m, _dev(feat, "float32")), ctx)
+    return feat
+
+
+def bh_group_rms_error(ctx, grid, phi, ref, rms):
+    _check(_lib.bh_group_rms_error(ctx, grid, _dev(phi, "float64"), _dev(ref, "float64"), _dev(rms, "float32")), ctx)
+    return rms
+
+
+def bh_mlp_create(ctx, params, mean, scale):
+    h = ctypes.c_void_p()
+    p = _np(params, np.float32)
+    mu = _np(mean, np.float32)
+    sc = _np(scale, np.float32)
+    assert p.size == MLP_PARAMS and mu.size == MLP_INPUTS and sc.size == MLP_INPUTS
+    _check(_lib.bh_mlp_create(ctx, ctypes.byref(h), _ptr(p), _ptr(mu), _ptr(sc)), ctx)
+    return h
+
+
+def bh_mlp_set_params(ctx, net, params):
+    p = _np(params, np.float32)
+    assert p.size == MLP_PARAMS
+    _check(_lib.bh_mlp_set_params(ctx, net, _ptr(p)), ctx)
+
+
+def bh_mlp_get_params(ctx, net):
+    p = np.empty(MLP_PARAMS, np.float32)
+    _check(_lib.bh_mlp_get_params(ctx, net, _ptr(p)), ctx)
+    return p
+
+
+def bh_mlp_forward(ctx, net, feat, theta, bf16=True):
+    n = int(feat.shape[0])
+    _check(_lib.bh_mlp_forward(ctx, net, _dev(feat, "float32"), n, int(bool(bf16)), _dev(theta, "float32")), ctx)
+    return theta
+
+
+def bh_mlp_grad(ctx, net, feat, label, grad, loss=None):
+    n = int(feat.shape[0])
+    _check(_lib.bh_mlp_grad(ctx, net, _dev(feat, "float32"), _dev(label, "float32"), n, _dev(grad, "float32"),
+                            _dev(loss, "float32") if loss is not None else None), ctx)
+    return grad
+
+
+def bh_mlp_adam_step(ctx, net, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(_lib.bh_mlp_adam_step(ctx, net, _dev(grad, "float32"), float(lr), float(beta1), float(beta2), float(eps)),
+           ctx)
+
+
+def bh_mlp_destroy(net):
+    _lib.bh_mlp_destroy(net)

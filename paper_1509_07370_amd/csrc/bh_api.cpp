@@ -58,6 +58,8 @@ void free_grid_device(bh_grid *g) {
     hfree(g->d_internal_of_canon);
     hfree(g->d_combine);
     hfree(g->d_combine_off);
+    hfree(g->d_parent);
+    g->d_parent = nullptr;
     g->d_geom = nullptr;
     g->d_child = g->d_flags = g->d_internal_of_canon = g->d_combine = nullptr;
     g->d_combine_off = nullptr;
@@ -161,7 +163,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
             (e = dalloc(&g->d_leaves, t.leaves.size())) != hipSuccess ||
             (e = dalloc(&g->d_internal_of_canon, t.internal_of_canon.size())) != hipSuccess ||
             (e = dalloc(&g->d_combine, t.combine_nodes.size())) != hipSuccess ||
-            (e = dalloc(&g->d_combine_off, t.combine_off.size())) != hipSuccess) {
+            (e = dalloc(&g->d_combine_off, t.combine_off.size())) != hipSuccess ||
+            (e = dalloc(&g->d_parent, t.parent.size())) != hipSuccess) {
             free_grid_device(g);
             delete g;
             return hip_fail(ctx, e, "device allocation of the grid topology");
@@ -176,7 +179,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
                   {g->d_leaves, t.leaves.data(), t.leaves.size() * sizeof(bh::LeafInfo)},
                   {g->d_internal_of_canon, t.internal_of_canon.data(), t.internal_of_canon.size() * sizeof(int32_t)},
                   {g->d_combine, t.combine_nodes.data(), t.combine_nodes.size() * sizeof(int32_t)},
-                  {g->d_combine_off, t.combine_off.data(), t.combine_off.size() * sizeof(int64_t)}};
+                  {g->d_combine_off, t.combine_off.data(), t.combine_off.size() * sizeof(int64_t)},
+                  {g->d_parent, t.parent.data(), t.parent.size() * sizeof(int32_t)}};
         for (auto &u : up) {
             if (u.n == 0) continue;
             e = hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice);

@@ -60,11 +60,13 @@ struct alignas(16) LeafInfo {
 // Host-side octree topology built from the block list.
 struct Topology {
     int nbase = 0, vlev = 0, nblocks = 0, n_levels = 0, max_depth = 0, root = 0;
+    double box = 0.0, box_lo[3] = {0.0, 0.0, 0.0};
     int64_t n_nodes = 0;
     std::vector<uint64_t> key;        // [n_nodes]
     std::vector<double> geom;         // [n_nodes][4]: centre x, y, z, edge
     std::vector<int32_t> child;       // [n_nodes]
     std::vector<int32_t> flags;       // [n_nodes] static FLAG_BOTTOM
+    std::vector<int32_t> parent;      // [n_nodes], -1 for the root
     std::vector<LeafInfo> leaves;     // internal leaf order
     std::vector<int32_t> internal_of_canon;  // canonical leaf -> internal leaf
     std::vector<int32_t> combine_nodes;      // virtual + parent-block nodes, deepest depth first
@@ -98,6 +100,7 @@ struct bh_grid {
     int32_t *d_internal_of_canon = nullptr;
     int32_t *d_combine = nullptr;
     int64_t *d_combine_off = nullptr;
+    int32_t *d_parent = nullptr;         // [n_nodes]
 };
 
 struct bh_moments {

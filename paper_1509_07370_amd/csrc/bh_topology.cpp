@@ -66,6 +66,8 @@ std::string build_topology(Topology &t, int n, const int32_t *level, const doubl
         return fmt("tree too deep: %lld virtual + %lld AMR levels (at most 16 in total)", vlev, maxlev);
     t.nbase = nbase;
     t.vlev = vlev;
+    t.box = box;
+    for (int d = 0; d < 3; d++) t.box_lo[d] = box_lo[d];
     t.nblocks = n;
     t.n_levels = maxlev + 1;
 
@@ -164,6 +166,7 @@ std::string build_topology(Topology &t, int n, const int32_t *level, const doubl
         nodes.push_back(Desc{VIRTUAL, 0, 0, 0, 0, -1, 0});
     t.child.clear();
     t.flags.clear();
+    t.parent.assign(1, -1);
     int maxd = 0;
     for (size_t i = 0; i < nodes.size(); i++) {
         Desc d = nodes[i];
@@ -204,6 +207,7 @@ std::string build_topology(Topology &t, int n, const int32_t *level, const doubl
                 break;
         }
         if (nodes.size() > (size_t)INT32_MAX / 2) return "grid too large for 32-bit node ids";
+        while (t.parent.size() < nodes.size()) t.parent.push_back((int32_t)i);
         t.child.push_back(first);
         t.flags.push_back(flag);
     }

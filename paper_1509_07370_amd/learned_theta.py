@@ -1,0 +1,246 @@
+"""Learned per-group opening angle: labels, training and inference.
+
+Everything numerical runs in libbh.so kernels (walk + sums, direct sum,
+per-group error, features, network forward / gradient / Adam); this module
+only orders the calls and keeps small host-side bookkeeping (label envelope,
+mini-batch order, files).
+
+Labels come from the method itself: for every group the largest theta on the
+grid {0.20, 0.25, ..., 1.00} such that the group's RMS relative error against
+the exact direct sum stays within the target for that theta and every smaller
+one.  At run time the network's bf16 output drives bh_walk_potential; a 1%
+sample of cells is checked against the direct sum and a fixed conservative
+theta (0.4) is used instead if the sample misses the target.
+
+Usage on a GPU:
+  python -m paper_1509_07370_amd.learned_theta train --target 1e-3 --out paper_1509_07370_amd/data/theta_mlp_1e-3.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .solver import BarnesHut
+
+THETA_GRID = np.round(np.arange(0.20, 1.0001, 0.05), 2)
+FALLBACK_THETA = 0.4
+DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+def direct_potential(bh: BarnesHut, rho: torch.Tensor) -> torch.Tensor:
+    """Exact fp64 direct sum at every cell (GPU), caller layout."""
+    bh.build_moments(rho)
+    n = bh.info["n_cells"]
+    return bh.direct(torch.arange(n, device=rho.device, dtype=torch.int64)).reshape(rho.shape)
+
+
+def error_table(bh: BarnesHut, rho: torch.Tensor, direct: torch.Tensor, thetas=THETA_GRID,
+                precision=B.BH_FP32) -> np.ndarray:
+    """[len(thetas), n_groups] per-group RMS relative error of the walk at each theta."""
+    ng = bh.info["n_groups"]
+    bh.build_moments(rho)
+    phi = torch.empty_like(rho)
+    rms = torch.empty((len(thetas), ng), dtype=torch.float32, device=rho.device)
+    for k, th in enumerate(thetas):
+        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, float(th), None, precision, 1.0, phi, None)
+        B.bh_group_rms_error(bh.ctx, bh.grid, phi, direct, rms[k])
+    bh.check()
+    return rms.cpu().numpy()
+
+
+def labels_from_errors(errs: np.ndarray, target: float, thetas=THETA_GRID) -> np.ndarray:
+    """Largest theta whose error, and the error of every smaller theta, meets the target."""
+    ok = np.logical_and.accumulate(errs <= target, axis=0)
+    k = ok.sum(axis=0) - 1
+    return np.asarray(thetas)[np.maximum(k, 0)].astype(np.float32)
+
+
+def group_features(bh: BarnesHut, rho: torch.Tensor, out=None) -> torch.Tensor:
+    bh.build_moments(rho)
+    if out is None:
+        out = torch.empty((bh.info["n_groups"], B.MLP_INPUTS), dtype=torch.float32, device=rho.device)
+    return B.bh_group_features(bh.ctx, bh.grid, bh.m, out)
+
+
+class ThetaNet:
+    """Handle of one bh_mlp network plus its input normalisation."""
+
+    def __init__(self, ctx, params, mean, scale, meta=None):
+        self.ctx = ctx
+        self.mean = np.asarray(mean, np.float32)
+        self.scale = np.asarray(scale, np.float32)
+        self.h = B.bh_mlp_create(ctx, params, self.mean, self.scale)
+        self.meta = dict(meta or {})
+
+    @classmethod
+    def fresh(cls, ctx, feat_host: np.ndarray, params, meta=None):
+        mean = feat_host.mean(0)
+        std = feat_host.std(0)
+        scale = 1.0 / np.maximum(std, 1e-3)
+        return cls(ctx, params, mean, scale, meta)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            B.bh_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        return B.bh_mlp_get_params(self.ctx, self.h)
+
+    def predict(self, feat: torch.Tensor, bf16=True, out=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+        return B.bh_mlp_forward(self.ctx, self.h, feat, out, bf16)
+
+    def train(self, feat: torch.Tensor, label: torch.Tensor, epochs=200, batch=4096, lr=3e-3, seed=42, log=None):
+        """Adam on mini-batches of the mean squared error; returns per-epoch mean loss."""
+        n = feat.shape[0]
+        gen = torch.Generator(device="cpu").manual_seed(seed)
+        grad = torch.empty(B.MLP_PARAMS, dtype=torch.float32, device=feat.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=feat.device)
+        hist = []
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=gen).to(feat.device)
+            tot = torch.zeros((), dtype=torch.float32, device=feat.device)
+            nb = 0
+            for b0 in range(0, n, batch):
+                idx = perm[b0:b0 + batch]
+                xb = feat.index_select(0, idx).contiguous()
+                yb = label.index_select(0, idx).contiguous()
+                B.bh_mlp_grad(self.ctx, self.h, xb, yb, grad, loss)
+                B.bh_mlp_adam_step(self.ctx, self.h, grad, lr)
+                tot += loss[0]
+                nb += 1
+            hist.append(float(tot) / nb)
+            if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
+                log("epoch %d loss %.3e" % (ep, hist[-1]))
+        return hist
+
+    def save(self, path):
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        np.savez(path, params=self.params(), mean=self.mean, scale=self.scale,
+                 meta=np.array(json.dumps(self.meta)))
+
+    @classmethod
+    def load(cls, ctx, path):
+        z = np.load(path, allow_pickle=False)
+        return cls(ctx, z["params"], z["mean"], z["scale"], json.loads(str(z["meta"])))
+
+
+def solve_learned(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi: torch.Tensor, feat: torch.Tensor,
+                  theta: torch.Tensor, precision=B.BH_FP32, G=1.0):
+    """moments -> features -> bf16 network -> fused walk + sums with per-group theta."""
+    bh.build_moments(rho)
+    B.bh_group_features(bh.ctx, bh.grid, bh.m, feat)
+    B.bh_mlp_forward(bh.ctx, net.h, feat, theta, True)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta, precision, G, phi, None)
+    return phi
+
+
+def sampled_rms(bh: BarnesHut, phi: torch.Tensor, frac=0.01, seed=0, minimum=1000) -> float:
+    """RMS relative error of phi against the exact direct sum on a seeded sample of cells."""
+    n = bh.info["n_cells"]
+    k = min(n, max(minimum, int(frac * n)))
+    rng = np.random.default_rng(seed)
+    tg = torch.tensor(np.sort(rng.choice(n, k, replace=False)), dtype=torch.int64, device=phi.device)
+    d = bh.direct(tg)
+    rel = (phi.reshape(-1).index_select(0, tg) - d) / d
+    return float(torch.sqrt((rel * rel).mean()))
+
+
+def solve_with_fallback(bh, rho, net, phi, feat, theta, target, precision=B.BH_FP32, G=1.0):
+    """Learned theta, judged by a 1% sampled direct sum; fixed theta 0.4 if it misses the target."""
+    solve_learned(bh, rho, net, phi, feat, theta, precision, G)
+    err = sampled_rms(bh, phi)
+    if err <= target:
+        return phi, dict(mode="learned", sampled_rms=err)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, FALLBACK_THETA, None, precision, G, phi, None)
+    return phi, dict(mode="fallback", sampled_rms_learned=err, sampled_rms=sampled_rms(bh, phi))
+
+
+# ------------------------------------------------------------------ training workloads
+
+def training_grids():
+    """Seeded perturbations of the uniform-sphere and MacLaurin workloads."""
+    from amr_inputs import maclaurin_spheroid, uniform_sphere
+    out = []
+    for e in (0.75, 0.85, 0.9, 0.95):
+        for a1 in (0.2, 0.3):
+            out.append(maclaurin_spheroid(e=e, a1=a1, max_level=2))
+    out.append(maclaurin_spheroid(e=0.8, a1=0.25, max_level=3))
+    for R in (0.25, 0.4):
+        for ro in (1e-3, 1e-5):
+            out.append(uniform_sphere(radius=R, rho_out=ro, max_level=2))
+    return out
+
+
+def evaluation_grids(seed=2024, count=3):
+    """Held-out MacLaurin cores shaped like the benchmark workload (e in [0.7, 0.95])."""
+    from amr_inputs import maclaurin_spheroid
+    rng = np.random.default_rng(seed)
+    return [maclaurin_spheroid(e=float(e), a1=0.25, max_level=3) for e in rng.uniform(0.7, 0.95, count)]
+
+
+def build_dataset(grids, target, log=print):
+    feats, labs, errs = [], [], []
+    for g in grids:
+        t0 = time.time()
+        bh = BarnesHut(g)
+        rho = torch.tensor(g.rho, device="cuda")
+        direct = direct_potential(bh, rho)
+        table = error_table(bh, rho, direct)
+        f = group_features(bh, rho).cpu().numpy()
+        feats.append(f)
+        labs.append(labels_from_errors(table, target))
+        errs.append(table)
+        log("data %s: %d groups, %.1f s, mean label %.3f" % (g.name, f.shape[0], time.time() - t0, labs[-1].mean()))
+        bh.close()
+    return np.concatenate(feats), np.concatenate(labs), errs
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("--target", type=float, default=1e-3)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    from amr_inputs.mlp_init import glorot_init
+
+    def log(msg):
+        print("[learned-theta] " + msg, flush=True)
+
+    X, y, _ = build_dataset(training_grids(), args.target, log)
+    ctx = B.bh_ctx_create(0)
+    net = ThetaNet.fresh(ctx, X, glorot_init(42).astype(np.float32),
+                         meta=dict(target=args.target, epochs=args.epochs, lr=args.lr, n_train=int(len(y)), seed=42))
+    fx = torch.tensor(X, device="cuda")
+    fy = torch.tensor(y, device="cuda")
+    t0 = time.time()
+    hist = net.train(fx, fy, epochs=args.epochs, lr=args.lr, log=log)
+    net.meta.update(final_loss=hist[-1], train_seconds=time.time() - t0)
+    pred = net.predict(fx, bf16=True).cpu().numpy()
+    log("train mse %.3e, mean |pred - label| %.3f, label mean %.3f" % (
+        float(np.mean((pred - y) ** 2)), float(np.mean(np.abs(pred - y))), float(y.mean())))
+    out = args.out or os.path.join(DATA_DIR, "theta_mlp_%g.npz" % args.target)
+    net.save(out)
+    log("saved " + out)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

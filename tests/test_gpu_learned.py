@@ -1,0 +1,165 @@
+"""Learned-theta kernels vs the FP64 oracles (features, network, Adam), through the C ABI.
+
+* group features within 1e-4 of the oracle's (from its brute-force moments);
+* per-group RMS error kernel against numpy;
+* fp32 forward within 1e-5, bf16 forward within 0.01 of the FP64 network;
+* gradient within 1e-4 (relative to its largest entry) of the FP64 gradient;
+* Adam steps track the FP64 Adam; training lowers the loss;
+* the learned path (features -> bf16 network -> per-group walk) equals a walk
+  given the same theta array, and the fallback triggers on an impossible target.
+"""
+import numpy as np
+import pytest
+
+from amr_inputs import maclaurin_spheroid, random_amr
+from amr_inputs.mlp_init import glorot_init
+from oracle import OracleTree
+from oracle import mlp as omlp
+from oracle.features import group_features as oracle_features
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1509_07370_amd import binding as B  # noqa: E402
+from paper_1509_07370_amd import learned_theta as LT  # noqa: E402
+from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def amr():
+    g = random_amr(21, nbase=2, max_level=3, p_refine=0.3, zero_fraction=0.1)
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    yield g, bh, rho
+    bh.close()
+
+
+def test_features_parity(amr):
+    g, bh, rho = amr
+    F = LT.group_features(bh, rho).cpu().numpy()
+    ref = oracle_features(OracleTree(g), g)
+    assert F.shape == ref.shape
+    assert np.max(np.abs(F - ref)) <= 1e-4
+
+
+def test_group_rms_error_kernel(amr):
+    g, bh, rho = amr
+    rng = np.random.default_rng(0)
+    ref = torch.tensor(-rng.uniform(1, 2, g.rho.shape), device="cuda")
+    phi = ref * torch.tensor(1 + rng.normal(scale=1e-3, size=g.rho.shape), device="cuda")
+    rms = torch.empty(bh.info["n_groups"], dtype=torch.float32, device="cuda")
+    B.bh_group_rms_error(bh.ctx, bh.grid, phi, ref, rms)
+    r = ((phi - ref) / ref).cpu().numpy()
+    # canonical group g = leaf*8 + Morton run of 64 cells
+    want = np.empty(g.nleaf * 8)
+    for sub in range(8):
+        m = sub * 64 + np.arange(64)
+        i = sum(((m >> (3 * p)) & 1) << p for p in range(3))
+        j = sum(((m >> (3 * p + 1)) & 1) << p for p in range(3))
+        k = sum(((m >> (3 * p + 2)) & 1) << p for p in range(3))
+        want[np.arange(g.nleaf) * 8 + sub] = np.sqrt((r[:, k, j, i] ** 2).mean(1))
+    assert np.allclose(rms.cpu().numpy(), want, rtol=1e-5, atol=0)
+
+
+def _net_data(n=3000, seed=1):
+    rng = np.random.default_rng(seed)
+    X = (rng.normal(size=(n, 12)) * 2 + 0.5).astype(np.float32)
+    y = rng.uniform(0.2, 1.0, n).astype(np.float32)
+    mean = X.mean(0).astype(np.float32)
+    scale = (1 / X.std(0)).astype(np.float32)
+    return X, y, mean, scale
+
+
+def test_forward_fp32_and_bf16_parity():
+    ctx = B.bh_ctx_create(0)
+    X, y, mean, scale = _net_data()
+    p = (glorot_init(5) * 3).astype(np.float32)
+    net = B.bh_mlp_create(ctx, p, mean, scale)
+    fx = torch.tensor(X, device="cuda")
+    out = torch.empty(len(X), dtype=torch.float32, device="cuda")
+    ref, _ = omlp.forward(p.astype(np.float64), X.astype(np.float64), mean.astype(np.float64),
+                          scale.astype(np.float64))
+    B.bh_mlp_forward(ctx, net, fx, out, bf16=False)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-5
+    B.bh_mlp_forward(ctx, net, fx, out, bf16=True)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 0.01
+    B.bh_mlp_destroy(net)
+    B.bh_ctx_destroy(ctx)
+
+
+def test_gradient_parity():
+    ctx = B.bh_ctx_create(0)
+    X, y, mean, scale = _net_data(2500, seed=3)
+    fx, fy = torch.tensor(X, device="cuda"), torch.tensor(y, device="cuda")
+    grad = torch.empty(B.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    args64 = (X.astype(np.float64), y.astype(np.float64), mean.astype(np.float64), scale.astype(np.float64))
+    for seed, gain in ((6, 2.0), (7, 0.5), (8, 4.0)):
+        p = (glorot_init(seed) * gain).astype(np.float32)
+        net = B.bh_mlp_create(ctx, p, mean, scale)
+        B.bh_mlp_grad(ctx, net, fx, fy, grad, loss)
+        g_ref = omlp.grad(p.astype(np.float64), *args64)
+        L = omlp.loss(p.astype(np.float64), *args64)
+        assert np.max(np.abs(grad.cpu().numpy() - g_ref)) <= 1e-4 * np.abs(g_ref).max()
+        assert abs(float(loss[0]) - L) <= 1e-5 * L
+        B.bh_mlp_destroy(net)
+    B.bh_ctx_destroy(ctx)
+
+
+def test_adam_parity():
+    """Adam kernel on seeded gradients (inputs drawn by the test, not by the GPU)."""
+    ctx = B.bh_ctx_create(0)
+    _, _, mean, scale = _net_data(10)
+    p = glorot_init(9).astype(np.float32)
+    net = B.bh_mlp_create(ctx, p, mean, scale)
+    rng = np.random.default_rng(11)
+    pq = p.astype(np.float64)
+    m = np.zeros_like(pq)
+    v = np.zeros_like(pq)
+    for step in range(1, 6):
+        g = (rng.normal(size=B.MLP_PARAMS) * 10.0 ** rng.uniform(-3, 0, B.MLP_PARAMS)).astype(np.float32)
+        B.bh_mlp_adam_step(ctx, net, torch.tensor(g, device="cuda"), 1e-3, 0.9, 0.999, 1e-8)
+        pq, m, v = omlp.adam_step(pq, g.astype(np.float64), m, v, step, 1e-3)
+        assert np.max(np.abs(B.bh_mlp_get_params(ctx, net) - pq)) <= 1e-6
+    B.bh_mlp_destroy(net)
+    B.bh_ctx_destroy(ctx)
+
+
+def test_training_lowers_the_loss():
+    ctx = B.bh_ctx_create(0)
+    rng = np.random.default_rng(8)
+    X = rng.normal(size=(8192, 12)).astype(np.float32)
+    y = (0.6 + 0.3 * np.tanh(X[:, 1] - 0.5 * X[:, 4])).astype(np.float32)
+    net = LT.ThetaNet.fresh(ctx, X, glorot_init(42).astype(np.float32))
+    hist = net.train(torch.tensor(X, device="cuda"), torch.tensor(y, device="cuda"), epochs=40, batch=1024, lr=3e-3)
+    assert hist[-1] < 0.1 * hist[0]
+    net.close()
+    B.bh_ctx_destroy(ctx)
+
+
+def test_learned_path_equals_walk_with_same_thetas_and_fallback():
+    g = maclaurin_spheroid(max_level=1)
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    feat = torch.empty((ng, 12), dtype=torch.float32, device="cuda")
+    theta = torch.empty(ng, dtype=torch.float32, device="cuda")
+    phi = torch.empty_like(rho)
+    X = LT.group_features(bh, rho).cpu().numpy()
+    net = LT.ThetaNet.fresh(bh.ctx, X, glorot_init(42).astype(np.float32))
+    LT.solve_learned(bh, rho, net, phi, feat, theta)
+    th = theta.cpu().numpy()
+    assert np.all(th >= 0.2) and np.all(th <= 1.0)
+    ref = torch.empty_like(rho)
+    bh.walk(0.5, theta, B.BH_FP32)
+    bh.potential(ref, 1.0, B.BH_FP32)
+    assert torch.equal(phi, ref)
+    _, info = LT.solve_with_fallback(bh, rho, net, phi, feat, theta, target=1e-12)
+    assert info["mode"] == "fallback"
+    _, info = LT.solve_with_fallback(bh, rho, net, phi, feat, theta, target=1.0)
+    assert info["mode"] == "learned"
+    net.close()
+    bh.close()
