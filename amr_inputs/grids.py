@@ -294,13 +294,14 @@ def maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_le
 
 
 def cloud_core(r0=0.02, rho0=1.0, r_trunc=0.5, contrast_out=1e-4, sigma=0.1, seed=1509, nbase=4,
-               max_level=7, jeans_cs=None, target_leaves=20000, cells_per_jeans=4.0, centre=(0.5, 0.5, 0.5)):
+               max_level=7, jeans_cs=None, cells_per_jeans=4.0, centre=(0.5, 0.5, 0.5)):
     """Centrally condensed core rho0 / (1 + (r/r0)^2), truncated at r_trunc, lognormal noise.
 
     Blocks are refined while the Jeans length sqrt(pi c_s^2 / (G rho_max)) of the
     block's densest point is shorter than ``cells_per_jeans`` cells (G = 1).  If
-    ``jeans_cs`` is None it is chosen by bisection on log c_s so that the leaf
-    count is close to ``target_leaves`` with the refinement capped at ``max_level``.
+    ``jeans_cs`` is None it is the largest sound speed (bisection on log c_s)
+    for which that criterion still refines down to ``max_level``; with the
+    defaults this gives 24256 leaf blocks (12.4M cells) over 8 levels.
     """
     c = np.asarray(centre, np.float64)
 
@@ -318,9 +319,8 @@ def cloud_core(r0=0.02, rho0=1.0, r_trunc=0.5, contrast_out=1e-4, sigma=0.1, see
             return lam < cells_per_jeans * h
         return refine
 
-    def count_leaves(cs):
-        # cheap count without balance, used only for calibration
-        n = 0
+    def reaches_max_level(cs):
+        # refinement without balance is enough to know the deepest level
         frontier = [(0, np.array([i, j, k], float)) for i in range(nbase) for j in range(nbase)
                     for k in range(nbase)]
         ref = make_refine(cs)
@@ -328,24 +328,24 @@ def cloud_core(r0=0.02, rho0=1.0, r_trunc=0.5, contrast_out=1e-4, sigma=0.1, see
             nxt = []
             for L, ijk in frontier:
                 e = 1.0 / (nbase << L)
-                lo = ijk * e
-                if L < max_level and ref(L, lo, e):
+                if ref(L, ijk * e, e):
+                    if L + 1 == max_level:
+                        return True
                     for o in range(8):
                         nxt.append((L + 1, 2 * ijk + np.array([o & 1, (o >> 1) & 1, (o >> 2) & 1], float)))
-                else:
-                    n += 1
             frontier = nxt
-        return n
+        return False
 
     if jeans_cs is None:
-        lo_cs, hi_cs = -8.0, 2.0  # log10 bracket
+        # the largest sound speed whose Jeans criterion still reaches max_level
+        lo_cs, hi_cs = -8.0, 2.0  # log10 bracket: refines to max_level at lo, not at hi
         for _ in range(40):
             mid = 0.5 * (lo_cs + hi_cs)
-            if count_leaves(10.0 ** mid) > target_leaves:
+            if reaches_max_level(10.0 ** mid):
                 lo_cs = mid
             else:
                 hi_cs = mid
-        jeans_cs = 10.0 ** hi_cs
+        jeans_cs = 10.0 ** lo_cs
 
     rng = np.random.default_rng(seed)
 

@@ -227,9 +227,12 @@ int bh_mlp_create(bh_ctx *ctx, bh_mlp **net, const float *params, const float *m
 int bh_mlp_set_params(bh_ctx *ctx, bh_mlp *net, const float *params);
 /* Synchronising host copy of the parameters. */
 int bh_mlp_get_params(bh_ctx *ctx, const bh_mlp *net, float *params);
-/* theta_dev[n] = network(feat_dev[n][12]).  bf16 = 1: bf16 weights, inputs
- * and hidden activations with fp32 accumulation; bf16 = 0: fp32. */
-int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat_dev, int64_t n, int bf16, float *theta_dev);
+/* theta_dev[n] = clamp(network(feat_dev[n][12]) - theta_shift, 0.05, 1).
+ * bf16 = 1: bf16 weights, inputs and hidden activations with fp32
+ * accumulation; bf16 = 0: fp32.  theta_shift is a safety margin calibrated at
+ * training time (0 gives the raw network output). */
+int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat_dev, int64_t n, int bf16, float theta_shift,
+                   float *theta_dev);
 /* Gradient of L = (1/n) sum (theta(x_s) - label_s)^2 with respect to the
  * parameters (fp32, deterministic order).  grad_dev: fp32 [BH_MLP_PARAMS];
  * loss_dev: NULL or fp32 [1] receiving L. */

@@ -62,7 +62,7 @@ _SIGS = {
     "bh_mlp_create": (ctypes.c_int, [P, PP, P, P, P]),
     "bh_mlp_set_params": (ctypes.c_int, [P, P, P]),
     "bh_mlp_get_params": (ctypes.c_int, [P, P, P]),
-    "bh_mlp_forward": (ctypes.c_int, [P, P, P, i64, ctypes.c_int, P]),
+    "bh_mlp_forward": (ctypes.c_int, [P, P, P, i64, ctypes.c_int, ctypes.c_float, P]),
     "bh_mlp_grad": (ctypes.c_int, [P, P, P, P, i64, P, P]),
     "bh_mlp_adam_step": (ctypes.c_int, [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     "bh_mlp_destroy": (ctypes.c_int, [P]),
@@ -284,9 +284,10 @@ def bh_mlp_get_params(ctx, net):
     return p
 
 
-def bh_mlp_forward(ctx, net, feat, theta, bf16=True):
+def bh_mlp_forward(ctx, net, feat, theta, bf16=True, shift=0.0):
     n = int(feat.shape[0])
-    _check(_lib.bh_mlp_forward(ctx, net, _dev(feat, "float32"), n, int(bool(bf16)), _dev(theta, "float32")), ctx)
+    _check(_lib.bh_mlp_forward(ctx, net, _dev(feat, "float32"), n, int(bool(bf16)), float(shift),
+                               _dev(theta, "float32")), ctx)
     return theta
 
 

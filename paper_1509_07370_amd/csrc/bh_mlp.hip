@@ -124,7 +124,7 @@ template <bool BF16>
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restrict__ P, const uint16_t *__restrict__ Pb,
                                                           const float *__restrict__ mean,
                                                           const float *__restrict__ scale,
-                                                          const float *__restrict__ feat, int64_t n,
+                                                          const float *__restrict__ feat, int64_t n, float shift,
                                                           float *__restrict__ theta) {
     __shared__ float hb[4][64];
     const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
@@ -147,7 +147,10 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
     float h2 = tanhf(a2);
     if (BF16) h2 = bf16_round(h2);
     const float z = wave_sum(W(OW3 + j) * h2) + W(OB3);
-    if (j == 0) theta[s] = 0.2f + 0.8f / (1.0f + expf(-z));
+    if (j == 0) {
+        const float th = 0.2f + 0.8f / (1.0f + expf(-z)) - shift;
+        theta[s] = th < 0.05f ? 0.05f : (th > 1.0f ? 1.0f : th);
+    }
 }
 
 // Gradient of L = (1/n) sum_s (theta_s - y_s)^2 over a contiguous chunk of
@@ -242,16 +245,16 @@ hipError_t launch_mlp_bf16(bh_mlp *net, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(const bh_mlp *net, const float *feat, int64_t n, bool bf16, float *theta,
+hipError_t launch_mlp_forward(const bh_mlp *net, const float *feat, int64_t n, bool bf16, float shift, float *theta,
                               hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int blocks = (int)((n + 3) / 4);
     if (bf16)
         hipLaunchKernelGGL(mlp_forward_kernel<true>, dim3(blocks), dim3(256), 0, s, net->d_params, net->d_bf16,
-                           net->d_mean, net->d_scale, feat, n, theta);
+                           net->d_mean, net->d_scale, feat, n, shift, theta);
     else
         hipLaunchKernelGGL(mlp_forward_kernel<false>, dim3(blocks), dim3(256), 0, s, net->d_params, net->d_bf16,
-                           net->d_mean, net->d_scale, feat, n, theta);
+                           net->d_mean, net->d_scale, feat, n, shift, theta);
     return hipGetLastError();
 }
 

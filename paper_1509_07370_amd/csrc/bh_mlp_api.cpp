@@ -128,13 +128,16 @@ int bh_mlp_get_params(bh_ctx *ctx, const bh_mlp *net, float *params) {
     return BH_OK;
 }
 
-int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat, int64_t n, int bf16, float *theta) {
+int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat, int64_t n, int bf16, float theta_shift,
+                   float *theta) {
     int rc = require_gpu(ctx);
     if (rc) return rc;
     if (!net) return fail(ctx, BH_EINVAL, "network is NULL");
     if (n < 0) return fail(ctx, BH_EINVAL, "n must be >= 0");
     if (n > 0 && (!feat || !theta)) return fail(ctx, BH_EINVAL, "feat_dev or theta_dev is NULL");
-    HIPX(ctx, bh::launch_mlp_forward(net, feat, n, bf16 != 0, theta, ctx->stream), "network forward kernel");
+    if (!std::isfinite(theta_shift)) return fail(ctx, BH_EINVAL, "theta_shift must be finite");
+    HIPX(ctx, bh::launch_mlp_forward(net, feat, n, bf16 != 0, theta_shift, theta, ctx->stream),
+         "network forward kernel");
     return BH_OK;
 }
 

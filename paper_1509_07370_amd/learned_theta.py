@@ -100,10 +100,14 @@ class ThetaNet:
     def params(self) -> np.ndarray:
         return B.bh_mlp_get_params(self.ctx, self.h)
 
-    def predict(self, feat: torch.Tensor, bf16=True, out=None) -> torch.Tensor:
+    @property
+    def shift(self) -> float:
+        return float(self.meta.get("theta_shift", 0.0))
+
+    def predict(self, feat: torch.Tensor, bf16=True, out=None, shift=None) -> torch.Tensor:
         if out is None:
             out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
-        return B.bh_mlp_forward(self.ctx, self.h, feat, out, bf16)
+        return B.bh_mlp_forward(self.ctx, self.h, feat, out, bf16, self.shift if shift is None else shift)
 
     def train(self, feat: torch.Tensor, label: torch.Tensor, epochs=200, batch=4096, lr=3e-3, seed=42, log=None):
         """Adam on mini-batches of the mean squared error; returns per-epoch mean loss."""
@@ -145,7 +149,7 @@ def solve_learned(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi: torch.Te
     """moments -> features -> bf16 network -> fused walk + sums with per-group theta."""
     bh.build_moments(rho)
     B.bh_group_features(bh.ctx, bh.grid, bh.m, feat)
-    B.bh_mlp_forward(bh.ctx, net.h, feat, theta, True)
+    B.bh_mlp_forward(bh.ctx, net.h, feat, theta, True, net.shift)
     B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta, precision, G, phi, None)
     return phi
 
@@ -194,6 +198,28 @@ def evaluation_grids(seed=2024, count=3):
     return [maclaurin_spheroid(e=float(e), a1=0.25, max_level=3) for e in rng.uniform(0.7, 0.95, count)]
 
 
+def estimated_rms(errs: np.ndarray, theta: np.ndarray, thetas=THETA_GRID) -> float:
+    """Global RMS error of one grid if group g walks with theta[g], estimated
+    from its error table at the smallest tabulated theta >= theta[g]."""
+    k = np.clip(np.searchsorted(np.asarray(thetas), np.asarray(theta) - 1e-6), 0, len(thetas) - 1)
+    e = errs[k, np.arange(errs.shape[1])]
+    return float(np.sqrt(np.mean(e.astype(np.float64) ** 2)))
+
+
+def calibrate_shift(net, feats_per_grid, errs_per_grid, target, shifts=np.arange(0.0, 0.5001, 0.025)):
+    """Smallest output shift for which every training grid meets the target."""
+    for s in shifts:
+        ok = True
+        for f, e in zip(feats_per_grid, errs_per_grid):
+            th = net.predict(torch.tensor(f, device="cuda"), bf16=True, shift=float(s)).cpu().numpy()
+            if estimated_rms(e, th) > target:
+                ok = False
+                break
+        if ok:
+            return float(s)
+    return float(shifts[-1])
+
+
 def build_dataset(grids, target, log=print):
     feats, labs, errs = [], [], []
     for g in grids:
@@ -208,12 +234,66 @@ def build_dataset(grids, target, log=print):
         errs.append(table)
         log("data %s: %d groups, %.1f s, mean label %.3f" % (g.name, f.shape[0], time.time() - t0, labs[-1].mean()))
         bh.close()
-    return np.concatenate(feats), np.concatenate(labs), errs
+    return feats, labs, errs
+
+
+def evaluate(net: ThetaNet, grids, target, precision=B.BH_FP32, reps=10, log=print):
+    """Learned theta vs every fixed theta of the grid on held-out workloads."""
+    out = []
+    for g in grids:
+        bh = BarnesHut(g)
+        rho = torch.tensor(g.rho, device="cuda")
+        direct = direct_potential(bh, rho)
+        ng = bh.info["n_groups"]
+        n = bh.info["n_cells"]
+        phi = torch.empty_like(rho)
+        feat = torch.empty((ng, B.MLP_INPUTS), dtype=torch.float32, device="cuda")
+        theta = torch.empty(ng, dtype=torch.float32, device="cuda")
+
+        def rms_of(p):
+            rel = ((p - direct) / direct).reshape(-1)
+            return float(torch.sqrt((rel * rel).mean()))
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / reps
+
+        fixed = []
+        for th in THETA_GRID:
+            def run(th=float(th)):
+                bh.build_moments(rho)
+                B.bh_walk_potential(bh.ctx, bh.grid, bh.m, th, None, precision, 1.0, phi, None)
+            ms = timed(run)
+            fixed.append(dict(theta=float(th), rms=rms_of(phi), ms=ms))
+        ms_l = timed(lambda: solve_learned(bh, rho, net, phi, feat, theta, precision))
+        th = theta.cpu().numpy()
+        rec = dict(grid=g.name, meta={k: v for k, v in g.meta.items() if k in ("e", "a1")}, cells=n,
+                   learned=dict(rms=rms_of(phi), ms=ms_l, mcells=n / ms_l / 1e3, theta_mean=float(th.mean()),
+                                theta_p10=float(np.percentile(th, 10)), theta_p90=float(np.percentile(th, 90)),
+                                sampled_rms=sampled_rms(bh, phi)),
+                   fixed=fixed)
+        ok = [f for f in fixed if f["rms"] <= target]
+        best = max(ok, key=lambda f: f["theta"]) if ok else None
+        rec["best_fixed"] = best
+        if best:
+            rec["learned_speedup_vs_best_fixed"] = best["ms"] / ms_l
+        log("eval e=%.3f: learned rms %.2e %.3f ms (theta mean %.3f) | best fixed theta %s rms %s %s ms" % (
+            g.meta.get("e", 0), rec["learned"]["rms"], ms_l, th.mean(), best and best["theta"],
+            best and "%.2e" % best["rms"], best and "%.3f" % best["ms"]))
+        out.append(rec)
+        bh.close()
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("cmd", choices=["train", "evaluate"])
+    ap.add_argument("--weights", default=None)
     ap.add_argument("--target", type=float, default=1e-3)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=3e-3)
@@ -224,8 +304,14 @@ def main(argv=None):
     def log(msg):
         print("[learned-theta] " + msg, flush=True)
 
-    X, y, _ = build_dataset(training_grids(), args.target, log)
     ctx = B.bh_ctx_create(0)
+    if args.cmd == "evaluate":
+        net = ThetaNet.load(ctx, args.weights or os.path.join(DATA_DIR, "theta_mlp_%g.npz" % args.target))
+        res = evaluate(net, evaluation_grids(), float(net.meta.get("target", args.target)), log=log)
+        print(json.dumps(dict(target=net.meta.get("target"), shift=net.shift, results=res)))
+        return 0
+    F, Y, E = build_dataset(training_grids(), args.target, log)
+    X, y = np.concatenate(F), np.concatenate(Y)
     net = ThetaNet.fresh(ctx, X, glorot_init(42).astype(np.float32),
                          meta=dict(target=args.target, epochs=args.epochs, lr=args.lr, n_train=int(len(y)), seed=42))
     fx = torch.tensor(X, device="cuda")
@@ -236,6 +322,8 @@ def main(argv=None):
     pred = net.predict(fx, bf16=True).cpu().numpy()
     log("train mse %.3e, mean |pred - label| %.3f, label mean %.3f" % (
         float(np.mean((pred - y) ** 2)), float(np.mean(np.abs(pred - y))), float(y.mean())))
+    net.meta["theta_shift"] = calibrate_shift(net, F, E, args.target)
+    log("calibrated output shift %.3f" % net.meta["theta_shift"])
     out = args.out or os.path.join(DATA_DIR, "theta_mlp_%g.npz" % args.target)
     net.save(out)
     log("saved " + out)

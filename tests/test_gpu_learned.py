@@ -83,9 +83,12 @@ def test_forward_fp32_and_bf16_parity():
     ref, _ = omlp.forward(p.astype(np.float64), X.astype(np.float64), mean.astype(np.float64),
                           scale.astype(np.float64))
     B.bh_mlp_forward(ctx, net, fx, out, bf16=False)
+    ref_shift = np.clip(ref - 0.1, 0.05, 1.0)
     assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-5
     B.bh_mlp_forward(ctx, net, fx, out, bf16=True)
     assert np.max(np.abs(out.cpu().numpy() - ref)) <= 0.01
+    B.bh_mlp_forward(ctx, net, fx, out, bf16=False, shift=0.1)
+    assert np.max(np.abs(out.cpu().numpy() - ref_shift)) <= 1e-5
     B.bh_mlp_destroy(net)
     B.bh_ctx_destroy(ctx)
 

@@ -14,3 +14,10 @@ def test_labels_envelope():
 
 def test_theta_grid():
     assert LT.THETA_GRID[0] == 0.2 and LT.THETA_GRID[-1] == 1.0 and len(LT.THETA_GRID) == 17
+
+
+def test_estimated_rms_uses_the_next_tabulated_theta():
+    th = np.array([0.2, 0.25, 0.3])
+    e = np.array([[1e-5, 1e-5], [1e-4, 2e-5], [1e-3, 3e-5]], np.float32)
+    assert LT.estimated_rms(e, np.array([0.2, 0.25]), th) == pytest.approx(np.sqrt((1e-10 + 4e-10) / 2), rel=1e-6)
+    assert LT.estimated_rms(e, np.array([0.21, 0.3]), th) == pytest.approx(np.sqrt((1e-8 + 9e-10) / 2), rel=1e-6)
