@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: Barnes-Hut potential of a MacLaurin spheroid AMR mesh on one MI355X.
 
-Workload (fixed, synthetic, seeded by construction): homogeneous oblate spheroid
-of eccentricity 0.9 and semi-major axis 0.25 in the unit box, rho = 1 inside and
+Workload (fixed, synthetic, deterministic): homogeneous oblate spheroid of
+eccentricity 0.9 and semi-major axis 0.25 in the unit box, rho = 1 inside and
 1e-5 outside, base 4^3 blocks of 8^3 cells refined 3 levels at the surface
-(2752 leaf blocks, 1,409,024 cells), group size 64, G = 1.
+(2752 leaf blocks, 1,409,024 cells), 64-cell groups, G = 1.
 
 One step = the whole hot path with the densities already in HBM:
-moments upward pass -> group walk fused with the far + near potential sums
-(bh_walk_potential; the list API path is timed beside it in the sweep).  The metric is whole-step throughput in Mcells/s at
-the largest theta of {0.3, 0.5, 0.7} whose RMS relative error against the
-exact direct sum (computed on the GPU in fp64, outside the timed region) is at
-most 1e-3.
+moments upward pass -> per-group theta (features + bf16 network, one kernel)
+-> group walk fused with the far + near potential sums.  `value` is cells per
+second of that step with the network trained for an RMS target of 1e-3; the
+RMS relative error against the exact direct sum (GPU, fp64, outside the timed
+region) is checked.  For comparison the same step with a fixed theta -- the
+largest theta of {0.20, 0.25, ..., 1.00} meeting the gate -- is timed in fp32
+and fp64 (`fixed_theta`), with the full sweep in `sweep`.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -29,11 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector (packed) datasheet figure
-PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector datasheet figure
 F_FAR = 35                  # flop per (cell, far node): monopole + quadrupole
 F_NEAR = 11                 # flop per (cell, near cell) pair
 RMS_GATE = 1e-3
+WEIGHTS = os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz")
+PROFILE = os.path.join(ROOT, "profiles", "walk_potential_fp32_maclaurin_1p4M.md")
 
 
 def log(msg):
@@ -44,10 +47,9 @@ def profiled_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     summary, or None when the kernel source has changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "walk_potential_fp32_maclaurin_1p4M.md")
     src = os.path.join(ROOT, "paper_1509_07370_amd", "csrc", "bh_kernels.hip")
     try:
-        text = open(path).read()
+        text = open(PROFILE).read()
         want = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -75,7 +77,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
-                    help="skip the accuracy sweep and CPU baseline (for profiler runs)")
+                    help="time the headline step only (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -87,6 +89,7 @@ def main():
     import torch
     from amr_inputs import maclaurin_spheroid
     from paper_1509_07370_amd import binding as B
+    from paper_1509_07370_amd import learned_theta as LT
     from paper_1509_07370_amd.solver import BarnesHut
 
     dev = torch.device("cuda", 0)
@@ -101,6 +104,7 @@ def main():
         log("copied %d MiB three times (reads %d KiB and writes %d KiB per copy)" % (
             args.copy_calibration, args.copy_calibration * 1024, args.copy_calibration * 1024))
         return
+
     t0 = time.time()
     grid = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
     log("workload: %d leaf blocks, %d cells (%.1f s to generate)" % (grid.nleaf, grid.ncells, time.time() - t0))
@@ -110,81 +114,96 @@ def main():
     rho = torch.tensor(grid.rho, device=dev)
     phi = torch.empty_like(rho)
     ncells = grid.ncells
+    ng = bh.info["n_groups"]
+    counts = torch.zeros((ng, 2), dtype=torch.int32, device=dev)
+    feat = torch.empty((ng, B.MLP_INPUTS), dtype=torch.float32, device=dev)
+    theta_g = torch.empty(ng, dtype=torch.float32, device=dev)
+    net = LT.ThetaNet.load(bh.ctx, WEIGHTS)
 
-    counts = torch.zeros((bh.info["n_groups"], 2), dtype=torch.int32, device=dev)
+    def step_learned():
+        LT.solve_learned(bh, rho, net, phi, feat, theta_g, B.BH_FP32)
 
-    def step(theta, prec):
-        """one pass of the hot path: moments, then the fused walk + far/near sums"""
+    def step_fixed(theta, prec):
         bh.build_moments(rho)
         B.bh_walk_potential(bh.ctx, bh.grid, bh.m, theta, None, prec, 1.0, phi, None)
 
-    def step_lists(theta, prec):
-        """the same pass through the list API (walk count + scan + fill, then sums)"""
-        bh.build_moments(rho)
-        bh.walk(theta, None, prec)
-        bh.potential(phi, 1.0, prec)
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
 
-    sweep = []
-    thetas = (0.3, 0.5, 0.7)
-    head_theta = 0.7
+    sweep, fixed, learned = [], {}, {}
     if not args.profile_only:
         bh.build_moments(rho)
         t0 = time.time()
-        direct = bh.direct(torch.arange(ncells, device=dev, dtype=torch.int64))
+        direct = bh.direct(torch.arange(ncells, device=dev, dtype=torch.int64)).reshape(rho.shape)
         torch.cuda.synchronize()
         log("direct sum (fp64, full grid) %.2f s" % (time.time() - t0))
-        for prec in (B.BH_FP32, B.BH_FP64):
-            for th in thetas:
-                step(th, prec)
-                torch.cuda.synchronize()
-                rel = ((phi.reshape(-1) - direct) / direct).abs()
-                rms = float(torch.sqrt((rel ** 2).mean()))
-                mx = float(rel.max())
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(5):
-                    step(th, prec)
-                torch.cuda.synchronize()
-                ms = (time.perf_counter() - t0) * 1e3 / 5
-                t0 = time.perf_counter()
-                for _ in range(5):
-                    step_lists(th, prec)
-                torch.cuda.synchronize()
-                ms_lists = (time.perf_counter() - t0) * 1e3 / 5
-                nf, nn = B.bh_lists_info(bh.lists)
-                sweep.append(dict(theta=th, precision="fp32" if prec == B.BH_FP32 else "fp64", rms_rel_err=rms,
-                                  max_rel_err=mx, ms_per_step=ms, mcells_per_s=ncells / ms / 1e3,
-                                  ms_per_step_list_api=ms_lists, far_entries=nf, near_entries=nn))
-                log("sweep %s theta=%.1f rms=%.2e max=%.2e fused %.3f ms (%.1f Mcells/s), lists %.3f ms" % (
-                    sweep[-1]["precision"], th, rms, mx, ms, ncells / ms / 1e3, ms_lists))
-        ok = [s["theta"] for s in sweep if s["precision"] == "fp32" and s["rms_rel_err"] <= RMS_GATE]
-        head_theta = max(ok) if ok else min(thetas)
-    prec = B.BH_FP32
 
-    # ---- timed region: K whole steps
+        def errors():
+            rel = ((phi - direct) / direct).reshape(-1)
+            return float(torch.sqrt((rel * rel).mean())), float(rel.abs().max())
+
+        for th in LT.THETA_GRID:
+            step_fixed(float(th), B.BH_FP32)
+            rms, mx = errors()
+            ms = timed(lambda: step_fixed(float(th), B.BH_FP32), 5)
+            sweep.append(dict(theta=float(th), precision="fp32", rms_rel_err=rms, max_rel_err=mx, ms_per_step=ms,
+                              mcells_per_s=ncells / ms / 1e3))
+        ok = [s for s in sweep if s["rms_rel_err"] <= RMS_GATE]
+        best = max(ok, key=lambda s: s["theta"])
+        th_best = best["theta"]
+        for th in sorted({0.3, 0.5, 0.7, th_best}):
+            step_fixed(th, B.BH_FP64)
+            rms, mx = errors()
+            ms = timed(lambda: step_fixed(th, B.BH_FP64), 3)
+            sweep.append(dict(theta=th, precision="fp64", rms_rel_err=rms, max_rel_err=mx, ms_per_step=ms,
+                              mcells_per_s=ncells / ms / 1e3))
+        fp64 = [s for s in sweep if s["precision"] == "fp64" and s["theta"] == th_best][0]
+        fixed = dict(theta=th_best, fp32=best, fp64=fp64)
+        log("best fixed theta %.2f: fp32 %.1f Mcells/s (rms %.2e), fp64 %.1f Mcells/s" % (
+            th_best, best["mcells_per_s"], best["rms_rel_err"], fp64["mcells_per_s"]))
+        step_learned()
+        rms, mx = errors()
+        th = theta_g.cpu().numpy()
+        learned = dict(rms_rel_err=rms, max_rel_err=mx, sampled_rms_1pct=LT.sampled_rms(bh, phi),
+                       theta_mean=float(th.mean()), theta_min=float(th.min()), theta_max=float(th.max()),
+                       network_target=float(net.meta.get("target", RMS_GATE)), theta_shift=net.shift)
+        log("learned theta: rms %.2e (1%% sample %.2e), theta mean %.3f" % (rms, learned["sampled_rms_1pct"],
+                                                                           th.mean()))
+
+    # ---- timed region: K whole learned-theta steps
     for _ in range(args.warmup):
-        step(head_theta, prec)
+        step_learned()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(head_theta, prec)
+        step_learned()
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    log("timed %d steps at theta=%.1f: %.3f ms/step" % (args.steps, head_theta, ms_step))
-
     bh.check()
+    log("timed %d learned-theta steps: %.3f ms/step" % (args.steps, ms_step))
+    if learned:
+        learned.update(ms_per_step=ms_step, mcells_per_s=ncells / ms_step / 1e3)
+        if fixed:
+            learned["speedup_vs_fixed_fp32"] = fixed["fp32"]["ms_per_step"] / ms_step
+            learned["speedup_vs_fixed_fp64"] = fixed["fp64"]["ms_per_step"] / ms_step
 
-    # ---- dominant kernel: fused walk + far/near sums, timed with events on the library's stream
+    # ---- dominant kernel: fused walk + far/near sums, hipEvents on the library's stream
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     nrep = max(args.steps, 10)
     ev0.record(stream)
     for _ in range(nrep):
-        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, head_theta, None, prec, 1.0, phi, None)
+        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta_g, B.BH_FP32, 1.0, phi, None)
     ev1.record(stream)
     torch.cuda.synchronize()
     pot_ms = ev0.elapsed_time(ev1) / nrep
-    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, head_theta, None, prec, 1.0, phi, counts)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta_g, B.BH_FP32, 1.0, phi, counts)
     c = counts.cpu().numpy().astype(np.int64)
     flops, far_int, near_pairs = algorithmic_flops(c[:, 0], c[:, 1])
     achieved = flops / (pot_ms * 1e-3) / 1e12
@@ -193,16 +212,17 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and not args.profile_only:
         from oracle import OracleTree
+        th = theta_g.cpu().numpy().astype(np.float64)
         t0 = time.perf_counter()
         ot = OracleTree(grid)
         ot.moments()
-        ot.walk(64, head_theta)
+        ot.walk(64, th)
         ot.potential()
         cpu_s = time.perf_counter() - t0
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cpu = dict(value=ncells / cpu_s / 1e6, unit="Mcells/s", cores=threads, kind="oracle",
-                   sample="whole workload (%d cells), fp64 oracle: tree + moments + walk + sum at theta=%.1f, "
-                          "%.2f s" % (ncells, head_theta, cpu_s))
+                   sample="whole workload (%d cells): fp64 oracle tree + moments + walk + sum with the same "
+                          "per-group theta, %.2f s" % (ncells, cpu_s))
         log("cpu oracle %.2f s on %d threads" % (cpu_s, threads))
 
     out = {
@@ -219,10 +239,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "MacLaurin spheroid e=0.9 a1=0.25, rho 1/1e-5, 4^3 base blocks of 8^3 + 3 AMR "
-                               "levels at the surface (%d leaf blocks, %d cells), fixed theta=%.1f, group 64, "
-                               "fp32 walk and pair terms with fp64 accumulation" % (grid.nleaf, ncells, head_theta),
-                   "cells": ncells, "theta": head_theta, "group_cells": 64, "theta_mode": "fixed",
+                               "levels at the surface (%d leaf blocks, %d cells); learned per-group theta (bf16 "
+                               "network, RMS target 1e-3); fp32 walk and pair terms, fp64 accumulation; 64-cell "
+                               "groups" % (grid.nleaf, ncells),
+                   "cells": ncells, "group_cells": 64, "theta_mode": "learned",
                    "precision": "fp32-walk/fp64-accumulate"},
+        "learned_theta": learned,
+        "fixed_theta": fixed,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
                      "kernel": "walk_potential_kernel<float>", "kernel_ms": pot_ms, "flop_per_launch": flops,
@@ -232,6 +255,7 @@ def main():
         "sweep": sweep,
     }
     print(json.dumps(out), flush=True)
+    net.close()
     bh.close()
 
 

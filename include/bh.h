@@ -233,6 +233,11 @@ int bh_mlp_get_params(bh_ctx *ctx, const bh_mlp *net, float *params);
  * training time (0 gives the raw network output). */
 int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat_dev, int64_t n, int bf16, float theta_shift,
                    float *theta_dev);
+/* Per-group theta for a walk in one pass: the features of bh_group_features
+ * fed to the bf16 network (as bh_mlp_forward with bf16 = 1) without storing
+ * them.  theta_dev: fp32 [n_groups], canonical group order. */
+int bh_theta_infer(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_mlp *net, float theta_shift,
+                   float *theta_dev);
 /* Gradient of L = (1/n) sum (theta(x_s) - label_s)^2 with respect to the
  * parameters (fp32, deterministic order).  grad_dev: fp32 [BH_MLP_PARAMS];
  * loss_dev: NULL or fp32 [1] receiving L. */

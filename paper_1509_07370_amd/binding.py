@@ -64,6 +64,7 @@ _SIGS = {
     "bh_mlp_get_params": (ctypes.c_int, [P, P, P]),
     "bh_mlp_forward": (ctypes.c_int, [P, P, P, i64, ctypes.c_int, ctypes.c_float, P]),
     "bh_mlp_grad": (ctypes.c_int, [P, P, P, P, i64, P, P]),
+    "bh_theta_infer": (ctypes.c_int, [P, P, P, P, ctypes.c_float, P]),
     "bh_mlp_adam_step": (ctypes.c_int, [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     "bh_mlp_destroy": (ctypes.c_int, [P]),
 }
@@ -288,6 +289,11 @@ def bh_mlp_forward(ctx, net, feat, theta, bf16=True, shift=0.0):
     n = int(feat.shape[0])
     _check(_lib.bh_mlp_forward(ctx, net, _dev(feat, "float32"), n, int(bool(bf16)), float(shift),
                                _dev(theta, "float32")), ctx)
+    return theta
+
+
+def bh_theta_infer(ctx, grid, m, net, theta, shift=0.0):
+    _check(_lib.bh_theta_infer(ctx, grid, m, net, float(shift), _dev(theta, "float32")), ctx)
     return theta
 
 

@@ -30,6 +30,8 @@ struct bh_mlp {
 
 namespace bh {
 hipError_t launch_mlp_bf16(bh_mlp *net, hipStream_t s);
+hipError_t launch_theta_infer(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift, float *theta,
+                              hipStream_t s);
 hipError_t launch_mlp_forward(const bh_mlp *net, const float *feat, int64_t n, bool bf16, float shift, float *theta,
                               hipStream_t s);
 hipError_t launch_mlp_grad(bh_mlp *net, const float *feat, const float *label, int64_t n, float *grad, float *loss,

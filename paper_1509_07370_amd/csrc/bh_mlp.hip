@@ -239,6 +239,88 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ P, fl
     P[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
+// Features and bf16 network in one pass, one wavefront per group: lanes load
+// the group's 64 cell masses (max and mean by wave reductions), every lane
+// derives the 12 features (same arithmetic as features_kernel), then lane j
+// evaluates hidden unit j of both layers.
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        double u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void theta_infer_kernel(const LeafInfo *__restrict__ leaves,
+                                                          const double *__restrict__ mom,
+                                                          const double *__restrict__ geom,
+                                                          const int32_t *__restrict__ parent,
+                                                          const double4 *__restrict__ cells, int64_t n_groups,
+                                                          int root, double box, int nbase,
+                                                          const uint16_t *__restrict__ Pb,
+                                                          const float *__restrict__ mean,
+                                                          const float *__restrict__ scale, float shift,
+                                                          float *__restrict__ theta) {
+    __shared__ float hb[4][64];
+    const int w = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= n_groups) return;
+    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const LeafInfo L = leaves[f];
+    const double mc = cells[(int64_t)f * kCellsPerBlock + sub * 64 + j].w;
+    const double msum = wave_sum_d(mc);
+    const double mmax = wave_max_d(mc);
+    const int node[3] = {L.oct_first + sub, L.block_node, parent[L.block_node] >= 0 ? parent[L.block_node]
+                                                                                    : L.block_node};
+    const double Mroot = mom[(int64_t)root * kMom + 3];
+    const double Mg = mom[(int64_t)node[0] * kMom + 3];
+    const double Mb = mom[(int64_t)node[1] * kMom + 3];
+    float ft[kMlpIn];
+    ft[0] = 6.0f;
+    ft[1] = (float)log_floor(Mroot > 0.0 ? Mg / Mroot : 0.0, 1e-30);
+    ft[2] = (float)log(4.0 * L.h / box);
+    ft[3] = (float)rint(log2(box / ((double)nbase * kNB * L.h)));
+    ft[4] = (float)(msum > 0.0 ? log(mmax / (msum / 64.0)) : 0.0);
+    for (int a = 0; a < 3; a++) {
+        const double *r = mom + (int64_t)node[a] * kMom;
+        const double l = geom[4 * (int64_t)node[a] + 3];
+        const double M = r[3];
+        const double qf = sqrt(r[4] * r[4] + r[5] * r[5] + r[6] * r[6] + 2.0 * (r[7] * r[7] + r[8] * r[8] + r[9] * r[9]));
+        ft[5 + 2 * a] = (float)log(r[10] / l + 1e-6);
+        ft[6 + 2 * a] = (float)log((M > 0.0 ? qf / (M * l * l) : 0.0) + 1e-6);
+    }
+    ft[11] = (float)(Mb > 0.0 ? log_floor(8.0 * Mg / Mb, 1e-30) : 0.0);
+    float x[kMlpIn];
+    for (int i = 0; i < kMlpIn; i++) x[i] = bf16_round((ft[i] - mean[i]) * scale[i]);
+    float a1 = bf16_load(Pb, OB1 + j);
+    for (int i = 0; i < kMlpIn; i++) a1 = fmaf(bf16_load(Pb, OW1 + j * kMlpIn + i), x[i], a1);
+    hb[w][j] = bf16_round(tanhf(a1));
+    wave_lds_sync();
+    float a2 = bf16_load(Pb, OB2 + j);
+    for (int k = 0; k < kMlpHidden; k++) a2 = fmaf(bf16_load(Pb, OW2 + j * kMlpHidden + k), hb[w][k], a2);
+    const float h2 = bf16_round(tanhf(a2));
+    const float z = wave_sum(bf16_load(Pb, OW3 + j) * h2) + bf16_load(Pb, OB3);
+    if (j == 0) {
+        const float th = 0.2f + 0.8f / (1.0f + expf(-z)) - shift;
+        theta[(int64_t)L.canon * 8 + sub] = th < 0.05f ? 0.05f : (th > 1.0f ? 1.0f : th);
+    }
+}
+
+hipError_t launch_theta_infer(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift, float *theta,
+                              hipStream_t s) {
+    const int blocks = (int)((g->n_groups + 3) / 4);
+    hipLaunchKernelGGL(theta_infer_kernel, dim3(blocks), dim3(256), 0, s, g->d_leaves, m->d_mom, g->d_geom,
+                       g->d_parent, m->d_cell64, g->n_groups, g->topo.root, g->topo.box, g->topo.nbase, net->d_bf16,
+                       net->d_mean, net->d_scale, shift, theta);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_bf16(bh_mlp *net, hipStream_t s) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, net->d_params, net->d_bf16,
                        kMlpParams);

@@ -141,6 +141,17 @@ int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat, int64_t n,
     return BH_OK;
 }
 
+int bh_theta_infer(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift,
+                   float *theta) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!g || !m || !net || !theta) return fail(ctx, BH_EINVAL, "grid, moments, network or theta_dev is NULL");
+    if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (!std::isfinite(shift)) return fail(ctx, BH_EINVAL, "theta_shift must be finite");
+    HIPX(ctx, bh::launch_theta_infer(g, m, net, shift, theta, ctx->stream), "theta inference kernel");
+    return BH_OK;
+}
+
 int bh_mlp_grad(bh_ctx *ctx, bh_mlp *net, const float *feat, const float *label, int64_t n, float *grad,
                 float *loss) {
     int rc = require_gpu(ctx);

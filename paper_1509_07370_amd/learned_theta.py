@@ -146,10 +146,10 @@ class ThetaNet:
 
 def solve_learned(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi: torch.Tensor, feat: torch.Tensor,
                   theta: torch.Tensor, precision=B.BH_FP32, G=1.0):
-    """moments -> features -> bf16 network -> fused walk + sums with per-group theta."""
+    """moments -> features + bf16 network (one kernel) -> fused walk + sums with per-group theta.
+    ``feat`` is unused (kept for callers that stage features separately)."""
     bh.build_moments(rho)
-    B.bh_group_features(bh.ctx, bh.grid, bh.m, feat)
-    B.bh_mlp_forward(bh.ctx, net.h, feat, theta, True, net.shift)
+    B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, theta, net.shift)
     B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta, precision, G, phi, None)
     return phi
 

@@ -155,6 +155,11 @@ def test_learned_path_equals_walk_with_same_thetas_and_fallback():
     net = LT.ThetaNet.fresh(bh.ctx, X, glorot_init(42).astype(np.float32))
     LT.solve_learned(bh, rho, net, phi, feat, theta)
     th = theta.cpu().numpy()
+    # the one-pass inference equals features + bf16 forward
+    two = torch.empty_like(theta)
+    B.bh_group_features(bh.ctx, bh.grid, bh.m, feat)
+    B.bh_mlp_forward(bh.ctx, net.h, feat, two, True, net.shift)
+    assert np.max(np.abs(two.cpu().numpy() - th)) <= 5e-3  # same features up to summation order, bf16 inputs
     assert np.all(th >= 0.2) and np.all(th <= 1.0)
     ref = torch.empty_like(rho)
     bh.walk(0.5, theta, B.BH_FP32)
