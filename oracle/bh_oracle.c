@@ -512,9 +512,10 @@ void ot_walk_export(const otree *t, int64_t *far_off, uint64_t *far_keys, int64_
     memcpy(counts, t->counts, sizeof(int64_t) * 4 * (size_t)t->ngroups);
 }
 
-/* O7 for one group given its lists (node ids) */
-static void sum_group(const otree *t, int64_t g, int G, const int *far, int nfar, const int *near, int nnear,
-                      double Gc, int order, double *phi, int64_t *cells) {
+/* O7 for one group given its lists (node ids).  phi is indexed by canonical
+ * cell id, or by the cell's position in the group when local != 0. */
+static void sum_group_to(const otree *t, int64_t g, int G, const int *far, int nfar, const int *near, int nnear,
+                         double Gc, int order, double *phi, int64_t *cells, int local) {
     group_cells_of(t, g, G, cells);
     for (int q = 0; q < G; q++) {
         int64_t i = cells[q];
@@ -539,8 +540,13 @@ static void sum_group(const otree *t, int64_t g, int G, const int *far, int nfar
                 nadd(&acc, t->cm[j] / sqrt(rx * rx + ry * ry + rz * rz));
             }
         }
-        phi[i] = -Gc * nval(&acc);
+        phi[local ? q : i] = -Gc * nval(&acc);
     }
+}
+
+static void sum_group(const otree *t, int64_t g, int G, const int *far, int nfar, const int *near, int nnear,
+                      double Gc, int order, double *phi, int64_t *cells) {
+    sum_group_to(t, g, G, far, nfar, near, nnear, Gc, order, phi, cells, 0);
 }
 
 /* O7 using the lists of the last ot_walk; phi in caller layout.
@@ -597,6 +603,40 @@ int ot_potential_lists(const otree *t, int group_cells, const int64_t *far_off, 
         free(fl); free(nl); free(cells);
     }
     return err;
+}
+
+/* O5-O7 for a subset of groups only (sampled checks on large grids):
+ * counts[4 * q + ...] as in ot_walk for groups[q]; phi[q * G + c] for the
+ * group's c-th cell in Morton order.  theta_group is indexed by canonical
+ * group id, as in ot_walk. */
+void ot_solve_groups(const otree *t, int group_cells, const double *theta_group, const int64_t *groups, int64_t n,
+                     double tau, double Gc, int order, int64_t *counts, double *phi) {
+    int G = group_cells;
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)G);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < n; q++) {
+            int64_t g = groups[q];
+            group_cells_of(t, g, G, cells);
+            ivec far = {0, 0, NULL}, near = {0, 0, NULL};
+            walkctx w;
+            w.t = t; w.cells = cells; w.G = G;
+            w.inv_theta = 1.0 / theta_group[g];
+            w.tau = tau;
+            w.far = &far; w.near = &near;
+            w.visited = 0; w.marginal = 0;
+            walk_node(&w, t->root);
+            counts[4 * q + 0] = w.visited;
+            counts[4 * q + 1] = far.n;
+            counts[4 * q + 2] = near.n;
+            counts[4 * q + 3] = w.marginal;
+            sum_group_to(t, g, G, far.v, far.n, near.v, near.n, Gc, order, phi + q * G, cells, 1);
+            free(far.v);
+            free(near.v);
+        }
+        free(cells);
+    }
 }
 
 /* O2 for selected targets (canonical cell ids) */

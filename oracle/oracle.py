@@ -72,6 +72,8 @@ def _load():
         lib.ot_potential_lists.restype = ctypes.c_int
         lib.ot_potential_lists.argtypes = [P, ctypes.c_int, P, P, P, P, ctypes.c_double, ctypes.c_int, P]
         lib.ot_direct.argtypes = [P, P, i64, ctypes.c_double, P]
+        lib.ot_solve_groups.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        P, P]
         lib.ot_cells.argtypes = [P, P, P, P, P]
         _lib = lib
         return lib
@@ -221,6 +223,20 @@ class OracleTree:
         if rc != 0:
             raise ValueError("list replay: %s" % ("unknown node key" if rc == -1 else "near entry not a bottom node"))
         return phi.reshape(self.nleaf, 8, 8, 8)
+
+    def solve_groups(self, groups, group_cells=64, theta=0.5, tau=0.0, G=1.0, order=2):
+        """O5-O7 for selected canonical groups only.  Returns (phi[n, G] in the
+        group's Morton order, counts[n, 4] = visited, far, near, marginal)."""
+        if not self._moments_done:
+            self.moments()
+        ng = self.n_groups(group_cells)
+        th = np.broadcast_to(np.asarray(theta, np.float64), (ng,)).copy()
+        gs = np.ascontiguousarray(groups, np.int64)
+        phi = np.empty((gs.size, group_cells))
+        counts = np.empty((gs.size, 4), np.int64)
+        self.lib.ot_solve_groups(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau), float(G),
+                                 int(order), _p(counts), _p(phi))
+        return phi, counts
 
     # -- O2 ----------------------------------------------------------------------
     def direct(self, targets=None, G=1.0):

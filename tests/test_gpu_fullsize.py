@@ -1,0 +1,129 @@
+"""Full-size checks: the 12.4M-cell cloud core and the 1.4M-cell benchmark mesh.
+
+The oracle re-solves a seeded sample of groups one by one (its own walk and
+sums) and the exact direct sum at sampled cells; groups holding a decision the
+oracle flags as marginal are excluded from the element-wise comparison and
+counted.  Properties that hold at any size are checked on the whole grid.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from amr_inputs import cloud_core, maclaurin_spheroid
+from oracle import OracleTree
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1509_07370_amd import binding as B  # noqa: E402
+from paper_1509_07370_amd import learned_theta as LT  # noqa: E402
+from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TAU = {B.BH_FP64: 1e-12, B.BH_FP32: 2e-6}
+TOL = {B.BH_FP64: 1e-12, B.BH_FP32: 1e-5}
+
+
+def _morton_cells(groups):
+    """canonical cell ids of each group's cells in Morton order, [n, 64]"""
+    m = np.arange(64)
+    out = []
+    for gi in groups:
+        leaf, sub = divmod(int(gi), 8)
+        mm = sub * 64 + m
+        i = sum(((mm >> (3 * p)) & 1) << p for p in range(3))
+        j = sum(((mm >> (3 * p + 1)) & 1) << p for p in range(3))
+        k = sum(((mm >> (3 * p + 2)) & 1) << p for p in range(3))
+        out.append(leaf * 512 + k * 64 + j * 8 + i)
+    return np.array(out)
+
+
+def _sample_groups(ng, counts, n=48, seed=0):
+    """random groups plus the most expensive ones (longest lists, deepest walks)"""
+    rng = np.random.default_rng(seed)
+    heavy = np.argsort(counts[:, 0] * 35 + counts[:, 1] * 88)[-8:]
+    return np.unique(np.concatenate([rng.choice(ng, n, replace=False), heavy]))
+
+
+@pytest.fixture(scope="module")
+def core():
+    g = cloud_core()
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    t = OracleTree(g)
+    t.moments()
+    yield g, bh, rho, t
+    bh.close()
+
+
+@pytest.mark.parametrize("precision", [B.BH_FP32, B.BH_FP64])
+def test_cloud_core_sampled_groups(core, precision):
+    g, bh, rho, t = core
+    ng = bh.info["n_groups"]
+    assert g.ncells > 10_000_000 and g.max_level() == 7
+    phi = torch.empty_like(rho)
+    counts = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, None, precision, 1.0, phi, counts)
+    bh.check()
+    c = counts.cpu().numpy()
+    groups = _sample_groups(ng, c)
+    ref, oc = t.solve_groups(groups, theta=0.5, tau=TAU[precision])
+    got = phi.reshape(-1).cpu().numpy()[_morton_cells(groups)]
+    clean = oc[:, 3] == 0
+    assert clean.sum() >= len(groups) - 3
+    assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert np.max(rel[clean]) <= TOL[precision]
+
+
+def test_cloud_core_direct_and_method_error(core):
+    g, bh, rho, t = core
+    bh.build_moments(rho)
+    rng = np.random.default_rng(1)
+    tg = np.sort(rng.choice(g.ncells, 200, replace=False)).astype(np.int64)
+    d = bh.direct(torch.tensor(tg, device="cuda")).cpu().numpy()
+    assert np.max(np.abs(d - t.direct(tg)) / np.abs(d)) <= 1e-12
+    phi = torch.empty_like(rho)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, None, B.BH_FP32, 1.0, phi, None)
+    err = LT.sampled_rms(bh, phi, frac=0.001, seed=3)
+    assert err <= 1e-3
+    # fp32 and fp64 paths agree everywhere (same decisions up to marginal groups)
+    phi64 = torch.empty_like(rho)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, None, B.BH_FP64, 1.0, phi64, None)
+    rel = ((phi - phi64) / phi64).abs()
+    assert float(torch.quantile(rel.reshape(-1)[::97].float(), 0.999)) <= 1e-5
+
+
+def test_benchmark_mesh_in_bench_configuration():
+    g = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    t = OracleTree(g)
+    # fixed theta 1.0, fp32, fused path: sampled groups vs the oracle
+    phi = torch.empty_like(rho)
+    counts = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 1.0, None, B.BH_FP32, 1.0, phi, counts)
+    c = counts.cpu().numpy()
+    groups = _sample_groups(ng, c, seed=2)
+    ref, oc = t.solve_groups(groups, theta=1.0, tau=TAU[B.BH_FP32])
+    got = phi.reshape(-1).cpu().numpy()[_morton_cells(groups)]
+    clean = oc[:, 3] == 0
+    assert clean.sum() >= len(groups) - 3
+    assert np.max(np.abs(got - ref)[clean] / np.abs(ref)[clean]) <= 1e-5
+    # learned theta as bench.py runs it: RMS gate against the exact direct sum
+    net = LT.ThetaNet.load(bh.ctx, os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz"))
+    feat = torch.empty((ng, 12), dtype=torch.float32, device="cuda")
+    theta = torch.empty(ng, dtype=torch.float32, device="cuda")
+    LT.solve_learned(bh, rho, net, phi, feat, theta)
+    direct = LT.direct_potential(bh, rho)
+    rel = ((phi - direct) / direct).reshape(-1)
+    assert float(torch.sqrt((rel * rel).mean())) <= 1e-3
+    net.close()
+    bh.close()

@@ -186,3 +186,20 @@ def test_error_grows_with_theta_percent_level_at_one():
     assert 1e-3 < mono[-1] < 3e-2
     # the quadrupole improves every theta
     assert all(q < mo for q, mo in zip(quad, mono))
+
+
+def test_group_subset_solve_equals_full_solve():
+    g = random_amr(21, nbase=2, max_level=3, zero_fraction=0.1)
+    t = OracleTree(g)
+    w = t.walk(64, 0.6)
+    phi = t.potential().reshape(-1)
+    gs = np.array([0, 5, 17, 100, t.n_groups(64) - 1])
+    ps, cs = t.solve_groups(gs, theta=0.6)
+    for q, gi in enumerate(gs):
+        leaf, sub = divmod(int(gi), 8)
+        mm = sub * 64 + np.arange(64)
+        i = sum(((mm >> (3 * p)) & 1) << p for p in range(3))
+        j = sum(((mm >> (3 * p + 1)) & 1) << p for p in range(3))
+        k = sum(((mm >> (3 * p + 2)) & 1) << p for p in range(3))
+        assert np.array_equal(ps[q], phi[leaf * 512 + k * 64 + j * 8 + i])
+        assert cs[q, 1] == w["n_far"][gi] and cs[q, 2] == w["n_near"][gi] and cs[q, 0] == w["visited"][gi]
