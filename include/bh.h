@@ -58,6 +58,7 @@ typedef struct bh_grid bh_grid;
 typedef struct bh_moments bh_moments;
 typedef struct bh_lists bh_lists;
 typedef struct bh_mlp bh_mlp;
+typedef struct bh_batch bh_batch;
 
 /* ---------------------------------------------------------------- context */
 
@@ -191,6 +192,45 @@ int bh_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, dou
  * (n_targets < 0), BH_ESTATE. */
 int bh_direct(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const int64_t *targets_dev,
               int64_t n_targets, double G, double *phi_dev);
+
+/* ---------------------------------------------------------------- batches
+ *
+ * Many independent grids solved together: the moments of every grid, then ONE
+ * persistent launch of the fused walk + sums in which each wavefront takes the
+ * next (grid, group) work item from an atomic queue until all are done.  The
+ * method per group is exactly bh_walk_potential's (same tiles, same order, the
+ * same bits).  A batch owns its own moments; all grids must belong to ctx. */
+#define BH_ORDER_NATURAL 0 /* grid by grid, groups in Morton order */
+#define BH_ORDER_COST 1    /* most expensive groups first (counts of the last solve) */
+
+int bh_batch_create(bh_ctx *ctx, bh_batch **batch, int n_grids, bh_grid *const *grids);
+int bh_batch_destroy(bh_batch *batch);
+int bh_batch_info(const bh_batch *batch, int *n_grids, int64_t *n_groups);
+/* rho_dev[k] / phi_dev[k]: device pointers of grid k (caller layout); host arrays
+ * of n_grids pointers.  theta_group_dev: NULL or a host array whose entries are
+ * NULL (use theta) or device fp32 [n_groups_k].  Asynchronous; device-side
+ * conditions are reported by bh_batch_check. */
+int bh_batch_solve(bh_ctx *ctx, bh_batch *batch, const double *const *rho_dev, double *const *phi_dev, double theta,
+                   const float *const *theta_group_dev, int precision, double G);
+/* Record the same solve as a graph (nothing runs yet); bh_batch_replay launches
+ * it on the context's stream.  The graph keeps the buffers and parameters given
+ * here; the moments' flags are cleared by a kernel inside the graph, not by a
+ * memset, so replays are independent. */
+int bh_batch_capture(bh_ctx *ctx, bh_batch *batch, const double *const *rho_dev, double *const *phi_dev,
+                     double theta, const float *const *theta_group_dev, int precision, double G);
+int bh_batch_replay(bh_ctx *ctx, bh_batch *batch);
+/* Synchronise; BH_EINVAL (invalid density) or BH_ECAPACITY (stack) for the first
+ * grid that reported one in the last solve or replay. */
+int bh_batch_check(bh_ctx *ctx, const bh_batch *batch);
+/* Synchronising host copy of the per-group far / near counts of the last solve:
+ * counts[n_groups_total][2], grid by grid, canonical group order within a grid. */
+int bh_batch_counts(bh_ctx *ctx, const bh_batch *batch, int32_t *counts);
+/* Queue order for later solves (BH_ORDER_NATURAL or BH_ORDER_COST); drops a
+ * captured graph. */
+int bh_batch_schedule(bh_ctx *ctx, bh_batch *batch, int mode);
+/* Persistent workgroups per compute unit (0 = the kernel's resident waves per
+ * SIMD); a tuning knob, drops a captured graph. */
+int bh_batch_set_launch(bh_ctx *ctx, bh_batch *batch, int workgroups_per_cu);
 
 /* ---------------------------------------------------------------- learned theta
  *

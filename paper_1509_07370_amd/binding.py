@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbh.so")
+# BH_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("BH_LIBRARY") or os.path.join(HERE, "libbh.so")
 
 BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_ECAPACITY, BH_ESTATE = 0, -1, -2, -3, -4, -5
 BH_FP64, BH_FP32 = 0, 1
@@ -57,6 +58,16 @@ _SIGS = {
     "bh_potential": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
     "bh_walk_potential": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P]),
     "bh_direct": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
+    "bh_batch_create": (ctypes.c_int, [P, PP, ctypes.c_int, P]),
+    "bh_batch_destroy": (ctypes.c_int, [P]),
+    "bh_batch_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64)]),
+    "bh_batch_solve": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64]),
+    "bh_batch_capture": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64]),
+    "bh_batch_replay": (ctypes.c_int, [P, P]),
+    "bh_batch_check": (ctypes.c_int, [P, P]),
+    "bh_batch_counts": (ctypes.c_int, [P, P, P]),
+    "bh_batch_schedule": (ctypes.c_int, [P, P, ctypes.c_int]),
+    "bh_batch_set_launch": (ctypes.c_int, [P, P, ctypes.c_int]),
     "bh_group_features": (ctypes.c_int, [P, P, P, P]),
     "bh_group_rms_error": (ctypes.c_int, [P, P, P, P, P]),
     "bh_mlp_create": (ctypes.c_int, [P, PP, P, P, P]),
@@ -69,6 +80,7 @@ _SIGS = {
     "bh_mlp_destroy": (ctypes.c_int, [P]),
 }
 MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
+BH_ORDER_NATURAL, BH_ORDER_COST = 0, 1
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
@@ -311,3 +323,69 @@ def bh_mlp_adam_step(ctx, net, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 def bh_mlp_destroy(net):
     _lib.bh_mlp_destroy(net)
+
+
+# ------------------------------------------------------------------ batches
+
+def _ptr_array(tensors, dtype_name, allow_none=False):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for k, t in enumerate(tensors):
+        arr[k] = None if (t is None and allow_none) else _dev(t, dtype_name).value
+    return arr
+
+
+def bh_batch_create(ctx, grids):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * len(grids))(*[g.value for g in grids])
+    _check(_lib.bh_batch_create(ctx, ctypes.byref(h), len(grids), arr), ctx)
+    return h
+
+
+def bh_batch_destroy(batch):
+    _lib.bh_batch_destroy(batch)
+
+
+def bh_batch_info(batch):
+    n, t = ctypes.c_int(), i64()
+    _check(_lib.bh_batch_info(batch, ctypes.byref(n), ctypes.byref(t)), None)
+    return n.value, t.value
+
+
+def _batch_args(rho, phi, theta_group):
+    r = _ptr_array(rho, "float64")
+    p = _ptr_array(phi, "float64")
+    tg = _ptr_array(theta_group, "float32", allow_none=True) if theta_group is not None else None
+    return r, p, tg
+
+
+def bh_batch_solve(ctx, batch, rho, phi, theta=0.5, theta_group=None, precision=BH_FP32, G=1.0):
+    r, p, tg = _batch_args(rho, phi, theta_group)
+    _check(_lib.bh_batch_solve(ctx, batch, r, p, float(theta), tg, int(precision), float(G)), ctx)
+
+
+def bh_batch_capture(ctx, batch, rho, phi, theta=0.5, theta_group=None, precision=BH_FP32, G=1.0):
+    r, p, tg = _batch_args(rho, phi, theta_group)
+    _check(_lib.bh_batch_capture(ctx, batch, r, p, float(theta), tg, int(precision), float(G)), ctx)
+
+
+def bh_batch_replay(ctx, batch):
+    _check(_lib.bh_batch_replay(ctx, batch), ctx)
+
+
+def bh_batch_check(ctx, batch):
+    _check(_lib.bh_batch_check(ctx, batch), ctx)
+
+
+def bh_batch_counts(ctx, batch):
+    _, total = bh_batch_info(batch)
+    c = np.empty((total, 2), np.int32)
+    _check(_lib.bh_batch_counts(ctx, batch, _ptr(c)), ctx)
+    return c
+
+
+def bh_batch_schedule(ctx, batch, mode):
+    _check(_lib.bh_batch_schedule(ctx, batch, int(mode)), ctx)
+
+
+def bh_batch_set_launch(ctx, batch, workgroups_per_cu):
+    _check(_lib.bh_batch_set_launch(ctx, batch, int(workgroups_per_cu)), ctx)

@@ -1,0 +1,309 @@
+// C ABI of the batched path: many grids, one persistent fused launch, optional
+// graph capture.  Argument checking, ownership and launch order only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "bh_internal.h"
+
+struct bh_batch {
+    bh_ctx *ctx = nullptr;
+    std::vector<const bh_grid *> grids;
+    std::vector<bh_moments *> moments;
+    std::vector<int64_t> group_base;      // first queue slot of each grid, size n + 1
+    int64_t total = 0;
+    bh::WalkArgs *h_desc = nullptr;       // pinned
+    bh::WalkArgs *d_desc = nullptr;
+    int2 *d_order = nullptr;              // [total] (grid, internal group)
+    int32_t *d_counts = nullptr;          // [total][2], per grid in canonical group order
+    unsigned long long *d_counter = nullptr;
+    int cus = 0;
+    int workgroups_per_cu = 0;            // 0: one per resident slot
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int precision = BH_FP32;
+};
+
+namespace {
+
+int fail(bh_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_fail(bh_ctx *ctx, hipError_t e, const char *what) {
+    return fail(ctx, e == hipErrorOutOfMemory ? BH_ENOMEM : BH_EDEVICE,
+                std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+#define HIPX(ctx, expr, what)                                 \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+    } while (0)
+
+int require_gpu(bh_ctx *ctx) {
+    if (!ctx) return BH_EINVAL;
+    if (ctx->device < 0) return fail(ctx, BH_ESTATE, "host-only context: no GPU work possible");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    return BH_OK;
+}
+
+void drop_graph(bh_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+int upload_order(bh_ctx *ctx, bh_batch *b, const std::vector<int2> &order) {
+    HIPX(ctx, hipMemcpy(b->d_order, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice), "order");
+    return BH_OK;
+}
+
+// moments of every grid, then the persistent fused launch, all on stream s
+int enqueue_solve(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const *phi, double theta,
+                  const float *const *theta_group, int precision, double G, hipStream_t s) {
+    const int n = (int)b->grids.size();
+    for (int k = 0; k < n; k++) {
+        const bh_grid *g = b->grids[k];
+        const float *tg = theta_group ? theta_group[k] : nullptr;
+        b->h_desc[k] = bh::fused_args(g, b->moments[k], theta, tg, precision, G, phi[k],
+                                      b->d_counts + 2 * b->group_base[k], 1);
+    }
+    HIPX(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(bh::WalkArgs), hipMemcpyHostToDevice, s),
+         "upload of the batch descriptors");
+    HIPX(ctx, bh::launch_batch_reset(b->d_desc, n, b->d_counter, s), "batch reset kernel");
+    for (int k = 0; k < n; k++)
+        HIPX(ctx, bh::launch_moments(b->grids[k], b->moments[k], rho[k], s, 1), "moments kernels");
+    int per_cu = b->workgroups_per_cu > 0 ? b->workgroups_per_cu : bh::fused_waves_per_simd(precision);
+    int64_t wgs = (int64_t)b->cus * per_cu;
+    const int64_t need = (b->total + 3) / 4;
+    if (wgs > need) wgs = need;
+    if (wgs < 1) wgs = 1;
+    HIPX(ctx, bh::launch_batch_walk_potential(b->d_desc, b->d_order, b->total, b->d_counter, precision, (int)wgs, s),
+         "batch walk + potential kernel");
+    return BH_OK;
+}
+
+int check_args(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const *phi, double theta,
+               const float *const *theta_group, int precision, double G) {
+    if (!b || !rho || !phi) return fail(ctx, BH_EINVAL, "batch, rho or phi array is NULL");
+    if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    for (size_t k = 0; k < b->grids.size(); k++) {
+        if (!rho[k] || !phi[k]) return fail(ctx, BH_EINVAL, "a rho_dev or phi_dev entry is NULL");
+        const bool has_tg = theta_group && theta_group[k];
+        if (!has_tg && !(theta > 0.0 && theta <= 1.0)) return fail(ctx, BH_EINVAL, "theta must be in (0, 1]");
+    }
+    return BH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bh_batch_destroy(bh_batch *b) {
+    if (!b) return BH_OK;
+    if (b->ctx && b->ctx->device >= 0) (void)hipSetDevice(b->ctx->device);
+    drop_graph(b);
+    for (auto *m : b->moments) bh_moments_destroy(m);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_counts) (void)hipFree(b->d_counts);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return BH_OK;
+}
+
+int bh_batch_create(bh_ctx *ctx, bh_batch **out, int n, bh_grid *const *grids) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!out || !grids || n <= 0) return fail(ctx, BH_EINVAL, "batch needs at least one grid");
+    *out = nullptr;
+    bh_batch *b = new (std::nothrow) bh_batch();
+    if (!b) return fail(ctx, BH_ENOMEM, "host allocation of the batch");
+    b->ctx = ctx;
+    b->group_base.assign(1, 0);
+    for (int k = 0; k < n; k++) {
+        if (!grids[k] || grids[k]->ctx != ctx) {
+            bh_batch_destroy(b);
+            return fail(ctx, BH_EINVAL, "a grid is NULL or belongs to another context");
+        }
+        b->grids.push_back(grids[k]);
+        b->group_base.push_back(b->group_base.back() + grids[k]->n_groups);
+    }
+    b->total = b->group_base.back();
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
+    if (e != hipSuccess) {
+        bh_batch_destroy(b);
+        return hip_fail(ctx, e, "hipGetDeviceProperties");
+    }
+    b->cus = prop.multiProcessorCount;
+    if ((e = hipHostMalloc((void **)&b->h_desc, n * sizeof(bh::WalkArgs), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_desc, n * sizeof(bh::WalkArgs))) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_order, b->total * sizeof(int2))) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_counts, 2 * b->total * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        bh_batch_destroy(b);
+        return hip_fail(ctx, e, "allocation of the batch");
+    }
+    for (int k = 0; k < n; k++) {
+        bh_moments *m = new (std::nothrow) bh_moments();  // batch-owned moments of grid k
+        if (!m) {
+            bh_batch_destroy(b);
+            return fail(ctx, BH_ENOMEM, "host allocation of the moments");
+        }
+        m->grid = grids[k];
+        b->moments.push_back(m);
+        const int64_t nn = grids[k]->topo.n_nodes, nc = grids[k]->n_cells;
+        if ((e = hipMalloc((void **)&m->d_mom, nn * bh::kMom * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void **)&m->d_w32, nn * sizeof(bh::WalkRec32))) != hipSuccess ||
+            (e = hipMalloc((void **)&m->d_w64, nn * sizeof(bh::WalkRec64))) != hipSuccess ||
+            (e = hipMalloc((void **)&m->d_f32, nn * sizeof(bh::FarRec32))) != hipSuccess ||
+            (e = hipMalloc((void **)&m->d_cell64, nc * sizeof(double4))) != hipSuccess ||
+            (e = hipMalloc((void **)&m->d_cell32, nc * sizeof(float4))) != hipSuccess ||
+            (e = hipMalloc((void **)&m->d_flags, 2 * sizeof(int))) != hipSuccess ||
+            (e = hipMemset(m->d_flags, 0, 2 * sizeof(int))) != hipSuccess) {
+            bh_batch_destroy(b);
+            return hip_fail(ctx, e, "allocation of the batch moments");
+        }
+    }
+    std::vector<int2> order(b->total);
+    for (int k = 0; k < n; k++)
+        for (int64_t q = 0; q < grids[k]->n_groups; q++) order[b->group_base[k] + q] = make_int2(k, (int)q);
+    rc = upload_order(ctx, b, order);
+    if (rc) {
+        bh_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return BH_OK;
+}
+
+int bh_batch_info(const bh_batch *b, int *n_grids, int64_t *n_groups) {
+    if (!b) return BH_EINVAL;
+    if (n_grids) *n_grids = (int)b->grids.size();
+    if (n_groups) *n_groups = b->total;
+    return BH_OK;
+}
+
+int bh_batch_set_launch(bh_ctx *ctx, bh_batch *b, int workgroups_per_cu) {
+    if (!ctx || !b) return BH_EINVAL;
+    if (workgroups_per_cu < 0 || workgroups_per_cu > 64) return fail(ctx, BH_EINVAL, "workgroups_per_cu out of range");
+    b->workgroups_per_cu = workgroups_per_cu;
+    drop_graph(b);
+    return BH_OK;
+}
+
+int bh_batch_solve(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const *phi, double theta,
+                   const float *const *theta_group, int precision, double G) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if ((rc = check_args(ctx, b, rho, phi, theta, theta_group, precision, G))) return rc;
+    b->precision = precision;
+    return enqueue_solve(ctx, b, rho, phi, theta, theta_group, precision, G, ctx->stream);
+}
+
+int bh_batch_capture(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const *phi, double theta,
+                     const float *const *theta_group, int precision, double G) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if ((rc = check_args(ctx, b, rho, phi, theta, theta_group, precision, G))) return rc;
+    drop_graph(b);
+    b->precision = precision;
+    HIPX(ctx, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    rc = enqueue_solve(ctx, b, rho, phi, theta, theta_group, precision, G, b->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "end capture");
+    b->graph = graph;
+    HIPX(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiation");
+    return BH_OK;
+}
+
+int bh_batch_replay(bh_ctx *ctx, bh_batch *b) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!b || !b->exec) return fail(ctx, BH_ESTATE, "no captured graph (call bh_batch_capture first)");
+    HIPX(ctx, hipGraphLaunch(b->exec, ctx->stream), "graph launch");
+    return BH_OK;
+}
+
+int bh_batch_check(bh_ctx *ctx, const bh_batch *b) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!b) return fail(ctx, BH_EINVAL, "batch is NULL");
+    std::vector<int> flags(2 * b->grids.size());
+    for (size_t k = 0; k < b->grids.size(); k++)
+        HIPX(ctx, hipMemcpyAsync(&flags[2 * k], b->moments[k]->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                 ctx->stream), "copy flags");
+    HIPX(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    for (size_t k = 0; k < b->grids.size(); k++) {
+        if (flags[2 * k]) return fail(ctx, BH_EINVAL, "grid " + std::to_string(k) + ": densities must be finite and >= 0");
+        if (flags[2 * k + 1]) return fail(ctx, BH_ECAPACITY, "grid " + std::to_string(k) + ": walk stack overflow");
+    }
+    return BH_OK;
+}
+
+int bh_batch_counts(bh_ctx *ctx, const bh_batch *b, int32_t *counts) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!b || !counts) return fail(ctx, BH_EINVAL, "batch or counts is NULL");
+    HIPX(ctx, hipMemcpyAsync(counts, b->d_counts, 2 * b->total * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream),
+         "copy counts");
+    HIPX(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    return BH_OK;
+}
+
+int bh_batch_schedule(bh_ctx *ctx, bh_batch *b, int mode) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!b) return fail(ctx, BH_EINVAL, "batch is NULL");
+    if (mode != BH_ORDER_NATURAL && mode != BH_ORDER_COST) return fail(ctx, BH_EINVAL, "unknown schedule mode");
+    const int n = (int)b->grids.size();
+    std::vector<int2> order(b->total);
+    for (int k = 0; k < n; k++)
+        for (int64_t q = 0; q < b->grids[k]->n_groups; q++) order[b->group_base[k] + q] = make_int2(k, (int)q);
+    if (mode == BH_ORDER_COST) {
+        std::vector<int32_t> c(2 * b->total);
+        rc = bh_batch_counts(ctx, b, c.data());
+        if (rc) return rc;
+        // counts are stored per grid in canonical group order; queue items name internal groups
+        std::vector<double> cost(b->total);
+        for (int k = 0; k < n; k++) {
+            const bh_grid *g = b->grids[k];
+            const int per = bh::kCellsPerBlock / g->group_cells;
+            for (int64_t q = 0; q < g->n_groups; q++) {
+                const int64_t cg = (int64_t)g->topo.leaves[q / per].canon * per + q % per;
+                const int64_t i = b->group_base[k] + cg;
+                cost[b->group_base[k] + q] = 35.0 * 64 * c[2 * i] + 11.0 * (512.0 * c[2 * i + 1] - 64);
+            }
+        }
+        std::vector<int64_t> idx(b->total);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+        std::vector<int2> sorted(b->total);
+        for (int64_t i = 0; i < b->total; i++) sorted[i] = order[idx[i]];
+        order.swap(sorted);
+    }
+    drop_graph(b);
+    return upload_order(ctx, b, order);
+}
+
+}  // extern "C"

@@ -57,6 +57,31 @@ struct alignas(16) LeafInfo {
     int bot_first;    // node id of bottom node 0 (64 consecutive, Morton order)
 };
 
+// Arguments of one grid's walk (and of its fused walk + sums); also the
+// per-grid record of a batch, read by the persistent batch kernel.
+struct WalkArgs {
+    const void *nodes;
+    const LeafInfo *leaves;
+    const float *theta_group;
+    double theta;
+    int64_t n_groups;
+    int root;
+    int k8_threshold;
+    int epoch;
+    int *flags;  // flags[1] <- epoch on stack overflow
+    // list mode
+    int32_t *far_cnt, *near_cnt;
+    const int64_t *far_off, *near_off;
+    int32_t *far_out, *near_out;
+    // fused mode
+    const void *far_rec;
+    const int32_t *child;
+    const void *cells;
+    double G;
+    double *phi;
+    int32_t *counts;
+};
+
 // Host-side octree topology built from the block list.
 struct Topology {
     int nbase = 0, vlev = 0, nblocks = 0, n_levels = 0, max_depth = 0, root = 0;
@@ -134,7 +159,14 @@ struct bh_lists {
 
 namespace bh {
 // kernel launchers (bh_kernels.hip); all enqueue on `s`.
-hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s);
+// epoch > 0: stamp invalid densities with that value instead of a new epoch
+hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int epoch = 0);
+WalkArgs fused_args(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group, int precision,
+                    double G, double *phi, int32_t *counts, int epoch);
+hipError_t launch_batch_reset(const WalkArgs *grids, int n, unsigned long long *counter, hipStream_t s);
+hipError_t launch_batch_walk_potential(const WalkArgs *grids, const int2 *order, int64_t total,
+                                       unsigned long long *counter, int precision, int workgroups, hipStream_t s);
+int fused_waves_per_simd(int precision);
 hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
                        int precision, bool fill, hipStream_t s);
 hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipStream_t s);

@@ -253,10 +253,10 @@ __global__ __launch_bounds__(1024) void moments_levels_kernel(const int32_t *__r
 
 constexpr int64_t kSingleWorkgroupCombine = 16384;
 
-hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s) {
+hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int fixed_epoch) {
     MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32};
     const int nleaf = (int)g->topo.leaves.size();
-    const int epoch = ++m->mom_epoch;
+    const int epoch = fixed_epoch > 0 ? fixed_epoch : ++m->mom_epoch;
     hipLaunchKernelGGL(moments_leaf_kernel, dim3(nleaf), dim3(512), 0, s, rho, g->d_leaves, g->d_geom, g->d_child, o,
                        m->d_cell64, m->d_cell32, m->d_flags, epoch);
     hipError_t e = hipGetLastError();
@@ -312,28 +312,6 @@ __device__ __forceinline__ real nearest_gap(real x0, real h, real X, int n) {
     return d1 < d2 ? d1 : d2;
 }
 
-struct WalkArgs {
-    const void *nodes;
-    const LeafInfo *leaves;
-    const float *theta_group;
-    double theta;
-    int64_t n_groups;
-    int root;
-    int k8_threshold;
-    int epoch;
-    int *flags;  // flags[1] <- epoch on stack overflow
-    // list mode
-    int32_t *far_cnt, *near_cnt;
-    const int64_t *far_off, *near_off;
-    int32_t *far_out, *near_out;
-    // fused mode
-    const void *far_rec;
-    const int32_t *child;
-    const void *cells;
-    double G;
-    double *phi;
-    int32_t *counts;
-};
 
 // Group walk state of one wavefront.  The group vote of the potential kernel
 // (all lanes accept) needs, per node, the minimum over the group's cells of
@@ -835,24 +813,38 @@ hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_list
 // Walk and sum in one pass, without materialising the lists: accepted nodes
 // and near bottom nodes are buffered in LDS in walk order and summed as soon
 // as a full tile (64 far nodes / 8 bottom nodes) is available, so the tiles
-// are exactly those the list path forms, in the same order.
+// are exactly those the list path forms, in the same order.  A full far tile
+// is software-pipelined: its node records are loaded into registers before
+// the next walk step, whose own node loads then cover that latency, and are
+// summed after it.  Launch bounds set the waves per SIMD (and so the register
+// budget) that hide the walk's remaining load latency best.
+#ifndef BH_FUSED_WAVES_FP32
+#define BH_FUSED_WAVES_FP32 6
+#endif
 template <typename real>
-__global__ __launch_bounds__(256) void walk_potential_kernel(WalkArgs a) {
+struct FusedWaves {
+    static constexpr int value = sizeof(real) == 4 ? BH_FUSED_WAVES_FP32 : 4;
+};
+
+template <typename real>
+struct FusedSmem {
     using V4 = typename Prec<real>::V4;
-    __shared__ int stack[4][kWalkStackCap];
-    __shared__ int fbuf[4][128];
-    __shared__ int nbuf[4][72];
-    __shared__ V4 tile[4][64 * 3];
-    const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
+    int stack[4][kWalkStackCap];
+    int fbuf[4][128];
+    int nbuf[4][72];
+    V4 tile[4][64 * 3];
+};
+
+// one group g of the grid described by a, on wavefront w of the workgroup
+template <typename real>
+__device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w, int lane, FusedSmem<real> &sm) {
+    using V4 = typename Prec<real>::V4;
     const int f = (int)(g >> 3), sub = (int)(g & 7);
     const LeafInfo L = a.leaves[f];
     Walker<real> W;
-    W.init(a, L, sub, stack[w], lane);
+    W.init(a, L, sub, sm.stack[w], lane);
     Tiles<real> S;
-    S.T = tile[w];
+    S.T = sm.tile[w];
     S.rec = (const V4 *)a.far_rec;
     S.cells = (const V4 *)a.cells;
     S.child = a.child;
@@ -860,13 +852,23 @@ __global__ __launch_bounds__(256) void walk_potential_kernel(WalkArgs a) {
     S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
     S.acc_far = 0.0;
     S.acc_near = 0.0;
-    int *FB = fbuf[w];
-    int *NB = nbuf[w];
+    int *FB = sm.fbuf[w];
+    int *NB = sm.nbuf[w];
     int fcnt = 0, ncnt = 0, ftot = 0, ntot = 0;
+    bool pending = false;  // a full far tile waits in p0..p2
+    V4 p0, p1, p2;
     while (W.size > 0) {
         int id;
         bool acc, nr;
         W.step(lane, id, acc, nr);
+        if (pending) {  // loaded before the step: sum it now
+            S.T[3 * lane + 0] = p0;
+            S.T[3 * lane + 1] = p1;
+            S.T[3 * lane + 2] = p2;
+            wave_lds_sync();
+            S.sum_far(64);
+            pending = false;
+        }
         const uint64_t mf = __ballot(acc);
         const uint64_t mn = __ballot(nr);
         if (acc) FB[fcnt + lane_prefix(mf)] = id;
@@ -876,9 +878,12 @@ __global__ __launch_bounds__(256) void walk_potential_kernel(WalkArgs a) {
         ftot += __popcll(mf);
         ntot += __popcll(mn);
         wave_lds_sync();
-        if (fcnt >= 64) {
-            S.stage_far(lane, 64, FB[lane]);
-            S.sum_far(64);
+        if (fcnt >= 64) {  // issue the loads of the next full tile; summed after the next step
+            const int64_t rid = FB[lane];
+            p0 = S.rec[3 * rid + 0];
+            p1 = S.rec[3 * rid + 1];
+            p2 = S.rec[3 * rid + 2];
+            pending = true;
             const int rest = fcnt - 64;
             int v = lane < rest ? FB[64 + lane] : 0;
             wave_lds_sync();
@@ -897,6 +902,23 @@ __global__ __launch_bounds__(256) void walk_potential_kernel(WalkArgs a) {
         }
     }
     W.finish(a, lane);
+    if (pending) {
+        S.T[3 * lane + 0] = p0;
+        S.T[3 * lane + 1] = p1;
+        S.T[3 * lane + 2] = p2;
+        wave_lds_sync();
+        S.sum_far(64);
+    }
+    if (fcnt >= 64) {  // at most one more full tile can remain
+        S.stage_far(lane, 64, FB[lane]);
+        S.sum_far(64);
+        const int rest = fcnt - 64;
+        int v = lane < rest ? FB[64 + lane] : 0;
+        wave_lds_sync();
+        if (lane < rest) FB[lane] = v;
+        fcnt = rest;
+        wave_lds_sync();
+    }
     if (fcnt > 0) {
         S.stage_far(lane, fcnt, lane < fcnt ? FB[lane] : 0);
         S.sum_far(fcnt);
@@ -910,14 +932,52 @@ __global__ __launch_bounds__(256) void walk_potential_kernel(WalkArgs a) {
     }
 }
 
+template <typename real>
+__global__ __launch_bounds__(256, FusedWaves<real>::value) void walk_potential_kernel(WalkArgs a) {
+    __shared__ FusedSmem<real> sm;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    fused_group<real>(a, g, w, lane, sm);
+}
+
+// Many grids in one persistent launch: every wavefront takes the next
+// (grid, group) item of `order` from an atomic counter until the queue is
+// empty, so uneven grids and groups balance themselves; with `order` sorted
+// by decreasing cost the longest groups start first.  Every wave exits once
+// the counter passes `total`.
+template <typename real>
+__global__ __launch_bounds__(256, FusedWaves<real>::value) void batch_walk_potential_kernel(
+    const WalkArgs *__restrict__ grids, const int2 *__restrict__ order, int64_t total,
+    unsigned long long *__restrict__ counter) {
+    __shared__ FusedSmem<real> sm;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    while (true) {
+        unsigned long long q = 0;
+        if (lane == 0) q = atomicAdd(counter, 1ull);
+        q = __shfl(q, 0, 64);
+        if (q >= (unsigned long long)total) break;
+        const int2 item = order[q];
+        fused_group<real>(grids[item.x], item.y, w, lane, sm);
+    }
+}
+
+// Clears the queue counter and the device flags of every grid in a batch
+// (a kernel rather than a memset, so that the sequence can be captured).
+__global__ void batch_reset_kernel(const WalkArgs *__restrict__ grids, int n, unsigned long long *counter) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0ull;
+    if (i < n) {
+        grids[i].flags[0] = 0;
+        grids[i].flags[1] = 0;
+    }
+}
+
 hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                                  int precision, double G, double *phi, int32_t *counts, hipStream_t s) {
-    WalkArgs a = walk_args(g, m, theta, theta_group, precision, m->walk_epoch);
-    a.far_rec = precision == BH_FP64 ? (const void *)m->d_mom : (const void *)m->d_f32;
-    a.cells = precision == BH_FP64 ? (const void *)m->d_cell64 : (const void *)m->d_cell32;
-    a.G = G;
-    a.phi = phi;
-    a.counts = counts;
+    WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     const int blocks = (int)((g->n_groups + 3) / 4);
     if (precision == BH_FP64)
         hipLaunchKernelGGL(walk_potential_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
@@ -925,6 +985,35 @@ hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double t
         hipLaunchKernelGGL(walk_potential_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
+
+WalkArgs fused_args(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group, int precision,
+                    double G, double *phi, int32_t *counts, int epoch) {
+    WalkArgs a = walk_args(g, m, theta, theta_group, precision, epoch);
+    a.far_rec = precision == BH_FP64 ? (const void *)m->d_mom : (const void *)m->d_f32;
+    a.cells = precision == BH_FP64 ? (const void *)m->d_cell64 : (const void *)m->d_cell32;
+    a.G = G;
+    a.phi = phi;
+    a.counts = counts;
+    return a;
+}
+
+hipError_t launch_batch_reset(const WalkArgs *grids, int n, unsigned long long *counter, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((n + 63) / 64), dim3(64), 0, s, grids, n, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_walk_potential(const WalkArgs *grids, const int2 *order, int64_t total,
+                                       unsigned long long *counter, int precision, int workgroups, hipStream_t s) {
+    if (precision == BH_FP64)
+        hipLaunchKernelGGL(batch_walk_potential_kernel<double>, dim3(workgroups), dim3(256), 0, s, grids, order, total,
+                           counter);
+    else
+        hipLaunchKernelGGL(batch_walk_potential_kernel<float>, dim3(workgroups), dim3(256), 0, s, grids, order, total,
+                           counter);
+    return hipGetLastError();
+}
+
+int fused_waves_per_simd(int precision) { return precision == BH_FP64 ? 4 : BH_FUSED_WAVES_FP32; }
 
 // ---------------------------------------------------------------- direct
 
