@@ -42,6 +42,18 @@ def _morton_cells(groups):
     return np.array(out)
 
 
+def _check_groups(got, ref, oc, tol, max_marginal_mismatch=3):
+    """Groups without marginal decisions match to tol; a mismatching group must
+    hold a marginal decision (exact lattice ties, which both sides decide alike,
+    are flagged too, so most marginal groups match as well)."""
+    rel = (np.abs(got - ref) / np.abs(ref)).max(axis=1)
+    marginal = oc[:, 3] > 0
+    assert np.all(rel[~marginal] <= tol), rel[~marginal].max()
+    bad = rel > tol
+    assert np.all(marginal[bad])
+    assert bad.sum() <= max_marginal_mismatch
+
+
 def _sample_groups(ng, counts, n=48, seed=0):
     """random groups plus the most expensive ones (longest lists, deepest walks)"""
     rng = np.random.default_rng(seed)
@@ -75,10 +87,8 @@ def test_cloud_core_sampled_groups(core, precision):
     ref, oc = t.solve_groups(groups, theta=0.5, tau=TAU[precision])
     got = phi.reshape(-1).cpu().numpy()[_morton_cells(groups)]
     clean = oc[:, 3] == 0
-    assert clean.sum() >= len(groups) - 3
     assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
-    rel = np.abs(got - ref) / np.abs(ref)
-    assert np.max(rel[clean]) <= TOL[precision]
+    _check_groups(got, ref, oc, TOL[precision])
 
 
 def test_cloud_core_direct_and_method_error(core):
@@ -114,9 +124,7 @@ def test_benchmark_mesh_in_bench_configuration():
     groups = _sample_groups(ng, c, seed=2)
     ref, oc = t.solve_groups(groups, theta=1.0, tau=TAU[B.BH_FP32])
     got = phi.reshape(-1).cpu().numpy()[_morton_cells(groups)]
-    clean = oc[:, 3] == 0
-    assert clean.sum() >= len(groups) - 3
-    assert np.max(np.abs(got - ref)[clean] / np.abs(ref)[clean]) <= 1e-5
+    _check_groups(got, ref, oc, 1e-5)
     # learned theta as bench.py runs it: RMS gate against the exact direct sum
     net = LT.ThetaNet.load(bh.ctx, os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz"))
     feat = torch.empty((ng, 12), dtype=torch.float32, device="cuda")
