@@ -1,9 +1,9 @@
 """Full-size checks: the 12.4M-cell cloud core and the 1.4M-cell benchmark mesh.
 
 The oracle re-solves a seeded sample of groups one by one (its own walk and
-sums) and the exact direct sum at sampled cells; groups holding a decision the
-oracle flags as marginal are excluded from the element-wise comparison and
-counted.  Properties that hold at any size are checked on the whole grid.
+sums) and the exact direct sum at sampled cells; a group may differ from the
+oracle only if it holds a decision the oracle flags as marginal, and only a
+few may.  Properties that hold at any size are checked on the whole grid.
 """
 import os
 
