@@ -38,6 +38,9 @@
  *  O7 sum     - phi_i = -G [ sum_far (M/d + R^T Q R / (2 d^5))
  *                            + sum_{near cells j != i} m_j / |r_i - r_j| ],
  *               R = r_i - X_n, with Neumaier-compensated sums.
+ *  O8 accel   - g_i = -grad_i phi_i, the gradient of O7 term by term (an
+ *               extension: the paper's method yields the potential only;
+ *               forces are the item its section 3.1 writes back next to it).
  *
  * Tree shape: the box is the root (depth 0); log2(nbase) virtual levels lead
  * down to the level-0 blocks; an AMR block of level L sits at depth
@@ -661,4 +664,147 @@ void ot_cells(const otree *t, double *x, double *y, double *z, double *m) {
     memcpy(y, t->cy, sizeof(double) * (size_t)t->ncells);
     memcpy(z, t->cz, sizeof(double) * (size_t)t->ncells);
     memcpy(m, t->cm, sizeof(double) * (size_t)t->ncells);
+}
+
+/*
+ * O8 accelerations g = -grad phi (beyond the paper, whose method computes
+ * the potential only): the gradient of O7 taken term by term with respect to
+ * the target position r_i.  For a far node with R = r_i - X, d = |R|:
+ *   d/dr (M / d)                  = -M R / d^3
+ *   d/dr (R^T Q R / (2 d^5))      =  Q R / d^5 - (5/2) (R^T Q R) R / d^7
+ * so g_i += G [ Q R / d^5 - (M / d^3 + (5/2) R^T Q R / d^7) R ]  (order 2;
+ * order 0 keeps the monopole part), and for a near cell j != i
+ *   g_i -= G m_j (r_i - r_j) / |r_i - r_j|^3.
+ * Each component is a Neumaier sum; acc is [..][3].
+ */
+static void accel_group_to(const otree *t, int64_t g, int G, const int *far, int nfar, const int *near, int nnear,
+                           double Gc, int order, double *acc, int64_t *cells, int local) {
+    group_cells_of(t, g, G, cells);
+    for (int q = 0; q < G; q++) {
+        int64_t i = cells[q];
+        double xi = t->cx[i], yi = t->cy[i], zi = t->cz[i];
+        nsum ax = {0.0, 0.0}, ay = {0.0, 0.0}, az = {0.0, 0.0};
+        for (int f = 0; f < nfar; f++) {
+            const onode *a = &t->nodes[far[f]];
+            double rx = xi - a->X[0], ry = yi - a->X[1], rz = zi - a->X[2];
+            double d2 = rx * rx + ry * ry + rz * rz;
+            double d = sqrt(d2);
+            double d3 = d2 * d;
+            double cx = -a->M / d3 * rx, cy = -a->M / d3 * ry, cz = -a->M / d3 * rz;
+            if (order >= 2) {
+                /* Q R with Q in the order xx yy zz xy xz yz */
+                double qx = a->Q[0] * rx + a->Q[3] * ry + a->Q[4] * rz;
+                double qy = a->Q[3] * rx + a->Q[1] * ry + a->Q[5] * rz;
+                double qz = a->Q[4] * rx + a->Q[5] * ry + a->Q[2] * rz;
+                double rqr = rx * qx + ry * qy + rz * qz;
+                double d5 = d3 * d2, d7 = d5 * d2;
+                cx += qx / d5 - 2.5 * rqr / d7 * rx;
+                cy += qy / d5 - 2.5 * rqr / d7 * ry;
+                cz += qz / d5 - 2.5 * rqr / d7 * rz;
+            }
+            nadd(&ax, cx);
+            nadd(&ay, cy);
+            nadd(&az, cz);
+        }
+        for (int b = 0; b < nnear; b++) {
+            const onode *a = &t->nodes[near[b]];
+            for (int o = 0; o < 8; o++) {
+                int64_t j = a->cell[o];
+                if (j == i) continue;
+                double rx = xi - t->cx[j], ry = yi - t->cy[j], rz = zi - t->cz[j];
+                double d2 = rx * rx + ry * ry + rz * rz;
+                double w = t->cm[j] / (d2 * sqrt(d2));
+                nadd(&ax, -w * rx);
+                nadd(&ay, -w * ry);
+                nadd(&az, -w * rz);
+            }
+        }
+        int64_t o = local ? q : i;
+        acc[3 * o + 0] = Gc * nval(&ax);
+        acc[3 * o + 1] = Gc * nval(&ay);
+        acc[3 * o + 2] = Gc * nval(&az);
+    }
+}
+
+/* O8 with the lists of the last ot_walk; acc in caller layout [cell][3]. */
+void ot_accel(const otree *t, double Gc, int order, double *acc) {
+    int G = t->group_cells;
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)G);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t g = 0; g < t->ngroups; g++)
+            accel_group_to(t, g, G, t->far[g].v, t->far[g].n, t->near[g].v, t->near[g].n, Gc, order, acc, cells, 0);
+        free(cells);
+    }
+}
+
+/* O5, O6 and O8 for a subset of groups: counts as in ot_solve_groups,
+ * acc[(q * G + c) * 3 + k] for the group's c-th cell in Morton order. */
+void ot_solve_groups_accel(const otree *t, int group_cells, const double *theta_group, const int64_t *groups,
+                           int64_t n, double tau, double Gc, int order, int64_t *counts, double *acc) {
+    int G = group_cells;
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)G);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < n; q++) {
+            int64_t g = groups[q];
+            group_cells_of(t, g, G, cells);
+            ivec far = {0, 0, NULL}, near = {0, 0, NULL};
+            walkctx w;
+            w.t = t; w.cells = cells; w.G = G;
+            w.inv_theta = 1.0 / theta_group[g];
+            w.tau = tau;
+            w.far = &far; w.near = &near;
+            w.visited = 0; w.marginal = 0;
+            walk_node(&w, t->root);
+            counts[4 * q + 0] = w.visited;
+            counts[4 * q + 1] = far.n;
+            counts[4 * q + 2] = near.n;
+            counts[4 * q + 3] = w.marginal;
+            accel_group_to(t, g, G, far.v, far.n, near.v, near.n, Gc, order, acc + 3 * q * G, cells, 1);
+            free(far.v);
+            free(near.v);
+        }
+        free(cells);
+    }
+}
+
+/* Exact acceleration of the direct sum at selected cells: -G sum_{j != i}
+ * m_j (r_i - r_j) / |r_i - r_j|^3, acc[q][3]. */
+void ot_direct_accel(const otree *t, const int64_t *targets, int64_t ntargets, double Gc, double *acc) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t q = 0; q < ntargets; q++) {
+        int64_t i = targets[q];
+        double xi = t->cx[i], yi = t->cy[i], zi = t->cz[i];
+        nsum ax = {0.0, 0.0}, ay = {0.0, 0.0}, az = {0.0, 0.0};
+        for (int64_t j = 0; j < t->ncells; j++) {
+            if (j == i) continue;
+            double rx = xi - t->cx[j], ry = yi - t->cy[j], rz = zi - t->cz[j];
+            double d2 = rx * rx + ry * ry + rz * rz;
+            double w = t->cm[j] / (d2 * sqrt(d2));
+            nadd(&ax, -w * rx);
+            nadd(&ay, -w * ry);
+            nadd(&az, -w * rz);
+        }
+        acc[3 * q + 0] = Gc * nval(&ax);
+        acc[3 * q + 1] = Gc * nval(&ay);
+        acc[3 * q + 2] = Gc * nval(&az);
+    }
+}
+
+/* Direct-sum potential at arbitrary points p[q][3], leaving out cell
+ * exclude[q] (if >= 0): the reference for finite-difference checks. */
+void ot_direct_at(const otree *t, const double *p, const int64_t *exclude, int64_t n, double Gc, double *phi) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t q = 0; q < n; q++) {
+        nsum acc = {0.0, 0.0};
+        for (int64_t j = 0; j < t->ncells; j++) {
+            if (j == exclude[q]) continue;
+            double rx = p[3 * q] - t->cx[j], ry = p[3 * q + 1] - t->cy[j], rz = p[3 * q + 2] - t->cz[j];
+            nadd(&acc, t->cm[j] / sqrt(rx * rx + ry * ry + rz * rz));
+        }
+        phi[q] = -Gc * nval(&acc);
+    }
 }

@@ -75,6 +75,11 @@ def _load():
         lib.ot_solve_groups.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                         P, P]
         lib.ot_cells.argtypes = [P, P, P, P, P]
+        lib.ot_accel.argtypes = [P, ctypes.c_double, ctypes.c_int, P]
+        lib.ot_solve_groups_accel.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_int, P, P]
+        lib.ot_direct_accel.argtypes = [P, P, i64, ctypes.c_double, P]
+        lib.ot_direct_at.argtypes = [P, P, P, i64, ctypes.c_double, P]
         _lib = lib
         return lib
 
@@ -237,6 +242,47 @@ class OracleTree:
         self.lib.ot_solve_groups(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau), float(G),
                                  int(order), _p(counts), _p(phi))
         return phi, counts
+
+    # -- O8 ----------------------------------------------------------------------
+    def accel(self, G=1.0, order=2):
+        """O8 with the lists of the last walk; returns g[nleaf, 8, 8, 8, 3]."""
+        assert self.group_cells is not None, "walk() first"
+        acc = np.empty((self.ncells, 3))
+        self.lib.ot_accel(self.h, float(G), int(order), _p(acc))
+        return acc.reshape(self.nleaf, 8, 8, 8, 3)
+
+    def solve_groups_accel(self, groups, group_cells=64, theta=0.5, tau=0.0, G=1.0, order=2):
+        """O5, O6, O8 for selected canonical groups.  Returns (g[n, G, 3] in the
+        group's Morton order, counts[n, 4] = visited, far, near, marginal)."""
+        if not self._moments_done:
+            self.moments()
+        ng = self.n_groups(group_cells)
+        th = np.broadcast_to(np.asarray(theta, np.float64), (ng,)).copy()
+        gs = np.ascontiguousarray(groups, np.int64)
+        acc = np.empty((gs.size, group_cells, 3))
+        counts = np.empty((gs.size, 4), np.int64)
+        self.lib.ot_solve_groups_accel(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau), float(G),
+                                       int(order), _p(counts), _p(acc))
+        return acc, counts
+
+    def direct_accel(self, targets=None, G=1.0):
+        """Exact direct-sum acceleration at canonical cell ids (all if None), [n, 3]."""
+        if not self._density_set:
+            self.set_density()
+        t = np.arange(self.ncells, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, np.int64)
+        acc = np.empty((t.size, 3))
+        self.lib.ot_direct_accel(self.h, _p(t), int(t.size), float(G), _p(acc))
+        return acc
+
+    def direct_at(self, points, exclude, G=1.0):
+        """Direct-sum potential at arbitrary points [n, 3], leaving out cell exclude[q] (-1: none)."""
+        if not self._density_set:
+            self.set_density()
+        p = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+        ex = np.ascontiguousarray(np.broadcast_to(np.asarray(exclude, np.int64), (p.shape[0],)))
+        phi = np.empty(p.shape[0])
+        self.lib.ot_direct_at(self.h, _p(p), _p(ex), int(p.shape[0]), float(G), _p(phi))
+        return phi
 
     # -- O2 ----------------------------------------------------------------------
     def direct(self, targets=None, G=1.0):
