@@ -15,7 +15,14 @@ region) is checked.  For comparison the same step with a fixed theta -- the
 largest theta of {0.20, 0.25, ..., 1.00} meeting the gate -- is timed in fp32
 and fp64 (`fixed_theta`), with the full sweep in `sweep`.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+With --workload batched the step is instead one solve of 64 independent
+AMR grids (seeded mixes of 1-4 Plummer spheres, 100-8000 target leaf blocks,
+3-6 AMR levels; grid k drawn with seed 7370 + k) in one persistent launch
+replayed from a captured graph, at the largest fixed theta whose 1%-sampled
+RMS error meets the gate on every grid, under the launch configuration the
+library's autotuner picks.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload maclaurin|batched]
 """
 from __future__ import annotations
 
@@ -34,6 +41,8 @@ if ROOT not in sys.path:
 PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector datasheet figure
 F_FAR = 35                  # flop per (cell, far node): monopole + quadrupole
 F_NEAR = 11                 # flop per (cell, near cell) pair
+F_FAR_ACC = 55              # flop per (cell, far node) pair with potential + acceleration
+F_NEAR_ACC = 19             # flop per (cell, near cell) pair with potential + acceleration
 RMS_GATE = 1e-3
 WEIGHTS = os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz")
 PROFILE = os.path.join(ROOT, "profiles", "walk_potential_fp32_maclaurin_1p4M.md")
@@ -70,6 +79,182 @@ def algorithmic_flops(n_far, n_near):
     return F_FAR * far_int + F_NEAR * near_pairs, far_int, near_pairs
 
 
+BATCH_GRIDS = 64
+BATCH_SEED = 7370
+
+
+def run_batched(args, dev):
+    """64 uneven Plummer-mix grids, one persistent launch per solve (see module docstring)."""
+    import torch
+    from amr_inputs import plummer_mix
+    from paper_1509_07370_amd import binding as B
+    from paper_1509_07370_amd import learned_theta as LT
+
+    t0 = time.time()
+    grids = [plummer_mix(BATCH_SEED + k) for k in range(BATCH_GRIDS)]
+    cells = np.array([g.ncells for g in grids], np.int64)
+    ncells = int(cells.sum())
+    log("batched workload: %d grids, %d leaf blocks, %d cells (%d..%d per grid), %.1f s to generate" % (
+        len(grids), sum(g.nleaf for g in grids), ncells, cells.min(), cells.max(), time.time() - t0))
+    ctx = B.bh_ctx_create(0)
+    t0 = time.perf_counter()
+    handles = [B.bh_grid_create_from(ctx, g) for g in grids]
+    batch = B.bh_batch_create(ctx, handles)
+    topo_ms = (time.perf_counter() - t0) * 1e3
+    rho = [torch.tensor(g.rho, device=dev) for g in grids]
+    phi = [torch.empty_like(r) for r in rho]
+    _, total_groups = B.bh_batch_info(batch)
+    del grids
+
+    # exact direct sums at a seeded 1% sample of every grid (fp64, GPU), reused for every theta
+    t0 = time.time()
+    samples, direct = [], []
+    for k, (h, r) in enumerate(zip(handles, rho)):
+        m = B.bh_build_moments(ctx, h, r)
+        n = int(cells[k])
+        rng = np.random.default_rng(k)
+        tg = torch.tensor(np.sort(rng.choice(n, max(1000, n // 100), replace=False)), dtype=torch.int64,
+                          device=dev)
+        d = torch.empty(tg.numel(), dtype=torch.float64, device=dev)
+        B.bh_direct(ctx, h, m, tg, 1.0, d)
+        torch.cuda.synchronize()
+        B.bh_moments_destroy(m)
+        samples.append(tg)
+        direct.append(d)
+    log("sampled direct sums: %d targets, %.1f s" % (sum(int(t.numel()) for t in samples), time.time() - t0))
+
+    def errors():
+        per, allrel = [], []
+        for p, tg, d in zip(phi, samples, direct):
+            rel = (p.reshape(-1).index_select(0, tg) - d) / d
+            per.append(float(torch.sqrt((rel * rel).mean())))
+            allrel.append(rel)
+        rel = torch.cat(allrel)
+        return max(per), float(torch.sqrt((rel * rel).mean())), float(rel.abs().max())
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    sweep = []
+    for th in LT.THETA_GRID:
+        B.bh_batch_solve(ctx, batch, rho, phi, float(th), None, B.BH_FP32, 1.0)
+        B.bh_batch_check(ctx, batch)
+        worst, rms, mx = errors()
+        sweep.append(dict(theta=float(th), worst_grid_rms=worst, rms_rel_err=rms, max_rel_err=mx))
+    ok = [s_ for s_ in sweep if s_["worst_grid_rms"] <= RMS_GATE]
+    theta = max(s_["theta"] for s_ in ok) if ok else LT.FALLBACK_THETA
+    gate = [s_ for s_ in sweep if s_["theta"] == theta][0]
+    log("theta %.2f: worst grid rms %.2e, all-sample rms %.2e" % (theta, gate["worst_grid_rms"],
+                                                                  gate["rms_rel_err"]))
+
+    # 64 separate single-grid solves (moments + fused walk/sums per grid), for comparison
+    ms_sep = {}
+    for prec, name in ((B.BH_FP32, "fp32"), (B.BH_FP64, "fp64")):
+        ms_list = [B.bh_build_moments(ctx, h, r) for h, r in zip(handles, rho)]
+
+        def separate():
+            for h, r, p, m in zip(handles, rho, phi, ms_list):
+                B.bh_build_moments(ctx, h, r, m)
+                B.bh_walk_potential(ctx, h, m, theta, None, prec, 1.0, p, None)
+        ms_sep[name] = timed(separate, 3)
+        for m in ms_list:
+            B.bh_moments_destroy(m)
+    ms_eager = timed(lambda: B.bh_batch_solve(ctx, batch, rho, phi, theta, None, B.BH_FP32, 1.0), 3)
+    ms_eager64 = timed(lambda: B.bh_batch_solve(ctx, batch, rho, phi, theta, None, B.BH_FP64, 1.0), 2)
+    log("separate solves fp32 %.2f ms, fp64 %.2f ms; one batched launch fp32 %.2f ms, fp64 %.2f ms" % (
+        ms_sep["fp32"], ms_sep["fp64"], ms_eager, ms_eager64))
+
+    t0 = time.time()
+    best, best_ms, table = B.bh_batch_autotune(ctx, batch, rho, phi, theta, None, B.BH_FP32, 1.0, reps=3)
+    log("autotuner: %d candidates in %.1f s, best %s at %.2f ms" % (len(table), time.time() - t0, best, best_ms))
+    B.bh_batch_capture(ctx, batch, rho, phi, theta, None, B.BH_FP32, 1.0)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        B.bh_batch_replay(ctx, batch)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        B.bh_batch_replay(ctx, batch)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    B.bh_batch_check(ctx, batch)
+    worst, rms, mx = errors()
+    assert worst <= RMS_GATE or not ok, "replayed graph misses the accuracy gate"
+    counts = B.bh_batch_counts(ctx, batch).astype(np.int64)
+    flops, far_int, near_pairs = algorithmic_flops(counts[:, 0], counts[:, 1])
+    achieved = flops / (ms_step * 1e-3) / 1e12
+    log("graph replay %.3f ms/solve (wall %.3f): %.1f Mcells/s, %.2f TFLOP/s over the whole solve" % (
+        ms_step, wall_ms, ncells / ms_step / 1e3, achieved))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import OracleTree
+        k = int(np.argmin(cells))
+        g = plummer_mix(BATCH_SEED + k)
+        t0 = time.perf_counter()
+        ot = OracleTree(g)
+        ot.moments()
+        ot.walk(64, theta)
+        ot.potential()
+        cpu_s = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = dict(value=g.ncells / cpu_s / 1e6, unit="Mcells/s", cores=threads, kind="oracle",
+                   sample="smallest grid of the batch (seed %d, %d cells): fp64 oracle tree + moments + walk + "
+                          "sum at theta %.2f, %.2f s" % (BATCH_SEED + k, g.ncells, theta, cpu_s))
+        log("cpu oracle %.2f s on %d threads for %d cells" % (cpu_s, threads, g.ncells))
+
+    out = {
+        "metric": "Mcells/s potential eval at RMS rel err <=1e-3 vs direct sum; batched grids, fixed theta",
+        "value": ncells / ms_step / 1e3,
+        "unit": "Mcells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 Plummer-mix AMR grids (seeds %d..%d; 1-4 spheres, 100-8000 target leaf blocks, "
+                               "3-6 levels), %d cells, %d groups of 64, one persistent launch from a captured "
+                               "graph, fixed theta %.2f, fp32 walk and pair terms, fp64 accumulation" % (
+                                   BATCH_SEED, BATCH_SEED + BATCH_GRIDS - 1, ncells, total_groups, theta),
+                   "grids": BATCH_GRIDS, "cells": ncells, "groups": int(total_groups), "theta": theta,
+                   "precision": "fp32-walk/fp64-accumulate"},
+        "accuracy": dict(worst_grid_rms=worst, rms_rel_err=rms, max_rel_err=mx,
+                         sampled_targets=int(sum(int(t.numel()) for t in samples))),
+        "comparison_ms": {"separate_fp32": ms_sep["fp32"], "separate_fp64": ms_sep["fp64"],
+                          "batched_eager_fp32_default": ms_eager, "batched_eager_fp64_default": ms_eager64,
+                          "batched_graph_fp32_tuned": ms_step},
+        "autotune": {"best": best, "best_ms": best_ms,
+                     "table": [dict(c, ms=t) for c, t in table]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "whole batched solve (moments + batch_walk_potential_kernel<float>)",
+                     "kernel_ms": ms_step, "flop_per_launch": flops, "far_interactions": far_int,
+                     "near_pairs": near_pairs},
+        "cpu_baseline": cpu,
+        "topology_ms": topo_ms,
+        "sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+    B.bh_batch_destroy(batch)
+    for h in handles:
+        B.bh_grid_destroy(h)
+    B.bh_ctx_destroy(ctx)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +263,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="time the headline step only (for profiler runs)")
+    ap.add_argument("--workload", choices=("maclaurin", "batched"), default="maclaurin")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -104,6 +290,8 @@ def main():
         log("copied %d MiB three times (reads %d KiB and writes %d KiB per copy)" % (
             args.copy_calibration, args.copy_calibration * 1024, args.copy_calibration * 1024))
         return
+    if args.workload == "batched":
+        return run_batched(args, dev)
 
     t0 = time.time()
     grid = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
@@ -209,6 +397,37 @@ def main():
     achieved = flops / (pot_ms * 1e-3) / 1e12
     log("walk+potential kernel %.4f ms, %.3e flop -> %.2f TFLOP/s" % (pot_ms, flops, achieved))
 
+    # ---- accelerations (g = -grad phi) from the same walk, learned theta, fp32 walk / fp64 accumulation
+    accel = None
+    if not args.profile_only:
+        acc = torch.empty(rho.shape + (3,), dtype=torch.float64, device=dev)
+
+        def step_accel():
+            bh.build_moments(rho)
+            B.bh_walk_accel(bh.ctx, bh.grid, bh.m, 0.5, theta_g, B.BH_FP32, 1.0, phi, acc, None)
+        acc_ms = timed(step_accel, max(args.steps, 10))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(nrep):
+            B.bh_walk_accel(bh.ctx, bh.grid, bh.m, 0.5, theta_g, B.BH_FP32, 1.0, phi, acc, None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        acc_kernel_ms = e0.elapsed_time(e1) / nrep
+        rng = np.random.default_rng(11)
+        tg = torch.tensor(np.sort(rng.choice(ncells, ncells // 100, replace=False)), dtype=torch.int64, device=dev)
+        dacc = torch.empty((tg.numel(), 3), dtype=torch.float64, device=dev)
+        B.bh_direct_accel(bh.ctx, bh.grid, bh.m, tg, 1.0, dacc)
+        rel = torch.linalg.norm(acc.reshape(-1, 3).index_select(0, tg) - dacc, dim=1) / torch.linalg.norm(dacc, dim=1)
+        acc_flops = F_FAR_ACC * far_int + F_NEAR_ACC * near_pairs
+        accel = dict(ms_per_step=acc_ms, mcells_per_s=ncells / acc_ms / 1e3, kernel_ms=acc_kernel_ms,
+                     tflops=acc_flops / (acc_kernel_ms * 1e-3) / 1e12,
+                     frac=acc_flops / (acc_kernel_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                     sampled_rms_rel_err=float(torch.sqrt((rel * rel).mean())), sampled_max_rel_err=float(rel.max()),
+                     sample="1% of cells vs the exact fp64 direct acceleration (bh_direct_accel)",
+                     theta="learned (same per-group theta as the potential step)")
+        log("accelerations: %.3f ms/step (%.1f Mcells/s), kernel %.4f ms (%.2f TFLOP/s), sampled rms %.2e" % (
+            acc_ms, accel["mcells_per_s"], acc_kernel_ms, accel["tflops"], accel["sampled_rms_rel_err"]))
+
     cpu = None
     if not args.no_cpu_baseline and not args.profile_only:
         from oracle import OracleTree
@@ -246,6 +465,7 @@ def main():
                    "precision": "fp32-walk/fp64-accumulate"},
         "learned_theta": learned,
         "fixed_theta": fixed,
+        "accelerations": accel,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
                      "kernel": "walk_potential_kernel<float>", "kernel_ms": pot_ms, "flop_per_launch": flops,

@@ -186,12 +186,33 @@ int bh_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh
 int bh_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, double theta,
                       const float *theta_group_dev, int precision, double G, double *phi_dev, int32_t *counts_dev);
 
+/* Accelerations g = -grad phi from the same walk and tiles as
+ * bh_walk_potential: the gradient of the far term (monopole and quadrupole)
+ * and of the near pair terms, taken term by term (an extension of the method,
+ * whose potential the paper computes; section 3.1 lists forces among what is
+ * written back with it):
+ *   far node:  g += G [ Q R / d^5 - (M / d^3 + (5/2) R^T Q R / d^7) R ]
+ *   near cell: g -= G m_j (r_i - r_j) / |r_i - r_j|^3,   R = r_i - X.
+ * acc_dev: fp64 [n_leaf][8][8][8][3] (x, y, z per cell, caller layout), fully
+ * overwritten.  phi_dev: NULL, or receives the potential computed in the same
+ * pass (the method's value; its rounding may differ from bh_walk_potential's
+ * in the last fp32 bits, as the pair terms are evaluated in another order of
+ * operations).  Other arguments, precisions, counts and errors as for
+ * bh_walk_potential; tile sums in `precision`, accumulation in fp64. */
+int bh_walk_accel(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, double theta, const float *theta_group_dev,
+                  int precision, double G, double *phi_dev, double *acc_dev, int32_t *counts_dev);
+
 /* Exact direct sum (Eq. 2) in fp64 at n_targets canonical cell ids
  * targets_dev[n] (int64, device); phi_dev[n] receives -G sum_{j != i} m_j/|r_ij|.
  * Uses the cell masses of the last bh_build_moments on m.  Errors: BH_EINVAL
  * (n_targets < 0), BH_ESTATE. */
 int bh_direct(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const int64_t *targets_dev,
               int64_t n_targets, double G, double *phi_dev);
+/* Exact acceleration of the direct sum in fp64 at the same targets:
+ * acc_dev[n][3] receives -G sum_{j != i} m_j (r_i - r_j) / |r_i - r_j|^3.
+ * Arguments and errors as bh_direct. */
+int bh_direct_accel(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const int64_t *targets_dev,
+                    int64_t n_targets, double G, double *acc_dev);
 
 /* ---------------------------------------------------------------- batches
  *
@@ -231,6 +252,55 @@ int bh_batch_schedule(bh_ctx *ctx, bh_batch *batch, int mode);
 /* Persistent workgroups per compute unit (0 = the kernel's resident waves per
  * SIMD); a tuning knob, drops a captured graph. */
 int bh_batch_set_launch(bh_ctx *ctx, bh_batch *batch, int workgroups_per_cu);
+
+/* Launch configuration of a batch's persistent solve.  Order, width and
+ * variant leave the results unchanged bit for bit (each group is still
+ * computed by one wavefront with the same tiles in the same order); a stack
+ * limit below the default changes the traversal order and so the order of
+ * the far tiles: the same far and near sets, summed in another order.
+ *   order             BH_ORDER_NATURAL or BH_ORDER_COST (cost uses the counts
+ *                     of the last solve; before any solve it is the natural order)
+ *   workgroups_per_cu persistent workgroups of 4 wavefronts per compute unit,
+ *                     0 = one per resident slot of the kernel variant, <= 64
+ *   waves_per_simd    kernel variant by register budget (the compiler fits the
+ *                     kernel in 512 / waves VGPRs): fp32 4, 6 or 8; fp64 2 or 4;
+ *                     0 = the precision's default (8 fp32, 4 fp64).  A value
+ *                     with no variant for the solve's precision makes that
+ *                     solve fail with BH_EINVAL.
+ *   stack_limit       traversal stack policy: the walk pops whole sibling sets
+ *                     (64 nodes a step) while its stack holds at most this many
+ *                     entries and single sets beyond; 0 = the largest value that
+ *                     cannot overflow for each grid's depth, else >= 8 and
+ *                     clamped to that value.
+ * bh_batch_configure drops a captured graph; BH_EINVAL for values out of range. */
+typedef struct bh_batch_config {
+    int32_t order;
+    int32_t workgroups_per_cu;
+    int32_t waves_per_simd;
+    int32_t stack_limit;
+} bh_batch_config;
+
+int bh_batch_configure(bh_ctx *ctx, bh_batch *batch, const bh_batch_config *config);
+int bh_batch_get_config(const bh_batch *batch, bh_batch_config *config);
+
+/* Autotuner: solves the batch (arguments as bh_batch_solve) under every
+ * candidate configuration -- each kernel variant of the precision x launch
+ * widths {1, waves/2, waves} workgroups per CU x both queue orders x stack
+ * limits {largest safe, 64} -- timing `reps` solves of each with HIP events
+ * after one untimed solve, and applies the one with the smallest median time.
+ * best (may be NULL) receives it and best_ms its median time.  table (may be
+ * NULL) receives up to table_cap rows of every candidate tried and its median
+ * time in ms; *n_table (may be NULL) the number of candidates.  Synchronises;
+ * phi_dev holds the potentials of the last candidate's solve.
+ * BH_EINVAL for reps < 1 or invalid solve arguments. */
+typedef struct bh_batch_timing {
+    bh_batch_config config;
+    float ms;
+} bh_batch_timing;
+
+int bh_batch_autotune(bh_ctx *ctx, bh_batch *batch, const double *const *rho_dev, double *const *phi_dev,
+                      double theta, const float *const *theta_group_dev, int precision, double G, int reps,
+                      bh_batch_config *best, float *best_ms, bh_batch_timing *table, int table_cap, int *n_table);
 
 /* ---------------------------------------------------------------- learned theta
  *

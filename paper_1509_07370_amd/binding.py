@@ -37,6 +37,17 @@ class GridInfo(ctypes.Structure):
                 ("nbase", i32), ("max_depth", i32), ("n_levels", i32)]
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("order", i32), ("workgroups_per_cu", i32), ("waves_per_simd", i32), ("stack_limit", i32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class BatchTiming(ctypes.Structure):
+    _fields_ = [("config", BatchConfig), ("ms", ctypes.c_float)]
+
+
 _SIGS = {
     "bh_ctx_create": (ctypes.c_int, [PP, ctypes.c_int, P]),
     "bh_ctx_set_stream": (ctypes.c_int, [P, P]),
@@ -57,6 +68,8 @@ _SIGS = {
     "bh_lists_destroy": (ctypes.c_int, [P]),
     "bh_potential": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
     "bh_walk_potential": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P]),
+    "bh_walk_accel": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P, P]),
+    "bh_direct_accel": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
     "bh_direct": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
     "bh_batch_create": (ctypes.c_int, [P, PP, ctypes.c_int, P]),
     "bh_batch_destroy": (ctypes.c_int, [P]),
@@ -68,6 +81,10 @@ _SIGS = {
     "bh_batch_counts": (ctypes.c_int, [P, P, P]),
     "bh_batch_schedule": (ctypes.c_int, [P, P, ctypes.c_int]),
     "bh_batch_set_launch": (ctypes.c_int, [P, P, ctypes.c_int]),
+    "bh_batch_configure": (ctypes.c_int, [P, P, P]),
+    "bh_batch_get_config": (ctypes.c_int, [P, P]),
+    "bh_batch_autotune": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64, ctypes.c_int, P, P, P,
+                                         ctypes.c_int, P]),
     "bh_group_features": (ctypes.c_int, [P, P, P, P]),
     "bh_group_rms_error": (ctypes.c_int, [P, P, P, P, P]),
     "bh_mlp_create": (ctypes.c_int, [P, PP, P, P, P]),
@@ -256,6 +273,22 @@ def bh_walk_potential(ctx, grid, m, theta, theta_group, precision, G, phi, count
     return phi
 
 
+def bh_walk_accel(ctx, grid, m, theta, theta_group, precision, G, phi, acc, counts=None):
+    """acc: float64 CUDA tensor [n_leaf, 8, 8, 8, 3]; phi: None or [n_leaf, 8, 8, 8]."""
+    tg = _dev(theta_group, "float32") if theta_group is not None else None
+    ph = _dev(phi, "float64") if phi is not None else None
+    c = _dev(counts, "int32") if counts is not None else None
+    _check(_lib.bh_walk_accel(ctx, grid, m, float(theta), tg, int(precision), float(G), ph, _dev(acc, "float64"), c),
+           ctx)
+    return acc
+
+
+def bh_direct_accel(ctx, grid, m, targets, G, acc):
+    n = int(targets.numel())
+    _check(_lib.bh_direct_accel(ctx, grid, m, _dev(targets, "int64"), n, float(G), _dev(acc, "float64")), ctx)
+    return acc
+
+
 def bh_direct(ctx, grid, m, targets, G, phi):
     n = int(targets.numel())
     _check(_lib.bh_direct(ctx, grid, m, _dev(targets, "int64"), n, float(G), _dev(phi, "float64")), ctx)
@@ -389,3 +422,26 @@ def bh_batch_schedule(ctx, batch, mode):
 
 def bh_batch_set_launch(ctx, batch, workgroups_per_cu):
     _check(_lib.bh_batch_set_launch(ctx, batch, int(workgroups_per_cu)), ctx)
+
+
+def bh_batch_configure(ctx, batch, order=BH_ORDER_NATURAL, workgroups_per_cu=0, waves_per_simd=0, stack_limit=0):
+    cfg = BatchConfig(int(order), int(workgroups_per_cu), int(waves_per_simd), int(stack_limit))
+    _check(_lib.bh_batch_configure(ctx, batch, ctypes.byref(cfg)), ctx)
+
+
+def bh_batch_get_config(batch):
+    cfg = BatchConfig()
+    _check(_lib.bh_batch_get_config(batch, ctypes.byref(cfg)), None)
+    return cfg.as_dict()
+
+
+def bh_batch_autotune(ctx, batch, rho, phi, theta=0.5, theta_group=None, precision=BH_FP32, G=1.0, reps=3):
+    """Returns (best config dict, best median ms, [(config dict, ms), ...])."""
+    r, p, tg = _batch_args(rho, phi, theta_group)
+    best, best_ms, n = BatchConfig(), ctypes.c_float(), ctypes.c_int()
+    cap = 128
+    table = (BatchTiming * cap)()
+    _check(_lib.bh_batch_autotune(ctx, batch, r, p, float(theta), tg, int(precision), float(G), int(reps),
+                                  ctypes.byref(best), ctypes.byref(best_ms), table, cap, ctypes.byref(n)), ctx)
+    rows = [(table[i].config.as_dict(), float(table[i].ms)) for i in range(min(n.value, cap))]
+    return best.as_dict(), float(best_ms.value), rows

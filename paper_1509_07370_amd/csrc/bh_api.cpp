@@ -463,6 +463,21 @@ int bh_walk_potential(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double
     return BH_OK;
 }
 
+int bh_walk_accel(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                  int precision, double G, double *phi, double *acc, int32_t *counts) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!g || !m || !acc) return fail(ctx, BH_EINVAL, "grid, moments or acc_dev is NULL");
+    if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
+    if (!theta_group && !(theta > 0.0 && theta <= 1.0)) return fail(ctx, BH_EINVAL, "theta must be in (0, 1]");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    m->walk_epoch++;
+    HIPX(ctx, bh::launch_walk_accel(g, m, theta, theta_group, precision, G, phi, acc, counts, ctx->stream),
+         "fused walk + acceleration kernel");
+    return BH_OK;
+}
+
 int bh_direct(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,
               double *phi) {
     int rc = require_gpu(ctx);
@@ -472,7 +487,20 @@ int bh_direct(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const int64_t 
     if (n < 0) return fail(ctx, BH_EINVAL, "n_targets must be >= 0");
     if (n > 0 && (!targets || !phi)) return fail(ctx, BH_EINVAL, "targets_dev or phi_dev is NULL");
     if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
-    HIPX(ctx, bh::launch_direct(g, m, targets, n, G, phi, ctx->stream), "direct-sum kernel");
+    HIPX(ctx, bh::launch_direct(g, m, targets, n, G, phi, false, ctx->stream), "direct-sum kernel");
+    return BH_OK;
+}
+
+int bh_direct_accel(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,
+                    double *acc) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!g || !m) return fail(ctx, BH_EINVAL, "grid or moments is NULL");
+    if (m->grid != g) return fail(ctx, BH_ESTATE, "moments belong to another grid");
+    if (n < 0) return fail(ctx, BH_EINVAL, "n_targets must be >= 0");
+    if (n > 0 && (!targets || !acc)) return fail(ctx, BH_EINVAL, "targets_dev or acc_dev is NULL");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    HIPX(ctx, bh::launch_direct(g, m, targets, n, G, acc, true, ctx->stream), "direct-sum acceleration kernel");
     return BH_OK;
 }
 

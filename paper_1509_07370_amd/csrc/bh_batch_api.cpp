@@ -24,6 +24,9 @@ struct bh_batch {
     unsigned long long *d_counter = nullptr;
     int cus = 0;
     int workgroups_per_cu = 0;            // 0: one per resident slot
+    int order_mode = BH_ORDER_NATURAL;
+    int waves = 0;                        // kernel variant, 0: default of the precision
+    int stack_limit = 0;                  // 0: largest safe per grid
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -77,18 +80,22 @@ int enqueue_solve(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *co
         const float *tg = theta_group ? theta_group[k] : nullptr;
         b->h_desc[k] = bh::fused_args(g, b->moments[k], theta, tg, precision, G, phi[k],
                                       b->d_counts + 2 * b->group_base[k], 1);
+        if (b->stack_limit > 0 && b->stack_limit < b->h_desc[k].k8_threshold)
+            b->h_desc[k].k8_threshold = b->stack_limit;
     }
     HIPX(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(bh::WalkArgs), hipMemcpyHostToDevice, s),
          "upload of the batch descriptors");
     HIPX(ctx, bh::launch_batch_reset(b->d_desc, n, b->d_counter, s), "batch reset kernel");
     for (int k = 0; k < n; k++)
         HIPX(ctx, bh::launch_moments(b->grids[k], b->moments[k], rho[k], s, 1), "moments kernels");
-    int per_cu = b->workgroups_per_cu > 0 ? b->workgroups_per_cu : bh::fused_waves_per_simd(precision);
+    const int waves = b->waves > 0 ? b->waves : bh::fused_waves_per_simd(precision);
+    int per_cu = b->workgroups_per_cu > 0 ? b->workgroups_per_cu : waves;
     int64_t wgs = (int64_t)b->cus * per_cu;
     const int64_t need = (b->total + 3) / 4;
     if (wgs > need) wgs = need;
     if (wgs < 1) wgs = 1;
-    HIPX(ctx, bh::launch_batch_walk_potential(b->d_desc, b->d_order, b->total, b->d_counter, precision, (int)wgs, s),
+    HIPX(ctx, bh::launch_batch_walk_potential(b->d_desc, b->d_order, b->total, b->d_counter, precision, waves,
+                                              (int)wgs, s),
          "batch walk + potential kernel");
     return BH_OK;
 }
@@ -98,6 +105,9 @@ int check_args(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const
     if (!b || !rho || !phi) return fail(ctx, BH_EINVAL, "batch, rho or phi array is NULL");
     if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
     if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    if (b->waves > 0 && !bh::fused_variant_exists(precision, b->waves))
+        return fail(ctx, BH_EINVAL, "waves_per_simd " + std::to_string(b->waves) + " has no " +
+                                        (precision == BH_FP64 ? "fp64" : "fp32") + " kernel variant");
     for (size_t k = 0; k < b->grids.size(); k++) {
         if (!rho[k] || !phi[k]) return fail(ctx, BH_EINVAL, "a rho_dev or phi_dev entry is NULL");
         const bool has_tg = theta_group && theta_group[k];
@@ -303,7 +313,112 @@ int bh_batch_schedule(bh_ctx *ctx, bh_batch *b, int mode) {
         order.swap(sorted);
     }
     drop_graph(b);
-    return upload_order(ctx, b, order);
+    rc = upload_order(ctx, b, order);
+    if (rc == BH_OK) b->order_mode = mode;
+    return rc;
+}
+
+int bh_batch_get_config(const bh_batch *b, bh_batch_config *cfg) {
+    if (!b || !cfg) return BH_EINVAL;
+    cfg->order = b->order_mode;
+    cfg->workgroups_per_cu = b->workgroups_per_cu;
+    cfg->waves_per_simd = b->waves;
+    cfg->stack_limit = b->stack_limit;
+    return BH_OK;
+}
+
+int bh_batch_configure(bh_ctx *ctx, bh_batch *b, const bh_batch_config *cfg) {
+    if (!ctx || !b || !cfg) return fail(ctx, BH_EINVAL, "context, batch or config is NULL");
+    if (cfg->order != BH_ORDER_NATURAL && cfg->order != BH_ORDER_COST)
+        return fail(ctx, BH_EINVAL, "unknown queue order");
+    if (cfg->workgroups_per_cu < 0 || cfg->workgroups_per_cu > 64)
+        return fail(ctx, BH_EINVAL, "workgroups_per_cu out of range");
+    if (cfg->waves_per_simd != 0 && !bh::fused_variant_exists(BH_FP32, cfg->waves_per_simd) &&
+        !bh::fused_variant_exists(BH_FP64, cfg->waves_per_simd))
+        return fail(ctx, BH_EINVAL, "no kernel variant for waves_per_simd " + std::to_string(cfg->waves_per_simd));
+    if (cfg->stack_limit != 0 && (cfg->stack_limit < 8 || cfg->stack_limit > bh::kWalkStackCap))
+        return fail(ctx, BH_EINVAL, "stack_limit must be 0 or in [8, stack capacity]");
+    int rc = bh_batch_schedule(ctx, b, cfg->order);
+    if (rc) return rc;
+    b->workgroups_per_cu = cfg->workgroups_per_cu;
+    b->waves = cfg->waves_per_simd;
+    b->stack_limit = cfg->stack_limit;
+    drop_graph(b);
+    return BH_OK;
+}
+
+int bh_batch_autotune(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const *phi, double theta,
+                      const float *const *theta_group, int precision, double G, int reps, bh_batch_config *best,
+                      float *best_ms, bh_batch_timing *table, int table_cap, int *n_table) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!b) return fail(ctx, BH_EINVAL, "batch is NULL");
+    if (reps < 1) return fail(ctx, BH_EINVAL, "reps must be >= 1");
+    if (table_cap < 0 || (table_cap > 0 && !table)) return fail(ctx, BH_EINVAL, "table is NULL or table_cap < 0");
+    const bh_batch_config saved = {b->order_mode, b->workgroups_per_cu, b->waves, b->stack_limit};
+    b->waves = 0;
+    if ((rc = check_args(ctx, b, rho, phi, theta, theta_group, precision, G))) return rc;
+    drop_graph(b);
+    // a first solve fills the counts that the cost order needs
+    b->precision = precision;
+    if ((rc = enqueue_solve(ctx, b, rho, phi, theta, theta_group, precision, G, ctx->stream))) return rc;
+    std::vector<bh_batch_config> cands;
+    const int variants32[] = {8, 6, 4}, variants64[] = {4, 2};
+    const int *var = precision == BH_FP64 ? variants64 : variants32;
+    const int nvar = precision == BH_FP64 ? 2 : 3;
+    for (int order : {BH_ORDER_NATURAL, BH_ORDER_COST})
+        for (int v = 0; v < nvar; v++) {
+            std::vector<int> widths = {var[v], var[v] / 2, 1};
+            std::sort(widths.begin(), widths.end());
+            widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+            for (int w : widths)
+                for (int stack : {0, 64}) cands.push_back({order, w, var[v], stack});
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPX(ctx, hipEventCreate(&e0), "event");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(ctx, he, "event");
+    }
+    std::vector<float> med(cands.size(), 0.f);
+    int best_i = -1;
+    for (size_t c = 0; c < cands.size() && rc == BH_OK; c++) {
+        if (c == 0 || cands[c].order != cands[c - 1].order) rc = bh_batch_schedule(ctx, b, cands[c].order);
+        if (rc) break;
+        b->workgroups_per_cu = cands[c].workgroups_per_cu;
+        b->waves = cands[c].waves_per_simd;
+        b->stack_limit = cands[c].stack_limit;
+        if ((rc = enqueue_solve(ctx, b, rho, phi, theta, theta_group, precision, G, ctx->stream))) break;
+        std::vector<float> t(reps);
+        for (int r = 0; r < reps && rc == BH_OK; r++) {
+            if ((he = hipEventRecord(e0, ctx->stream)) != hipSuccess) { rc = hip_fail(ctx, he, "event record"); break; }
+            if ((rc = enqueue_solve(ctx, b, rho, phi, theta, theta_group, precision, G, ctx->stream))) break;
+            if ((he = hipEventRecord(e1, ctx->stream)) != hipSuccess ||
+                (he = hipEventSynchronize(e1)) != hipSuccess || (he = hipEventElapsedTime(&t[r], e0, e1)) != hipSuccess)
+                rc = hip_fail(ctx, he, "event timing");
+        }
+        if (rc) break;
+        std::sort(t.begin(), t.end());
+        med[c] = t[reps / 2];
+        if (best_i < 0 || med[c] < med[best_i]) best_i = (int)c;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {  // leave the batch as it was
+        b->workgroups_per_cu = saved.workgroups_per_cu;
+        b->waves = saved.waves_per_simd;
+        b->stack_limit = saved.stack_limit;
+        (void)bh_batch_schedule(ctx, b, saved.order);
+        return rc;
+    }
+    const bh_batch_config &w = cands[best_i];
+    if ((rc = bh_batch_configure(ctx, b, &w))) return rc;
+    if (best) *best = w;
+    if (best_ms) *best_ms = med[best_i];
+    for (int c = 0; c < (int)cands.size() && c < table_cap; c++) table[c] = {cands[c], med[c]};
+    if (n_table) *n_table = (int)cands.size();
+    return BH_OK;
 }
 
 }  // extern "C"

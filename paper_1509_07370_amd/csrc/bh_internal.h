@@ -44,7 +44,8 @@ struct alignas(16) FarRec32 {
     float d, e, pad0, pad1;
 };
 // fp64 node moments, 12 doubles per node:
-//   0 X, 1 Y, 2 Z, 3 M, 4 Qxx, 5 Qyy, 6 Qzz, 7 Qxy, 8 Qxz, 9 Qyz, 10 delta, 11 unused
+//   0 X, 1 Y, 2 Z, 3 M, 4 Qxx, 5 Qyy, 6 Qzz, 7 Qxy, 8 Qxz, 9 Qyz, 10 delta,
+//   11 largest single-cell mass below the node (in-block nodes; 0 elsewhere)
 constexpr int kMom = 12;
 
 // Per leaf block, internal (Morton) order.  48 bytes.
@@ -80,6 +81,7 @@ struct WalkArgs {
     double G;
     double *phi;
     int32_t *counts;
+    double *acc;  // accelerations [cell][3] (acceleration kernels only)
 };
 
 // Host-side octree topology built from the block list.
@@ -164,17 +166,23 @@ hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hi
 WalkArgs fused_args(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group, int precision,
                     double G, double *phi, int32_t *counts, int epoch);
 hipError_t launch_batch_reset(const WalkArgs *grids, int n, unsigned long long *counter, hipStream_t s);
+// waves: kernel variant (fused_variant_exists), workgroups: persistent grid size
 hipError_t launch_batch_walk_potential(const WalkArgs *grids, const int2 *order, int64_t total,
-                                       unsigned long long *counter, int precision, int workgroups, hipStream_t s);
+                                       unsigned long long *counter, int precision, int waves, int workgroups,
+                                       hipStream_t s);
 int fused_waves_per_simd(int precision);
+bool fused_variant_exists(int precision, int waves);
 hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
                        int precision, bool fill, hipStream_t s);
 hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipStream_t s);
 hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                                  int precision, double G, double *phi, int32_t *counts, hipStream_t s);
+// walk fused with potential (phi may be NULL) and acceleration sums
+hipError_t launch_walk_accel(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                             int precision, double G, double *phi, double *acc, int32_t *counts, hipStream_t s);
 hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_lists *L, double G, int precision,
                             double *phi, hipStream_t s);
 hipError_t launch_direct(const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,
-                         double *phi, hipStream_t s);
+                         double *out, bool accel, hipStream_t s);
 int walk_k8_threshold(int max_depth);
 }  // namespace bh

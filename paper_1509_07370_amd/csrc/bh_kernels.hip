@@ -1,9 +1,9 @@
 // HIP kernels for gfx950 (CDNA4, wave64) of the Barnes-Hut potential path.
 //
 //   moments_leaf_kernel    one workgroup per leaf block: cells -> 64 bottom nodes
-//                          -> 8 octants -> block node, in LDS (fp64)
-//   moments_combine_kernel one thread per parent/virtual node, one launch per
-//                          tree depth, deepest first (parallel-axis rule)
+//                          -> 8 octants -> block node by lane shuffles (fp64)
+//   moments_levels_kernel  the nodes above the leaf blocks, 8 lanes per node,
+//                          deepest depth first (parallel-axis rule)
 //   walk_kernel            one wavefront per 64-cell group: breadth-limited
 //                          depth-first traversal with an LDS stack of sibling
 //                          sets; 64 lanes test 8 sibling sets at once, the
@@ -31,7 +31,7 @@ struct MomOut {
 
 // Write every derived record of node `id` from its fp64 moments.
 __device__ void store_node(const MomOut &o, int id, double M, double X, double Y, double Z, const double *Q,
-                           const double *geom, int child, int sflags) {
+                           const double *geom, int child, int sflags, double mmax = 0.0) {
 #pragma clang fp contract(off)
     double cx = geom[0], cy = geom[1], cz = geom[2], l = geom[3];
     double q[6];
@@ -57,7 +57,7 @@ __device__ void store_node(const MomOut &o, int id, double M, double X, double Y
     mo[3] = M;
     for (int c = 0; c < 6; c++) mo[4 + c] = q[c];
     mo[10] = delta;
-    mo[11] = 0.0;
+    mo[11] = mmax;
     WalkRec32 w;
     w.x = (float)X;
     w.y = (float)Y;
@@ -93,40 +93,50 @@ __device__ void store_node(const MomOut &o, int id, double M, double X, double Y
     o.f32[id] = f;
 }
 
-// Parallel-axis combination of 8 children (masses Mc, centres of mass Xc,
-// quadrupoles Qc about their own centres of mass) into the parent moments.
-__device__ void combine8(const double *Mc, const double *Xc, const double *Yc, const double *Zc,
-                         const double (*Qc)[6], double &M, double &X, double &Y, double &Z, double *Q) {
-#pragma clang fp contract(off)
-    M = 0.0;
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int c = 0; c < 8; c++) {
-        M += Mc[c];
-        sx += Mc[c] * Xc[c];
-        sy += Mc[c] * Yc[c];
-        sz += Mc[c] * Zc[c];
-    }
-    for (int c = 0; c < 6; c++) Q[c] = 0.0;
-    X = Y = Z = 0.0;
-    if (!(M > 0.0)) return;
-    X = sx / M;
-    Y = sy / M;
-    Z = sz / M;
-    for (int c = 0; c < 8; c++) {
-        double m = Mc[c];
-        double dx = Xc[c] - X, dy = Yc[c] - Y, dz = Zc[c] - Z;
-        double r2 = dx * dx + dy * dy + dz * dz;
-        Q[0] += Qc[c][0] + m * (3.0 * dx * dx - r2);
-        Q[1] += Qc[c][1] + m * (3.0 * dy * dy - r2);
-        Q[2] += Qc[c][2] + m * (3.0 * dz * dz - r2);
-        Q[3] += Qc[c][3] + m * (3.0 * dx * dy);
-        Q[4] += Qc[c][4] + m * (3.0 * dx * dz);
-        Q[5] += Qc[c][5] + m * (3.0 * dy * dz);
-    }
-}
-
 // ---------------------------------------------------------------- moments
 
+// Butterfly sum / max over the 8 lanes of an aligned group of 8 (every lane
+// ends with the same bits: each level adds the same two partial sums).
+__device__ __forceinline__ double sum8(double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+}
+__device__ __forceinline__ double max8(double v) {
+    for (int o = 1; o < 8; o <<= 1) {
+        const double u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// One node from its 8 children held by the 8 lanes of a group (child c in
+// lane c): M, centre of mass, quadrupole about it by the parallel-axis rule.
+// Cells enter as children with Q = 0.  Every lane of the group gets the node.
+__device__ __forceinline__ void combine_lanes(double m, double x, double y, double z, const double *qc, double &M,
+                                              double &X, double &Y, double &Z, double *Q) {
+#pragma clang fp contract(off)
+    M = sum8(m);
+    const double sx = sum8(m * x), sy = sum8(m * y), sz = sum8(m * z);
+    X = M > 0.0 ? sx / M : 0.0;
+    Y = M > 0.0 ? sy / M : 0.0;
+    Z = M > 0.0 ? sz / M : 0.0;
+    const double dx = x - X, dy = y - Y, dz = z - Z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    Q[0] = sum8(qc[0] + m * (3.0 * dx * dx - r2));
+    Q[1] = sum8(qc[1] + m * (3.0 * dy * dy - r2));
+    Q[2] = sum8(qc[2] + m * (3.0 * dz * dz - r2));
+    Q[3] = sum8(qc[3] + m * (3.0 * dx * dy));
+    Q[4] = sum8(qc[4] + m * (3.0 * dx * dz));
+    Q[5] = sum8(qc[5] + m * (3.0 * dy * dz));
+}
+
+// In-block part of the upward pass, one 512-thread workgroup per leaf block.
+// Thread t owns cell t of the block in Morton order, so the 8 cells of bottom
+// node b sit in lanes 8b..8b+7 and combine by lane shuffles; the 64 bottom
+// nodes then combine into the 8 octants and the block node in the first
+// wavefront.
 __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restrict__ rho,
                                                            const LeafInfo *__restrict__ leaves,
                                                            const double *__restrict__ geom,
@@ -134,121 +144,121 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
                                                            double4 *__restrict__ cell64, float4 *__restrict__ cell32,
                                                            int *__restrict__ flags, int epoch) {
 #pragma clang fp contract(off)
-    __shared__ double sm[512], sx[512], sy[512], sz[512];
-    __shared__ double bM[64], bX[64], bY[64], bZ[64], bQ[64][6];
-    __shared__ double oM[8], oX[8], oY[8], oZ[8], oQ[8][6];
+    __shared__ double bM[64], bX[64], bY[64], bZ[64], bQ[64][6], bmax[64];
     const int f = blockIdx.x;
     const int t = threadIdx.x;
     const LeafInfo L = leaves[f];
-    const int i = t & 7, j = (t >> 3) & 7, k = t >> 6;
-    const double r = rho[(int64_t)L.canon * kCellsPerBlock + t];
+    int i, j, k;
+    demorton9(t, i, j, k);
+    const double r = rho[(int64_t)L.canon * kCellsPerBlock + k * 64 + j * 8 + i];
     if (!(r >= 0.0) || !isfinite(r)) atomicMax(flags, epoch);
     const double h = L.h;
-    const double vol = h * h * h;
-    const double mass = r * vol;
+    const double mass = r * (h * h * h);
     const double x = L.lo[0] + (i + 0.5) * h;
     const double y = L.lo[1] + (j + 0.5) * h;
     const double z = L.lo[2] + (k + 0.5) * h;
-    const int m = morton9(i, j, k);
-    const int64_t c = (int64_t)f * kCellsPerBlock + m;
+    const int64_t c = (int64_t)f * kCellsPerBlock + t;
     cell64[c] = make_double4(x, y, z, mass);
     cell32[c] = make_float4((float)x, (float)y, (float)z, (float)mass);
-    sm[m] = mass;
-    sx[m] = x;
-    sy[m] = y;
-    sz[m] = z;
-    __syncthreads();
-    if (t < 64) {
-        double M = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-        for (int q = 0; q < 8; q++) {
-            int s = 8 * t + q;
-            M += sm[s];
-            ax += sm[s] * sx[s];
-            ay += sm[s] * sy[s];
-            az += sm[s] * sz[s];
-        }
-        double X = 0.0, Y = 0.0, Z = 0.0, Q[6] = {0, 0, 0, 0, 0, 0};
-        if (M > 0.0) {
-            X = ax / M;
-            Y = ay / M;
-            Z = az / M;
-            for (int q = 0; q < 8; q++) {
-                int s = 8 * t + q;
-                double dx = sx[s] - X, dy = sy[s] - Y, dz = sz[s] - Z;
-                double r2 = dx * dx + dy * dy + dz * dz;
-                Q[0] += sm[s] * (3.0 * dx * dx - r2);
-                Q[1] += sm[s] * (3.0 * dy * dy - r2);
-                Q[2] += sm[s] * (3.0 * dz * dz - r2);
-                Q[3] += sm[s] * (3.0 * dx * dy);
-                Q[4] += sm[s] * (3.0 * dx * dz);
-                Q[5] += sm[s] * (3.0 * dy * dz);
-            }
-        }
-        int id = L.bot_first + t;
-        store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], FLAG_BOTTOM);
-        bM[t] = M;
-        bX[t] = M > 0.0 ? X : geom[4 * (int64_t)id + 0];
-        bY[t] = M > 0.0 ? Y : geom[4 * (int64_t)id + 1];
-        bZ[t] = M > 0.0 ? Z : geom[4 * (int64_t)id + 2];
-        for (int q = 0; q < 6; q++) bQ[t][q] = Q[q];
-    }
-    __syncthreads();
-    if (t < 8) {
+    {  // bottom node t >> 3 from its 8 cells
+        const double q0[6] = {0, 0, 0, 0, 0, 0};
         double M, X, Y, Z, Q[6];
-        combine8(bM + 8 * t, bX + 8 * t, bY + 8 * t, bZ + 8 * t, bQ + 8 * t, M, X, Y, Z, Q);
-        int id = L.oct_first + t;
-        store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], 0);
-        oM[t] = M;
-        oX[t] = M > 0.0 ? X : geom[4 * (int64_t)id + 0];
-        oY[t] = M > 0.0 ? Y : geom[4 * (int64_t)id + 1];
-        oZ[t] = M > 0.0 ? Z : geom[4 * (int64_t)id + 2];
-        for (int q = 0; q < 6; q++) oQ[t][q] = Q[q];
+        combine_lanes(mass, x, y, z, q0, M, X, Y, Z, Q);
+        const double mx = max8(mass);
+        if ((t & 7) == 0) {
+            const int b = t >> 3, id = L.bot_first + b;
+            store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], FLAG_BOTTOM, mx);
+            bM[b] = M;
+            bX[b] = M > 0.0 ? X : geom[4 * (int64_t)id + 0];
+            bY[b] = M > 0.0 ? Y : geom[4 * (int64_t)id + 1];
+            bZ[b] = M > 0.0 ? Z : geom[4 * (int64_t)id + 2];
+            for (int q = 0; q < 6; q++) bQ[b][q] = M > 0.0 ? Q[q] : 0.0;
+            bmax[b] = mx;
+        }
     }
     __syncthreads();
-    if (t == 0) {
-        double M, X, Y, Z, Q[6];
-        combine8(oM, oX, oY, oZ, oQ, M, X, Y, Z, Q);
-        int id = L.block_node;
-        store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], 0);
-    }
-}
-
-__device__ __forceinline__ void combine_node(int id, const double *__restrict__ geom,
-                                             const int32_t *__restrict__ child_arr, const MomOut &out) {
-    const int first = child_arr[id];
-    double Mc[8], Xc[8], Yc[8], Zc[8], Qc[8][6];
-    for (int c = 0; c < 8; c++) {
-        const double *mo = out.mom + (int64_t)(first + c) * kMom;
-        Mc[c] = mo[3];
-        Xc[c] = mo[0];
-        Yc[c] = mo[1];
-        Zc[c] = mo[2];
-        for (int k = 0; k < 6; k++) Qc[c][k] = mo[4 + k];
-    }
+    if (t >= 64) return;
+    // octant t >> 3 from its 8 bottom nodes (lane t holds bottom node t)
     double M, X, Y, Z, Q[6];
-    combine8(Mc, Xc, Yc, Zc, Qc, M, X, Y, Z, Q);
-    store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, first, 0);
+    combine_lanes(bM[t], bX[t], bY[t], bZ[t], bQ[t], M, X, Y, Z, Q);
+    const double mx = max8(bmax[t]);
+    const int o = t >> 3;
+    const int oid = L.oct_first + o;
+    if ((t & 7) == 0) store_node(out, oid, M, X, Y, Z, Q, geom + 4 * (int64_t)oid, child_arr[oid], 0, mx);
+    // block node from the 8 octants: lane c of the first group takes octant c
+    const double e = M > 0.0 ? 1.0 : 0.0;
+    const double oX = M > 0.0 ? X : geom[4 * (int64_t)oid + 0];
+    const double oY = M > 0.0 ? Y : geom[4 * (int64_t)oid + 1];
+    const double oZ = M > 0.0 ? Z : geom[4 * (int64_t)oid + 2];
+    const int src = 8 * (t & 7);
+    double oq[6];
+    for (int q = 0; q < 6; q++) oq[q] = __shfl(Q[q] * e, src, 64);
+    double BM, BX, BY, BZ, BQ[6];
+    combine_lanes(__shfl(M, src, 64), __shfl(oX, src, 64), __shfl(oY, src, 64), __shfl(oZ, src, 64), oq, BM, BX, BY,
+                  BZ, BQ);
+    if (t != 0) return;
+    const int node = L.block_node;
+    store_node(out, node, BM, BX, BY, BZ, BQ, geom + 4 * (int64_t)node, child_arr[node], 0);
 }
 
-// One tree depth of parent-block / virtual nodes (used when there are many).
-__global__ __launch_bounds__(256) void moments_combine_kernel(const int32_t *__restrict__ nodes, int64_t count,
-                                                              const double *__restrict__ geom,
-                                                              const int32_t *__restrict__ child_arr, MomOut out) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= count) return;
-    combine_node(nodes[q], geom, child_arr, out);
-}
-
-// All depths in one workgroup, deepest first, a barrier between depths (the
-// usual case: a few hundred to a few thousand nodes above the leaf blocks).
+// Nodes above the leaf blocks (virtual and parent-block nodes, 8 node
+// children each) in one workgroup, deepest depth first with a barrier between
+// depths: 8 lanes per node, lane c loads child c's row, and the node combines
+// by lane shuffles.  The leaf blocks' rows come from the previous launch.
 __global__ __launch_bounds__(1024) void moments_levels_kernel(const int32_t *__restrict__ nodes,
                                                               const int64_t *__restrict__ off, int nbuckets,
                                                               const double *__restrict__ geom,
                                                               const int32_t *__restrict__ child_arr, MomOut out) {
+#pragma clang fp contract(off)
+    const int c = threadIdx.x & 7;
     for (int b = 0; b < nbuckets; b++) {
-        for (int64_t q = off[b] + threadIdx.x; q < off[b + 1]; q += blockDim.x) combine_node(nodes[q], geom, child_arr, out);
+        const int64_t end = off[b + 1];
+        // whole groups of 8 lanes iterate together, so the shuffles see all 8
+        for (int64_t q0 = off[b]; q0 < end; q0 += blockDim.x / 8) {
+            const int64_t q = q0 + (threadIdx.x >> 3);
+            const bool live = q < end;
+            const int id = live ? nodes[q] : 0;
+            const int first = live ? child_arr[id] : 0;
+            double m = 0.0, x = 0.0, y = 0.0, z = 0.0, qc[6] = {0, 0, 0, 0, 0, 0};
+            if (live) {
+                const double *mo = out.mom + (int64_t)(first + c) * kMom;
+                x = mo[0];
+                y = mo[1];
+                z = mo[2];
+                m = mo[3];
+                for (int k = 0; k < 6; k++) qc[k] = mo[4 + k];
+            }
+            double M, X, Y, Z, Q[6];
+            combine_lanes(m, x, y, z, qc, M, X, Y, Z, Q);
+            if (live && c == 0) store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, first, 0);
+        }
         __syncthreads();
     }
+}
+
+// One tree depth of the nodes above the leaf blocks, for grids with more of
+// them than one workgroup handles well.
+__global__ __launch_bounds__(256) void moments_combine_kernel(const int32_t *__restrict__ nodes, int64_t count,
+                                                              const double *__restrict__ geom,
+                                                              const int32_t *__restrict__ child_arr, MomOut out) {
+#pragma clang fp contract(off)
+    const int c = threadIdx.x & 7;
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const bool live = q < count;
+    const int id = live ? nodes[q] : 0;
+    const int first = live ? child_arr[id] : 0;
+    double m = 0.0, x = 0.0, y = 0.0, z = 0.0, qc[6] = {0, 0, 0, 0, 0, 0};
+    if (live) {
+        const double *mo = out.mom + (int64_t)(first + c) * kMom;
+        x = mo[0];
+        y = mo[1];
+        z = mo[2];
+        m = mo[3];
+        for (int k = 0; k < 6; k++) qc[k] = mo[4 + k];
+    }
+    double M, X, Y, Z, Q[6];
+    combine_lanes(m, x, y, z, qc, M, X, Y, Z, Q);
+    if (live && c == 0) store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, first, 0);
 }
 
 constexpr int64_t kSingleWorkgroupCombine = 16384;
@@ -270,12 +280,11 @@ hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hi
         return hipGetLastError();
     }
     for (int b = 0; b < nb; b++) {
-        int64_t cnt = off[b + 1] - off[b];
-        int blocks = (int)((cnt + 255) / 256);
+        const int64_t cnt = off[b + 1] - off[b];
+        const int blocks = (int)((8 * cnt + 255) / 256);
         hipLaunchKernelGGL(moments_combine_kernel, dim3(blocks), dim3(256), 0, s, g->d_combine + off[b], cnt,
                            g->d_geom, g->d_child, o);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -683,6 +692,52 @@ __device__ __forceinline__ double near_pair_self(double px, double py, double pz
     return r2 > 0.0 ? part + s.w * rsqrt64(r2) : part;
 }
 
+__device__ __forceinline__ float rsq_any(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_any(double x) { return rsqrt64(x); }
+
+// Potential and acceleration of one far node (monopole + quadrupole) at one
+// cell: the gradient of the far term taken term by term.  The staged record
+// holds the full Q: p = (X, Y, Z, M), q = (Qxx, Qyy, Qzz, Qxy), u = (Qxz, Qyz,
+// -, -).  Accumulates the bracket of phi = -G [M/d + R^T Q R / (2 d^5)] into
+// phi and of g = G [Q R / d^5 - (M / d^3 + 5/2 R^T Q R / d^7) R] into g.
+template <typename real, typename V4>
+__device__ __forceinline__ void far_term_acc(real px, real py, real pz, const V4 p, const V4 q, const V4 u, real &phi,
+                                             real &gx, real &gy, real &gz) {
+    const real dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    const real ri = rsq_any(r2);
+    const real ri2 = ri * ri;
+    const real qx = q.x * dx + q.w * dy + u.x * dz;
+    const real qy = q.w * dx + q.y * dy + u.y * dz;
+    const real qz = u.x * dx + u.y * dy + q.z * dz;
+    const real rqr = dx * qx + dy * qy + dz * qz;
+    const real ri3 = ri * ri2;
+    const real w5 = ri3 * ri2;
+    const real t5 = rqr * w5;
+    phi += p.w * ri + (real)0.5 * t5;
+    const real s = p.w * ri3 + (real)2.5 * (t5 * ri2);
+    gx += w5 * qx - s * dx;
+    gy += w5 * qy - s * dy;
+    gz += w5 * qz - s * dz;
+}
+
+// Potential and acceleration of one near cell (none for the cell itself when
+// SELF: a zero distance contributes nothing).
+template <typename real, bool SELF, typename V4>
+__device__ __forceinline__ void near_pair_acc(real px, real py, real pz, const V4 c, real &phi, real &gx, real &gy,
+                                              real &gz) {
+    const real dx = px - c.x, dy = py - c.y, dz = pz - c.z;
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    const real r0 = rsq_any(r2);
+    const real ri = SELF ? (r2 > (real)0 ? r0 : (real)0) : r0;  // the cell itself: 1/d -> 0, not inf
+    const real mri = c.w * ri;
+    const real w = mri * ri * ri;
+    phi += mri;
+    gx -= w * dx;
+    gy -= w * dy;
+    gz -= w * dz;
+}
+
 // Per-wavefront tile evaluation.  Far tile: up to 64 node records (3 x V4
 // each) staged in T by lane, then read back by every lane as broadcasts.
 // Near tile: up to 8 bottom nodes = 64 cells.  Each tile is summed in `real`
@@ -699,12 +754,15 @@ struct Tiles {
     int own_lo;
     double acc_far, acc_near;
 
+    __device__ void init() { acc_far = acc_near = 0.0; }
+
+    __device__ void put(int lane, const V4 a, const V4 b, const V4 c) {
+        T[3 * lane + 0] = a;
+        T[3 * lane + 1] = b;
+        T[3 * lane + 2] = c;
+    }
     __device__ void stage_far(int lane, int n, int id) {
-        if (lane < n) {
-            T[3 * lane + 0] = rec[3 * (int64_t)id + 0];
-            T[3 * lane + 1] = rec[3 * (int64_t)id + 1];
-            T[3 * lane + 2] = rec[3 * (int64_t)id + 2];
-        }
+        if (lane < n) put(lane, rec[3 * (int64_t)id + 0], rec[3 * (int64_t)id + 1], rec[3 * (int64_t)id + 2]);
         wave_lds_sync();
     }
     __device__ void sum_far(int n) {
@@ -729,6 +787,73 @@ struct Tiles {
             for (int j = 0; j < 8 * n; j++) part = near_pair_self(me.x, me.y, me.z, T[j], part);
         acc_near += (double)part;
         wave_lds_sync();
+    }
+    __device__ void finish(const WalkArgs &a, int64_t cell) const { a.phi[cell] = -a.G * (acc_far + acc_near); }
+};
+
+// The same tiles for the acceleration kernels: potential and acceleration per
+// pair, each tile summed in `real` and folded into fp64 accumulators.  The
+// fp32 far records keep Q/2 on the diagonal; the staged copy gets the full Q.
+template <typename real>
+struct TilesAcc {
+    using V4 = typename Prec<real>::V4;
+    V4 *T;
+    const V4 *rec;
+    const V4 *cells;
+    const int32_t *child;
+    V4 me;
+    int own_lo;
+    double phi, gx, gy, gz;
+
+    __device__ void init() { phi = gx = gy = gz = 0.0; }
+    __device__ static V4 full_q(const V4 q) {
+        if constexpr (sizeof(real) == 4)
+            return make_float4(2.0f * q.x, 2.0f * q.y, 2.0f * q.z, q.w);
+        else
+            return q;
+    }
+    __device__ void put(int lane, const V4 a, const V4 b, const V4 c) {
+        T[3 * lane + 0] = a;
+        T[3 * lane + 1] = full_q(b);
+        T[3 * lane + 2] = c;
+    }
+    __device__ void stage_far(int lane, int n, int id) {
+        if (lane < n) put(lane, rec[3 * (int64_t)id + 0], rec[3 * (int64_t)id + 1], rec[3 * (int64_t)id + 2]);
+        wave_lds_sync();
+    }
+    __device__ void sum_far(int n) {
+        real p = 0, x = 0, y = 0, z = 0;
+        for (int j = 0; j < n; j++) far_term_acc<real>(me.x, me.y, me.z, T[3 * j], T[3 * j + 1], T[3 * j + 2], p, x, y, z);
+        phi += (double)p;
+        gx += (double)x;
+        gy += (double)y;
+        gz += (double)z;
+        wave_lds_sync();
+    }
+    __device__ void near_tile(int lane, int n, int id) {
+        bool own = false;
+        if (lane < 8 * n) {
+            own = (unsigned)(id - own_lo) < 8u;
+            T[lane] = cells[(int64_t)child[id] + (lane & 7)];
+        }
+        const bool any_own = __ballot(own) != 0;
+        wave_lds_sync();
+        real p = 0, x = 0, y = 0, z = 0;
+        if (!any_own)
+            for (int j = 0; j < 8 * n; j++) near_pair_acc<real, false>(me.x, me.y, me.z, T[j], p, x, y, z);
+        else
+            for (int j = 0; j < 8 * n; j++) near_pair_acc<real, true>(me.x, me.y, me.z, T[j], p, x, y, z);
+        phi += (double)p;
+        gx += (double)x;
+        gy += (double)y;
+        gz += (double)z;
+        wave_lds_sync();
+    }
+    __device__ void finish(const WalkArgs &a, int64_t cell) const {
+        if (a.phi) a.phi[cell] = -a.G * phi;
+        a.acc[3 * cell + 0] = a.G * gx;
+        a.acc[3 * cell + 1] = a.G * gy;
+        a.acc[3 * cell + 2] = a.G * gz;
     }
 };
 
@@ -818,13 +943,13 @@ hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_list
 // the next walk step, whose own node loads then cover that latency, and are
 // summed after it.  Launch bounds set the waves per SIMD (and so the register
 // budget) that hide the walk's remaining load latency best.
-#ifndef BH_FUSED_WAVES_FP32
-#define BH_FUSED_WAVES_FP32 6
-#endif
-template <typename real>
-struct FusedWaves {
-    static constexpr int value = sizeof(real) == 4 ? BH_FUSED_WAVES_FP32 : 4;
-};
+// Kernel variants by register budget: waves per SIMD the compiler must fit
+// (256 VGPRs per SIMD lane / waves).  More waves hide more of the walk's load
+// latency, fewer leave more registers to the pipelined far tile; the default
+// of each precision is the fastest single-grid variant, and batched solves
+// may pick another one.
+constexpr int kFusedDefaultWaves32 = 8;
+constexpr int kFusedDefaultWaves64 = 4;
 
 template <typename real>
 struct FusedSmem {
@@ -835,23 +960,23 @@ struct FusedSmem {
     V4 tile[4][64 * 3];
 };
 
-// one group g of the grid described by a, on wavefront w of the workgroup
-template <typename real>
+// one group g of the grid described by a, on wavefront w of the workgroup;
+// TL: the tile evaluator (potential, or potential and acceleration)
+template <typename real, typename TL = Tiles<real>>
 __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w, int lane, FusedSmem<real> &sm) {
     using V4 = typename Prec<real>::V4;
     const int f = (int)(g >> 3), sub = (int)(g & 7);
     const LeafInfo L = a.leaves[f];
     Walker<real> W;
     W.init(a, L, sub, sm.stack[w], lane);
-    Tiles<real> S;
+    TL S;
     S.T = sm.tile[w];
     S.rec = (const V4 *)a.far_rec;
     S.cells = (const V4 *)a.cells;
     S.child = a.child;
     S.own_lo = L.bot_first + sub * 8;
     S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
-    S.acc_far = 0.0;
-    S.acc_near = 0.0;
+    S.init();
     int *FB = sm.fbuf[w];
     int *NB = sm.nbuf[w];
     int fcnt = 0, ncnt = 0, ftot = 0, ntot = 0;
@@ -862,9 +987,7 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
         bool acc, nr;
         W.step(lane, id, acc, nr);
         if (pending) {  // loaded before the step: sum it now
-            S.T[3 * lane + 0] = p0;
-            S.T[3 * lane + 1] = p1;
-            S.T[3 * lane + 2] = p2;
+            S.put(lane, p0, p1, p2);
             wave_lds_sync();
             S.sum_far(64);
             pending = false;
@@ -903,9 +1026,7 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
     }
     W.finish(a, lane);
     if (pending) {
-        S.T[3 * lane + 0] = p0;
-        S.T[3 * lane + 1] = p1;
-        S.T[3 * lane + 2] = p2;
+        S.put(lane, p0, p1, p2);
         wave_lds_sync();
         S.sum_far(64);
     }
@@ -924,7 +1045,7 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
         S.sum_far(fcnt);
     }
     if (ncnt > 0) S.near_tile(lane, ncnt, lane < 8 * ncnt ? NB[lane >> 3] : 0);
-    a.phi[phi_index(L, sub, lane)] = -a.G * (S.acc_far + S.acc_near);
+    S.finish(a, phi_index(L, sub, lane));
     if (a.counts && lane == 0) {
         const int64_t cg = (int64_t)L.canon * 8 + sub;
         a.counts[2 * cg + 0] = ftot;
@@ -932,8 +1053,8 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
     }
 }
 
-template <typename real>
-__global__ __launch_bounds__(256, FusedWaves<real>::value) void walk_potential_kernel(WalkArgs a) {
+template <typename real, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void walk_potential_kernel(WalkArgs a) {
     __shared__ FusedSmem<real> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -942,13 +1063,39 @@ __global__ __launch_bounds__(256, FusedWaves<real>::value) void walk_potential_k
     fused_group<real>(a, g, w, lane, sm);
 }
 
+// Walk fused with the potential and acceleration sums.  More live values than
+// the potential kernel, hence a smaller register budget per wave.
+constexpr int kAccelWaves32 = 6;
+constexpr int kAccelWaves64 = 4;
+template <typename real, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void walk_accel_kernel(WalkArgs a) {
+    __shared__ FusedSmem<real> sm;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    fused_group<real, TilesAcc<real>>(a, g, w, lane, sm);
+}
+
+hipError_t launch_walk_accel(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                             int precision, double G, double *phi, double *acc, int32_t *counts, hipStream_t s) {
+    WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
+    a.acc = acc;
+    const int blocks = (int)((g->n_groups + 3) / 4);
+    if (precision == BH_FP64)
+        hipLaunchKernelGGL((walk_accel_kernel<double, kAccelWaves64>), dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((walk_accel_kernel<float, kAccelWaves32>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // Many grids in one persistent launch: every wavefront takes the next
 // (grid, group) item of `order` from an atomic counter until the queue is
 // empty, so uneven grids and groups balance themselves; with `order` sorted
 // by decreasing cost the longest groups start first.  Every wave exits once
 // the counter passes `total`.
-template <typename real>
-__global__ __launch_bounds__(256, FusedWaves<real>::value) void batch_walk_potential_kernel(
+template <typename real, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void batch_walk_potential_kernel(
     const WalkArgs *__restrict__ grids, const int2 *__restrict__ order, int64_t total,
     unsigned long long *__restrict__ counter) {
     __shared__ FusedSmem<real> sm;
@@ -957,7 +1104,11 @@ __global__ __launch_bounds__(256, FusedWaves<real>::value) void batch_walk_poten
     while (true) {
         unsigned long long q = 0;
         if (lane == 0) q = atomicAdd(counter, 1ull);
-        q = __shfl(q, 0, 64);
+        // lane 0's item, read as a wave-uniform value: the item and its grid's
+        // arguments then live in scalar registers, not in 64 copies
+        const uint32_t qlo = __builtin_amdgcn_readfirstlane((uint32_t)q);
+        const uint32_t qhi = __builtin_amdgcn_readfirstlane((uint32_t)(q >> 32));
+        q = ((unsigned long long)qhi << 32) | qlo;
         if (q >= (unsigned long long)total) break;
         const int2 item = order[q];
         fused_group<real>(grids[item.x], item.y, w, lane, sm);
@@ -980,9 +1131,9 @@ hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double t
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     const int blocks = (int)((g->n_groups + 3) / 4);
     if (precision == BH_FP64)
-        hipLaunchKernelGGL(walk_potential_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((walk_potential_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(walk_potential_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((walk_potential_kernel<float, kFusedDefaultWaves32>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1003,20 +1154,40 @@ hipError_t launch_batch_reset(const WalkArgs *grids, int n, unsigned long long *
 }
 
 hipError_t launch_batch_walk_potential(const WalkArgs *grids, const int2 *order, int64_t total,
-                                       unsigned long long *counter, int precision, int workgroups, hipStream_t s) {
-    if (precision == BH_FP64)
-        hipLaunchKernelGGL(batch_walk_potential_kernel<double>, dim3(workgroups), dim3(256), 0, s, grids, order, total,
-                           counter);
-    else
-        hipLaunchKernelGGL(batch_walk_potential_kernel<float>, dim3(workgroups), dim3(256), 0, s, grids, order, total,
-                           counter);
+                                       unsigned long long *counter, int precision, int waves, int workgroups,
+                                       hipStream_t s) {
+    const dim3 grid(workgroups), block(256);
+#define BH_BATCH_LAUNCH(T, W) \
+    hipLaunchKernelGGL((batch_walk_potential_kernel<T, W>), grid, block, 0, s, grids, order, total, counter)
+    if (precision == BH_FP64) {
+        switch (waves) {
+            case 2: BH_BATCH_LAUNCH(double, 2); break;
+            case 4: BH_BATCH_LAUNCH(double, 4); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (waves) {
+            case 4: BH_BATCH_LAUNCH(float, 4); break;
+            case 6: BH_BATCH_LAUNCH(float, 6); break;
+            case 8: BH_BATCH_LAUNCH(float, 8); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+#undef BH_BATCH_LAUNCH
     return hipGetLastError();
 }
 
-int fused_waves_per_simd(int precision) { return precision == BH_FP64 ? 4 : BH_FUSED_WAVES_FP32; }
+int fused_waves_per_simd(int precision) { return precision == BH_FP64 ? kFusedDefaultWaves64 : kFusedDefaultWaves32; }
+
+bool fused_variant_exists(int precision, int waves) {
+    return precision == BH_FP64 ? (waves == 2 || waves == 4) : (waves == 4 || waves == 6 || waves == 8);
+}
 
 // ---------------------------------------------------------------- direct
 
+// ACC: out[3 t + k] = -G sum_{j != i} m_j (r_i - r_j)_k / |r_i - r_j|^3
+// (acceleration) instead of the potential.
+template <bool ACC>
 __global__ __launch_bounds__(256) void direct_kernel(const int64_t *__restrict__ targets, int64_t n,
                                                      const double4 *__restrict__ cells, int64_t ncells,
                                                      const int32_t *__restrict__ internal_of_canon, double G,
@@ -1038,29 +1209,51 @@ __global__ __launch_bounds__(256) void direct_kernel(const int64_t *__restrict__
             ok = true;
         }
     }
-    double acc = 0.0;
+    double acc = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
     for (int64_t base = 0; base < ncells; base += 256) {
         __syncthreads();
         tile[threadIdx.x] = cells[base + threadIdx.x];  // ncells is a multiple of 512
         __syncthreads();
-        double part = 0.0;
+        double part = 0.0, px = 0.0, py = 0.0, pz = 0.0;
         for (int j = 0; j < 256; j++) {
             const double4 s = tile[j];
             const double dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            if (base + j != self) part += s.w / sqrt(r2);
+            if (base + j == self) continue;
+            if (ACC) {
+                const double w = s.w / (r2 * sqrt(r2));
+                px -= w * dx;
+                py -= w * dy;
+                pz -= w * dz;
+            } else {
+                part += s.w / sqrt(r2);
+            }
         }
         acc += part;
+        ax += px;
+        ay += py;
+        az += pz;
     }
-    if (valid) phi[t] = ok ? -G * acc : __builtin_nan("");
+    if (!valid) return;
+    if (ACC) {
+        phi[3 * t + 0] = ok ? G * ax : __builtin_nan("");
+        phi[3 * t + 1] = ok ? G * ay : __builtin_nan("");
+        phi[3 * t + 2] = ok ? G * az : __builtin_nan("");
+    } else {
+        phi[t] = ok ? -G * acc : __builtin_nan("");
+    }
 }
 
 hipError_t launch_direct(const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,
-                         double *phi, hipStream_t s) {
+                         double *out, bool accel, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int blocks = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(direct_kernel, dim3(blocks), dim3(256), 0, s, targets, n, m->d_cell64, g->n_cells,
-                       g->d_internal_of_canon, G, phi);
+    if (accel)
+        hipLaunchKernelGGL(direct_kernel<true>, dim3(blocks), dim3(256), 0, s, targets, n, m->d_cell64, g->n_cells,
+                           g->d_internal_of_canon, G, out);
+    else
+        hipLaunchKernelGGL(direct_kernel<false>, dim3(blocks), dim3(256), 0, s, targets, n, m->d_cell64, g->n_cells,
+                           g->d_internal_of_canon, G, out);
     return hipGetLastError();
 }
 

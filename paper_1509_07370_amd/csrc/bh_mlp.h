@@ -22,6 +22,7 @@ struct bh_mlp {
     bh_ctx *ctx = nullptr;
     float *d_params = nullptr;   // [kMlpParams]
     uint16_t *d_bf16 = nullptr;  // bf16 copy of the parameters
+    uint16_t *d_w2t = nullptr;   // bf16 W2 transposed, [k][u] = W2[u][k] (inference staging)
     float *d_mean = nullptr, *d_scale = nullptr;  // [kMlpIn]
     float *d_m = nullptr, *d_v = nullptr;         // Adam moments
     float *d_partials = nullptr;                  // [kMlpChunks][kMlpParams + 1]

@@ -64,6 +64,7 @@ int bh_mlp_destroy(bh_mlp *net) {
     if (net->ctx && net->ctx->device >= 0) (void)hipSetDevice(net->ctx->device);
     hfree(net->d_params);
     hfree(net->d_bf16);
+    hfree(net->d_w2t);
     hfree(net->d_mean);
     hfree(net->d_scale);
     hfree(net->d_m);
@@ -89,6 +90,7 @@ int bh_mlp_create(bh_ctx *ctx, bh_mlp **out, const float *params, const float *m
     hipError_t e;
     if ((e = hipMalloc((void **)&n->d_params, P * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_bf16, P * sizeof(uint16_t))) != hipSuccess ||
+        (e = hipMalloc((void **)&n->d_w2t, bh::kMlpHidden * bh::kMlpHidden * sizeof(uint16_t))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_mean, bh::kMlpIn * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_scale, bh::kMlpIn * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_m, P * sizeof(float))) != hipSuccess ||

@@ -76,6 +76,16 @@ class BarnesHut:
         B.bh_walk_potential(self.ctx, self.grid, self.m, theta, theta_group, precision, G, phi, counts)
         return phi
 
+    def solve_accel(self, rho: torch.Tensor, theta=0.5, theta_group=None, precision=B.BH_FP32, G=1.0, acc=None,
+                    phi=None, counts=None):
+        """moments -> fused walk + potential and acceleration sums; returns acc [n_leaf, 8, 8, 8, 3]
+        (phi, if given, receives the potential of the same pass)."""
+        if acc is None:
+            acc = torch.empty(rho.shape + (3,), dtype=torch.float64, device=rho.device)
+        self.build_moments(rho)
+        B.bh_walk_accel(self.ctx, self.grid, self.m, theta, theta_group, precision, G, phi, acc, counts)
+        return acc
+
     def check(self):
         B.bh_moments_check(self.ctx, self.m)
 
@@ -83,6 +93,11 @@ class BarnesHut:
         if out is None:
             out = torch.empty(targets.numel(), dtype=torch.float64, device=targets.device)
         return B.bh_direct(self.ctx, self.grid, self.m, targets, G, out)
+
+    def direct_accel(self, targets: torch.Tensor, G=1.0, out=None):
+        if out is None:
+            out = torch.empty((targets.numel(), 3), dtype=torch.float64, device=targets.device)
+        return B.bh_direct_accel(self.ctx, self.grid, self.m, targets, G, out)
 
     # ---- host copies for tests and reports
     def node_keys(self):

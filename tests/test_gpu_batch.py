@@ -108,3 +108,53 @@ def test_invalid_density_is_reported_per_replay(batch):
     assert ei.value.code == B.BH_EINVAL and "grid 3" in str(ei.value)
     B.bh_batch_solve(ctx, b, rho, phi, 0.5, None, B.BH_FP32, 1.0)
     B.bh_batch_check(ctx, b)
+
+
+def test_launch_configurations_and_autotuner(batch):
+    """Order, width and kernel variant keep the bits; a lower stack limit keeps
+    the far/near sets (counts) and changes only the summation order."""
+    grids, solvers, ctx, handles, b, rho = batch
+    ref = _reference(solvers, rho, 0.7, B.BH_FP32)
+    phi = [torch.empty_like(r) for r in rho]
+    B.bh_batch_solve(ctx, b, rho, phi, 0.7, None, B.BH_FP32, 1.0)
+    ref_counts = B.bh_batch_counts(ctx, b)
+    for cfg in (dict(order=B.BH_ORDER_COST, workgroups_per_cu=2, waves_per_simd=4, stack_limit=0),
+                dict(order=B.BH_ORDER_NATURAL, workgroups_per_cu=0, waves_per_simd=6, stack_limit=0),
+                dict(order=B.BH_ORDER_COST, workgroups_per_cu=1, waves_per_simd=8, stack_limit=0),
+                dict(order=B.BH_ORDER_NATURAL, workgroups_per_cu=3, waves_per_simd=8, stack_limit=8),
+                dict(order=B.BH_ORDER_COST, workgroups_per_cu=0, waves_per_simd=6, stack_limit=64)):
+        B.bh_batch_configure(ctx, b, **cfg)
+        assert B.bh_batch_get_config(b) == cfg
+        for p in phi:
+            p.fill_(float("nan"))
+        B.bh_batch_solve(ctx, b, rho, phi, 0.7, None, B.BH_FP32, 1.0)
+        B.bh_batch_check(ctx, b)
+        assert np.array_equal(B.bh_batch_counts(ctx, b), ref_counts)
+        for p, q in zip(phi, ref):
+            if cfg["stack_limit"] == 0:
+                assert torch.equal(p, q)
+            else:
+                assert float(((p - q) / q).abs().max()) <= 1e-5
+    # fp64 variants; an fp32-only variant is refused for an fp64 solve
+    ref64 = _reference(solvers, rho, 0.7, B.BH_FP64)
+    for waves in (2, 4):
+        B.bh_batch_configure(ctx, b, waves_per_simd=waves)
+        B.bh_batch_solve(ctx, b, rho, phi, 0.7, None, B.BH_FP64, 1.0)
+        for p, q in zip(phi, ref64):
+            assert torch.equal(p, q)
+    B.bh_batch_configure(ctx, b, waves_per_simd=6)
+    with pytest.raises(B.BHError):
+        B.bh_batch_solve(ctx, b, rho, phi, 0.7, None, B.BH_FP64, 1.0)
+    for bad in (dict(waves_per_simd=5), dict(stack_limit=4), dict(order=7), dict(workgroups_per_cu=65)):
+        with pytest.raises(B.BHError):
+            B.bh_batch_configure(ctx, b, **bad)
+    # the autotuner tries every candidate and leaves the best one applied
+    best, best_ms, table = B.bh_batch_autotune(ctx, b, rho, phi, 0.7, None, B.BH_FP32, 1.0, reps=1)
+    assert len(table) == 36 and best_ms > 0
+    assert best_ms == min(t for _, t in table)
+    assert B.bh_batch_get_config(b) == best
+    B.bh_batch_solve(ctx, b, rho, phi, 0.7, None, B.BH_FP32, 1.0)
+    B.bh_batch_check(ctx, b)
+    for p, q in zip(phi, ref):
+        assert float(((p - q) / q).abs().max()) <= 1e-5
+    B.bh_batch_configure(ctx, b)

@@ -135,3 +135,39 @@ def test_benchmark_mesh_in_bench_configuration():
     assert float(torch.sqrt((rel * rel).mean())) <= 1e-3
     net.close()
     bh.close()
+
+
+def test_benchmark_mesh_accelerations():
+    """bh_walk_accel at theta 1.0, fp32, on the benchmark mesh: sampled groups
+    against the oracle (cell scale as in test_gpu_accel), and the method's own
+    acceleration error against the exact direct sum on sampled cells."""
+    g = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    t = OracleTree(g)
+    acc = torch.empty(g.rho.shape + (3,), dtype=torch.float64, device="cuda")
+    counts = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_walk_accel(bh.ctx, bh.grid, bh.m, 1.0, None, B.BH_FP32, 1.0, None, acc, counts)
+    bh.check()
+    c = counts.cpu().numpy()
+    groups = _sample_groups(ng, c, seed=3)
+    ref, oc = t.solve_groups_accel(groups, theta=1.0, tau=TAU[B.BH_FP32])
+    got = acc.reshape(-1, 3).cpu().numpy()[_morton_cells(groups)]
+    n = np.linalg.norm(ref, axis=-1)
+    scale = np.maximum(n, 0.1 * np.sqrt((n * n).mean()))
+    err = (np.linalg.norm(got - ref, axis=-1) / scale).max(axis=1)
+    marginal = oc[:, 3] > 0
+    assert np.all(err[~marginal] <= 1e-5), err[~marginal].max()
+    assert (err > 1e-5).sum() <= 3
+    rng = np.random.default_rng(6)
+    tg = torch.tensor(np.sort(rng.choice(g.ncells, 4000, replace=False)), dtype=torch.int64, device="cuda")
+    d = torch.empty((tg.numel(), 3), dtype=torch.float64, device="cuda")
+    B.bh_direct_accel(bh.ctx, bh.grid, bh.m, tg, 1.0, d)
+    a = acc.reshape(-1, 3).index_select(0, tg)
+    rel = torch.linalg.norm(a - d, dim=1) / torch.linalg.norm(d, dim=1)
+    rms = float(torch.sqrt((rel * rel).mean()))
+    print("[accel] theta 1.0 fp32: rms relative acceleration error %.3e, max %.3e" % (rms, float(rel.max())))
+    assert rms <= 1e-2
+    bh.close()

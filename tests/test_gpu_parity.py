@@ -71,6 +71,37 @@ def test_moments_parity(name):
     assert np.max(np.abs(gm["delta"] - d)) <= 4e-15 * g.box_size
 
 
+def _check_moments(g, gm, om, keys):
+    idx = _by_key(keys, om["key"])
+    M, X, Q, d = om["M"][idx], om["X"][idx], om["Q"][idx], om["delta"][idx]
+    l = om["edge"][idx]
+    assert np.all(np.abs(gm["M"] - M) <= 1e-13 * M)
+    assert np.max(np.abs(gm["X"] - X)) <= 4e-15 * g.box_size
+    assert np.all(np.abs(gm["Q"] - Q) <= 1e-13 * (M * l * l)[:, None] + 1e-300)
+    assert np.max(np.abs(gm["delta"] - d)) <= 4e-15 * g.box_size
+
+
+@pytest.mark.parametrize("seed,nbase,max_level", [(33, 2, 4), (34, 1, 5), (35, 4, 2)])
+def test_repeated_upward_passes(seed, nbase, max_level):
+    """Upward passes in a row, with densities that change (zero blocks
+    included), on deep and shallow trees: each must give the oracle's moments
+    (nothing may carry over between calls)."""
+    g = random_amr(seed, nbase=nbase, max_level=max_level, p_refine=0.35, zero_fraction=0.1)
+    bh = BarnesHut(g)
+    keys = bh.node_keys()
+    t = OracleTree(g)
+    rng = np.random.default_rng(seed)
+    for rep in range(4):
+        rho_h = g.rho.copy() if rep == 0 else g.rho * rng.uniform(0.5, 2.0, size=g.rho.shape)
+        if rep == 3:
+            rho_h[::3] = 0.0
+        bh.build_moments(torch.tensor(rho_h, device="cuda"))
+        bh.check()
+        t.set_density(rho_h)
+        _check_moments(g, bh.moments_host(), t.moments(), keys)
+    bh.close()
+
+
 def _gpu_lists_as_keys(bh, keys):
     L = bh.lists_host()
     return L["far_off"], keys[L["far_node"]], L["near_off"], keys[L["near_node"]]
