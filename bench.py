@@ -45,21 +45,32 @@ F_FAR_ACC = 55              # flop per (cell, far node) pair with potential + ac
 F_NEAR_ACC = 19             # flop per (cell, near cell) pair with potential + acceleration
 RMS_GATE = 1e-3
 WEIGHTS = os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz")
-PROFILE = os.path.join(ROOT, "profiles", "walk_potential_fp32_maclaurin_1p4M.md")
+PROFILE = os.path.join(ROOT, "profiles", "walk_potential_learned_fp32_maclaurin_1p4M.md")
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("bh_kernels.hip", "bh_theta_net.h", "bh_internal.h", "bh_device.h")
+
+
+def kernel_source_sha256():
+    """SHA-256 over the sources the dominant kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1509_07370_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def profiled_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    summary, or None when the kernel source has changed since it was taken."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_1509_07370_amd", "csrc", "bh_kernels.hip")
+    summary, or None when the kernel's sources have changed since it was taken."""
     try:
         text = open(PROFILE).read()
-        want = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        want = kernel_source_sha256()
     except OSError:
         return None
     fields = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("traffic_bytes_per_launch:",
@@ -324,7 +335,7 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3 / reps
 
-    sweep, fixed, learned = [], {}, {}
+    sweep, fixed, learned, ablation = [], {}, {}, {}
     if not args.profile_only:
         bh.build_moments(rho)
         t0 = time.time()
@@ -352,6 +363,33 @@ def main():
             sweep.append(dict(theta=th, precision="fp64", rms_rel_err=rms, max_rel_err=mx, ms_per_step=ms,
                               mcells_per_s=ncells / ms / 1e3))
         fp64 = [s for s in sweep if s["precision"] == "fp64" and s["theta"] == th_best][0]
+        # the paper's own opening test (group cube) and far field (monopole), each at its own
+        # largest theta meeting the gate, fp32: what this library's choices gain over them
+        for name, mac, order in (("group_box_monopole", B.BH_MAC_GROUP_BOX, 0),
+                                 ("group_box_quadrupole", B.BH_MAC_GROUP_BOX, 2),
+                                 ("cell_vote_monopole", B.BH_MAC_CELLS, 0)):
+            def step_opts(theta, mac=mac, order=order):
+                bh.build_moments(rho)
+                B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, theta, None, B.BH_FP32, 1.0, phi, None, mac=mac,
+                                       order=order)
+            ok_th = None
+            for th in LT.THETA_GRID:
+                step_opts(float(th))
+                if errors()[0] <= RMS_GATE:
+                    ok_th = float(th)
+            if ok_th is None:
+                ablation[name] = dict(theta=None)
+                continue
+            step_opts(ok_th)
+            rms, mx = errors()
+            ms = timed(lambda: step_opts(ok_th), 5)
+            ablation[name] = dict(theta=ok_th, rms_rel_err=rms, max_rel_err=mx, ms_per_step=ms,
+                                  mcells_per_s=ncells / ms / 1e3)
+        ablation["cell_vote_quadrupole (default)"] = dict(theta=th_best, rms_rel_err=best["rms_rel_err"],
+                                                          ms_per_step=best["ms_per_step"],
+                                                          mcells_per_s=best["mcells_per_s"])
+        log("ablation (fp32, each at its largest theta meeting the gate): " + ", ".join(
+            "%s theta %s %.1f Mcells/s" % (k, v.get("theta"), v.get("mcells_per_s", 0.0)) for k, v in ablation.items()))
         fixed = dict(theta=th_best, fp32=best, fp64=fp64)
         log("best fixed theta %.2f: fp32 %.1f Mcells/s (rms %.2e), fp64 %.1f Mcells/s" % (
             th_best, best["mcells_per_s"], best["rms_rel_err"], fp64["mcells_per_s"]))
@@ -381,17 +419,18 @@ def main():
             learned["speedup_vs_fixed_fp32"] = fixed["fp32"]["ms_per_step"] / ms_step
             learned["speedup_vs_fixed_fp64"] = fixed["fp64"]["ms_per_step"] / ms_step
 
-    # ---- dominant kernel: fused walk + far/near sums, hipEvents on the library's stream
+    # ---- dominant kernel of the step: per-group theta + walk + far/near sums in one launch,
+    # hipEvents on the library's stream (torch's current stream)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     nrep = max(args.steps, 10)
     ev0.record(stream)
     for _ in range(nrep):
-        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta_g, B.BH_FP32, 1.0, phi, None)
+        B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, B.BH_FP32, 1.0, phi, None)
     ev1.record(stream)
     torch.cuda.synchronize()
     pot_ms = ev0.elapsed_time(ev1) / nrep
-    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta_g, B.BH_FP32, 1.0, phi, counts)
+    B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, B.BH_FP32, 1.0, phi, theta_g, counts)
     c = counts.cpu().numpy().astype(np.int64)
     flops, far_int, near_pairs = algorithmic_flops(c[:, 0], c[:, 1])
     achieved = flops / (pot_ms * 1e-3) / 1e12
@@ -466,9 +505,11 @@ def main():
         "learned_theta": learned,
         "fixed_theta": fixed,
         "accelerations": accel,
+        "ablation": ablation,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
-                     "kernel": "walk_potential_kernel<float>", "kernel_ms": pot_ms, "flop_per_launch": flops,
+                     "kernel": "walk_potential_learned_kernel<float, 6>", "kernel_ms": pot_ms,
+                     "flop_per_launch": flops,
                      "far_interactions": far_int, "near_pairs": near_pairs},
         "cpu_baseline": cpu,
         "topology_ms": topo_ms,

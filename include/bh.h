@@ -202,6 +202,31 @@ int bh_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, dou
 int bh_walk_accel(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, double theta, const float *theta_group_dev,
                   int precision, double G, double *phi_dev, double *acc_dev, int32_t *counts_dev);
 
+/* The fused walk with the paper's own choices instead of this library's, for
+ * comparison (both are beyond the default path, none changes the interface):
+ *   mac   BH_MAC_CELLS (default): a node is accepted iff every cell of the
+ *         group passes Eq. THETA2 (the all() vote of section 3.3, computed
+ *         exactly in O(1) per node);
+ *         BH_MAC_GROUP_BOX: iff the smallest distance d_c from the node's
+ *         centre of mass to the group's cube (faces at the outer cell faces)
+ *         passes it -- the test the paper uses between a node and a region
+ *         (section 3.2, Fig. opening_angles2); stricter, so more work.
+ *   order 2 (default): monopole + quadrupole far terms; 0: monopole only, the
+ *         paper's far field.
+ * Other arguments, outputs and errors as bh_walk_potential; opts NULL means
+ * the defaults (then the result is bh_walk_potential's, bit for bit).
+ * BH_EINVAL for an unknown mac or an order other than 0 or 2. */
+#define BH_MAC_CELLS 0
+#define BH_MAC_GROUP_BOX 1
+typedef struct bh_walk_options {
+    int32_t mac;
+    int32_t order;
+} bh_walk_options;
+
+int bh_walk_potential_ex(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, double theta,
+                         const float *theta_group_dev, int precision, double G, double *phi_dev, int32_t *counts_dev,
+                         const bh_walk_options *opts);
+
 /* Exact direct sum (Eq. 2) in fp64 at n_targets canonical cell ids
  * targets_dev[n] (int64, device); phi_dev[n] receives -G sum_{j != i} m_j/|r_ij|.
  * Uses the cell masses of the last bh_build_moments on m.  Errors: BH_EINVAL
@@ -348,6 +373,15 @@ int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat_dev, int64_
  * them.  theta_dev: fp32 [n_groups], canonical group order. */
 int bh_theta_infer(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_mlp *net, float theta_shift,
                    float *theta_dev);
+/* The whole learned-theta walk in one launch: each group's theta from the
+ * network (exactly the value bh_theta_infer gives), then the walk and sums of
+ * bh_walk_potential with that theta -- the same bits as bh_theta_infer
+ * followed by bh_walk_potential with theta_group_dev, without the
+ * intermediate launch.  theta_dev: NULL, or fp32 [n_groups] receiving the
+ * thetas used.  Other arguments and errors as bh_walk_potential. */
+int bh_learned_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_mlp *net,
+                              float theta_shift, int precision, double G, double *phi_dev, float *theta_dev,
+                              int32_t *counts_dev);
 /* Gradient of L = (1/n) sum (theta(x_s) - label_s)^2 with respect to the
  * parameters (fp32, deterministic order).  grad_dev: fp32 [BH_MLP_PARAMS];
  * loss_dev: NULL or fp32 [1] receiving L. */

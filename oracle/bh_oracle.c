@@ -31,6 +31,8 @@
  *               d^2 > s^2, d = |r_i - X_n|, s = l (1/theta_g) + delta
  *               (Eq. THETA2 combined with the all() vote of the potential
  *               kernel, section 3.3; equality opens).
+ *  O5b        - the variant the paper uses between a node and a region: d is
+ *               the smallest distance from X_n to the group's cube.
  *  O6 walk    - depth-first from the root; accepted -> far list, rejected
  *               bottom node (children are cells) -> near list, rejected
  *               internal node -> visit its 8 children.  Zero-mass nodes are
@@ -424,7 +426,26 @@ typedef struct {
     double tau;
     ivec *far, *near;
     int64_t visited, marginal;
+    int mac;            /* 0: every cell of the group (O5); 1: the group's cube (O5b) */
+    double box[6];      /* O5b: lower and upper corner of the group's cube */
 } walkctx;
+
+/* O5b (the paper's test between a node and a whole region, section 3.2
+ * "Find Essential Nodes" and Fig. opening_angles2): d_c is the smallest
+ * distance from the node's centre of mass to the group's cube, whose faces are
+ * the outer faces of its cells; the node is accepted iff d_c^2 > s^2. */
+static void group_cube(const otree *t, const int64_t *cells, int G, double *box) {
+    int64_t leaf = cells[0] / NCB;
+    double h = t->leaf_h[leaf];
+    for (int d = 0; d < 3; d++) { box[d] = INFINITY; box[3 + d] = -INFINITY; }
+    for (int q = 0; q < G; q++) {
+        double p[3] = {t->cx[cells[q]], t->cy[cells[q]], t->cz[cells[q]]};
+        for (int d = 0; d < 3; d++) {
+            if (p[d] - 0.5 * h < box[d]) box[d] = p[d] - 0.5 * h;
+            if (p[d] + 0.5 * h > box[3 + d]) box[3 + d] = p[d] + 0.5 * h;
+        }
+    }
+}
 
 /* O5 + O6 */
 static void walk_node(walkctx *w, int n) {
@@ -436,14 +457,24 @@ static void walk_node(walkctx *w, int n) {
     double s2 = s * s;
     int accept = 1;
     double dmin2 = INFINITY;
-    for (int q = 0; q < w->G; q++) {
-        int64_t c = w->cells[q];
-        double dx = t->cx[c] - a->X[0];
-        double dy = t->cy[c] - a->X[1];
-        double dz = t->cz[c] - a->X[2];
-        double d2 = dx * dx + dy * dy + dz * dz;
-        if (!(d2 > s2)) accept = 0;
-        if (d2 < dmin2) dmin2 = d2;
+    if (w->mac == 1) {
+        double g[3];
+        for (int d = 0; d < 3; d++) {
+            double below = w->box[d] - a->X[d], above = a->X[d] - w->box[3 + d];
+            g[d] = below > 0.0 ? below : (above > 0.0 ? above : 0.0);
+        }
+        dmin2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        accept = dmin2 > s2;
+    } else {
+        for (int q = 0; q < w->G; q++) {
+            int64_t c = w->cells[q];
+            double dx = t->cx[c] - a->X[0];
+            double dy = t->cy[c] - a->X[1];
+            double dz = t->cz[c] - a->X[2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (!(d2 > s2)) accept = 0;
+            if (d2 < dmin2) dmin2 = d2;
+        }
     }
     if (fabs(dmin2 - s2) <= w->tau * s2) w->marginal++;
     if (accept) {
@@ -457,7 +488,7 @@ static void walk_node(walkctx *w, int n) {
 
 /* Walk every group; theta_group[g] per group (canonical group order:
  * leaf-major, then Morton run).  Returns the number of groups. */
-int64_t ot_walk(otree *t, int group_cells, const double *theta_group, double tau) {
+int64_t ot_walk_mac(otree *t, int group_cells, const double *theta_group, double tau, int mac) {
     free_walk(t);
     int G = group_cells;
     t->group_cells = G;
@@ -477,6 +508,8 @@ int64_t ot_walk(otree *t, int group_cells, const double *theta_group, double tau
             w.tau = tau;
             w.far = &t->far[g]; w.near = &t->near[g];
             w.visited = 0; w.marginal = 0;
+            w.mac = mac;
+            if (mac == 1) group_cube(t, cells, G, w.box);
             walk_node(&w, t->root);
             t->counts[4 * g + 0] = w.visited;
             t->counts[4 * g + 1] = t->far[g].n;
@@ -486,6 +519,10 @@ int64_t ot_walk(otree *t, int group_cells, const double *theta_group, double tau
         free(cells);
     }
     return t->ngroups;
+}
+
+int64_t ot_walk(otree *t, int group_cells, const double *theta_group, double tau) {
+    return ot_walk_mac(t, group_cells, theta_group, tau, 0);
 }
 
 void ot_walk_sizes(const otree *t, int64_t *total_far, int64_t *total_near) {
@@ -612,8 +649,8 @@ int ot_potential_lists(const otree *t, int group_cells, const int64_t *far_off, 
  * counts[4 * q + ...] as in ot_walk for groups[q]; phi[q * G + c] for the
  * group's c-th cell in Morton order.  theta_group is indexed by canonical
  * group id, as in ot_walk. */
-void ot_solve_groups(const otree *t, int group_cells, const double *theta_group, const int64_t *groups, int64_t n,
-                     double tau, double Gc, int order, int64_t *counts, double *phi) {
+void ot_solve_groups_mac(const otree *t, int group_cells, const double *theta_group, const int64_t *groups,
+                         int64_t n, double tau, double Gc, int order, int mac, int64_t *counts, double *phi) {
     int G = group_cells;
 #pragma omp parallel
     {
@@ -629,6 +666,8 @@ void ot_solve_groups(const otree *t, int group_cells, const double *theta_group,
             w.tau = tau;
             w.far = &far; w.near = &near;
             w.visited = 0; w.marginal = 0;
+            w.mac = mac;
+            if (mac == 1) group_cube(t, cells, G, w.box);
             walk_node(&w, t->root);
             counts[4 * q + 0] = w.visited;
             counts[4 * q + 1] = far.n;
@@ -640,6 +679,11 @@ void ot_solve_groups(const otree *t, int group_cells, const double *theta_group,
         }
         free(cells);
     }
+}
+
+void ot_solve_groups(const otree *t, int group_cells, const double *theta_group, const int64_t *groups, int64_t n,
+                     double tau, double Gc, int order, int64_t *counts, double *phi) {
+    ot_solve_groups_mac(t, group_cells, theta_group, groups, n, tau, Gc, order, 0, counts, phi);
 }
 
 /* O2 for selected targets (canonical cell ids) */
@@ -758,6 +802,7 @@ void ot_solve_groups_accel(const otree *t, int group_cells, const double *theta_
             w.tau = tau;
             w.far = &far; w.near = &near;
             w.visited = 0; w.marginal = 0;
+            w.mac = 0;
             walk_node(&w, t->root);
             counts[4 * q + 0] = w.visited;
             counts[4 * q + 1] = far.n;
@@ -804,6 +849,94 @@ void ot_direct_at(const otree *t, const double *p, const int64_t *exclude, int64
             if (j == exclude[q]) continue;
             double rx = p[3 * q] - t->cx[j], ry = p[3 * q + 1] - t->cy[j], rz = p[3 * q + 2] - t->cz[j];
             nadd(&acc, t->cm[j] / sqrt(rx * rx + ry * ry + rz * rz));
+        }
+        phi[q] = -Gc * nval(&acc);
+    }
+}
+
+/*
+ * O9 periodic boundaries (appendix "Periodic boundaries"): the potential of a
+ * unit mass in a cubic box of side L repeated in all three directions, with
+ * the mean density removed, split with the error function into a short-range
+ * sum over images and a long-range sum over wave vectors (Ewald):
+ *   psi(r) = sum_n erfc(a |r + nL|) / |r + nL|
+ *          + 1/(pi L) sum_{m != 0} exp(-pi^2 |m|^2 / (a L)^2) / |m|^2 cos(2 pi m.r / L)
+ *          - pi / (a^2 L^3),
+ * independent of the splitting constant a.  D(r) = psi(r) - 1/|r| is smooth
+ * near r = 0, with D(0) the self term psi_0.  Sums run over |n_i| <= nreal and
+ * 0 < |m_i| <= nrecip (each component).
+ */
+static void ewald_at(double L, double a, int nreal, int nrecip, const double *r, double *D, double *g) {
+    const double sqpi = 1.7724538509055160273;
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    nsum s = {0.0, 0.0}, gx = {0.0, 0.0}, gy = {0.0, 0.0}, gz = {0.0, 0.0};
+    /* image n = 0 minus 1/r: -erf(a r)/r, a smooth even function */
+    if (a * rr < 1e-4) {
+        double x2 = a * a * rr * rr;
+        nadd(&s, -2.0 * a / sqpi * (1.0 - x2 / 3.0 + x2 * x2 / 10.0));
+        double c = 4.0 * a * a * a / (3.0 * sqpi) * (1.0 - 3.0 * x2 / 5.0);
+        nadd(&gx, c * r[0]); nadd(&gy, c * r[1]); nadd(&gz, c * r[2]);
+    } else {
+        nadd(&s, -erf(a * rr) / rr);
+        double f1 = erf(a * rr) / (rr * rr) - 2.0 * a / sqpi * exp(-a * a * rr * rr) / rr;  /* d/dr */
+        nadd(&gx, f1 * r[0] / rr); nadd(&gy, f1 * r[1] / rr); nadd(&gz, f1 * r[2] / rr);
+    }
+    for (int i = -nreal; i <= nreal; i++)
+        for (int j = -nreal; j <= nreal; j++)
+            for (int k = -nreal; k <= nreal; k++) {
+                if (i == 0 && j == 0 && k == 0) continue;
+                double p[3] = {r[0] + i * L, r[1] + j * L, r[2] + k * L};
+                double d = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+                nadd(&s, erfc(a * d) / d);
+                double f1 = -erfc(a * d) / (d * d) - 2.0 * a / sqpi * exp(-a * a * d * d) / d;
+                nadd(&gx, f1 * p[0] / d); nadd(&gy, f1 * p[1] / d); nadd(&gz, f1 * p[2] / d);
+            }
+    const double pi = 3.14159265358979323846;
+    for (int i = -nrecip; i <= nrecip; i++)
+        for (int j = -nrecip; j <= nrecip; j++)
+            for (int k = -nrecip; k <= nrecip; k++) {
+                if (i == 0 && j == 0 && k == 0) continue;
+                double m2 = (double)(i * i + j * j + k * k);
+                double w = exp(-pi * pi * m2 / (a * a * L * L)) / (pi * L * m2);
+                double ph = 2.0 * pi * (i * r[0] + j * r[1] + k * r[2]) / L;
+                nadd(&s, w * cos(ph));
+                double gs = -w * sin(ph) * 2.0 * pi / L;
+                nadd(&gx, gs * i); nadd(&gy, gs * j); nadd(&gz, gs * k);
+            }
+    nadd(&s, -pi / (a * a * L * L * L));
+    *D = nval(&s);
+    g[0] = nval(&gx); g[1] = nval(&gy); g[2] = nval(&gz);
+}
+
+/* D and grad D at n points r[n][3] (any r: the sums are periodic). */
+void ot_ewald(double L, double alpha, int nreal, int nrecip, const double *r, int64_t n, double *D, double *grad) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n; q++) ewald_at(L, alpha, nreal, nrecip, r + 3 * q, D + q, grad + 3 * q);
+}
+
+#define EW_ALPHA 2.0
+#define EW_NREAL 4
+#define EW_NRECIP 5
+
+/* Exact periodic direct sum at selected cells:
+ *   phi_i = -G [ sum_{j != i} m_j psi(r_i - r_j) + m_i psi_0 ],
+ * psi = 1/|r'| + D(r') with r' the nearest image, psi_0 = D(0). */
+void ot_direct_periodic(const otree *t, const int64_t *targets, int64_t ntargets, double Gc, double *phi) {
+    const double L = t->box;
+    double D0, g0[3], zero[3] = {0.0, 0.0, 0.0};
+    ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, zero, &D0, g0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < ntargets; q++) {
+        int64_t i = targets[q];
+        nsum acc = {0.0, 0.0};
+        nadd(&acc, t->cm[i] * D0);
+        for (int64_t j = 0; j < t->ncells; j++) {
+            if (j == i || t->cm[j] == 0.0) continue;
+            double r[3] = {t->cx[i] - t->cx[j], t->cy[i] - t->cy[j], t->cz[i] - t->cz[j]};
+            for (int d = 0; d < 3; d++) r[d] -= L * nearbyint(r[d] / L);
+            double D, gr[3];
+            ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, r, &D, gr);
+            nadd(&acc, t->cm[j] * (1.0 / sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) + D));
         }
         phi[q] = -Gc * nval(&acc);
     }

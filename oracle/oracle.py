@@ -66,6 +66,10 @@ def _load():
         lib.ot_get_moments.argtypes = [P, P, P, P, P]
         lib.ot_walk.restype = i64
         lib.ot_walk.argtypes = [P, ctypes.c_int, P, ctypes.c_double]
+        lib.ot_walk_mac.restype = i64
+        lib.ot_walk_mac.argtypes = [P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int]
+        lib.ot_solve_groups_mac.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int, ctypes.c_int, P, P]
         lib.ot_walk_sizes.argtypes = [P, P, P]
         lib.ot_walk_export.argtypes = [P, P, P, P, P, P]
         lib.ot_potential.argtypes = [P, ctypes.c_double, ctypes.c_int, P]
@@ -80,6 +84,8 @@ def _load():
                                               ctypes.c_int, P, P]
         lib.ot_direct_accel.argtypes = [P, P, i64, ctypes.c_double, P]
         lib.ot_direct_at.argtypes = [P, P, P, i64, ctypes.c_double, P]
+        lib.ot_ewald.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, i64, P, P]
+        lib.ot_direct_periodic.argtypes = [P, P, i64, ctypes.c_double, P]
         _lib = lib
         return lib
 
@@ -177,14 +183,15 @@ class OracleTree:
     def n_groups(self, group_cells):
         return self.nleaf * (512 // group_cells)
 
-    def walk(self, group_cells=64, theta=0.5, tau=0.0):
-        """O5/O6 for every group; ``theta`` is a scalar or one value per group."""
+    def walk(self, group_cells=64, theta=0.5, tau=0.0, mac=0):
+        """O5/O6 for every group; ``theta`` is a scalar or one value per group.
+        ``mac`` 0: every cell of the group is tested (O5); 1: the group's cube (O5b)."""
         assert 512 % group_cells == 0 and (group_cells & (group_cells - 1)) == 0
         if not self._moments_done:
             self.moments()
         ng = self.n_groups(group_cells)
         th = np.broadcast_to(np.asarray(theta, np.float64), (ng,)).copy()
-        self.lib.ot_walk(self.h, int(group_cells), _p(th), float(tau))
+        self.lib.ot_walk_mac(self.h, int(group_cells), _p(th), float(tau), int(mac))
         self.group_cells = group_cells
         tf = ctypes.c_int64()
         tn = ctypes.c_int64()
@@ -229,7 +236,7 @@ class OracleTree:
             raise ValueError("list replay: %s" % ("unknown node key" if rc == -1 else "near entry not a bottom node"))
         return phi.reshape(self.nleaf, 8, 8, 8)
 
-    def solve_groups(self, groups, group_cells=64, theta=0.5, tau=0.0, G=1.0, order=2):
+    def solve_groups(self, groups, group_cells=64, theta=0.5, tau=0.0, G=1.0, order=2, mac=0):
         """O5-O7 for selected canonical groups only.  Returns (phi[n, G] in the
         group's Morton order, counts[n, 4] = visited, far, near, marginal)."""
         if not self._moments_done:
@@ -239,9 +246,19 @@ class OracleTree:
         gs = np.ascontiguousarray(groups, np.int64)
         phi = np.empty((gs.size, group_cells))
         counts = np.empty((gs.size, 4), np.int64)
-        self.lib.ot_solve_groups(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau), float(G),
-                                 int(order), _p(counts), _p(phi))
+        self.lib.ot_solve_groups_mac(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau), float(G),
+                                     int(order), int(mac), _p(counts), _p(phi))
         return phi, counts
+
+    # -- O9 ----------------------------------------------------------------------
+    def direct_periodic(self, targets=None, G=1.0):
+        """Exact periodic direct sum (nearest image + Ewald smooth part + self images) at canonical cell ids."""
+        if not self._density_set:
+            self.set_density()
+        t = np.arange(self.ncells, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, np.int64)
+        phi = np.empty(t.size)
+        self.lib.ot_direct_periodic(self.h, _p(t), int(t.size), float(G), _p(phi))
+        return phi
 
     # -- O8 ----------------------------------------------------------------------
     def accel(self, G=1.0, order=2):
@@ -293,3 +310,15 @@ class OracleTree:
         phi = np.empty(t.size)
         self.lib.ot_direct(self.h, _p(t), int(t.size), float(G), _p(phi))
         return phi
+
+
+def ewald(points, L=1.0, alpha=None, nreal=4, nrecip=5):
+    """O9: smooth part D = psi - 1/r of the periodic Green's function and its
+    gradient at points [n, 3]; returns (D[n], grad[n, 3])."""
+    lib = _load()
+    p = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+    D = np.empty(p.shape[0])
+    g = np.empty((p.shape[0], 3))
+    a = 2.0 / L if alpha is None else float(alpha)
+    lib.ot_ewald(float(L), a, int(nreal), int(nrecip), _p(p), int(p.shape[0]), _p(D), _p(g))
+    return D, g

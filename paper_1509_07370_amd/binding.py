@@ -68,6 +68,7 @@ _SIGS = {
     "bh_lists_destroy": (ctypes.c_int, [P]),
     "bh_potential": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
     "bh_walk_potential": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P]),
+    "bh_walk_potential_ex": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P, P]),
     "bh_walk_accel": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P, P]),
     "bh_direct_accel": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
     "bh_direct": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
@@ -92,12 +93,14 @@ _SIGS = {
     "bh_mlp_get_params": (ctypes.c_int, [P, P, P]),
     "bh_mlp_forward": (ctypes.c_int, [P, P, P, i64, ctypes.c_int, ctypes.c_float, P]),
     "bh_mlp_grad": (ctypes.c_int, [P, P, P, P, i64, P, P]),
+    "bh_learned_walk_potential": (ctypes.c_int, [P, P, P, P, ctypes.c_float, ctypes.c_int, f64, P, P, P]),
     "bh_theta_infer": (ctypes.c_int, [P, P, P, P, ctypes.c_float, P]),
     "bh_mlp_adam_step": (ctypes.c_int, [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     "bh_mlp_destroy": (ctypes.c_int, [P]),
 }
 MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 BH_ORDER_NATURAL, BH_ORDER_COST = 0, 1
+BH_MAC_CELLS, BH_MAC_GROUP_BOX = 0, 1
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
@@ -273,6 +276,20 @@ def bh_walk_potential(ctx, grid, m, theta, theta_group, precision, G, phi, count
     return phi
 
 
+class WalkOptions(ctypes.Structure):
+    _fields_ = [("mac", i32), ("order", i32)]
+
+
+def bh_walk_potential_ex(ctx, grid, m, theta, theta_group, precision, G, phi, counts=None, mac=BH_MAC_CELLS,
+                         order=2):
+    tg = _dev(theta_group, "float32") if theta_group is not None else None
+    cn = _dev(counts, "int32") if counts is not None else None
+    opts = WalkOptions(int(mac), int(order))
+    _check(_lib.bh_walk_potential_ex(ctx, grid, m, float(theta), tg, int(precision), float(G), _dev(phi, "float64"),
+                                     cn, ctypes.byref(opts)), ctx)
+    return phi
+
+
 def bh_walk_accel(ctx, grid, m, theta, theta_group, precision, G, phi, acc, counts=None):
     """acc: float64 CUDA tensor [n_leaf, 8, 8, 8, 3]; phi: None or [n_leaf, 8, 8, 8]."""
     tg = _dev(theta_group, "float32") if theta_group is not None else None
@@ -335,6 +352,14 @@ def bh_mlp_forward(ctx, net, feat, theta, bf16=True, shift=0.0):
     _check(_lib.bh_mlp_forward(ctx, net, _dev(feat, "float32"), n, int(bool(bf16)), float(shift),
                                _dev(theta, "float32")), ctx)
     return theta
+
+
+def bh_learned_walk_potential(ctx, grid, m, net, shift, precision, G, phi, theta=None, counts=None):
+    th = _dev(theta, "float32") if theta is not None else None
+    c = _dev(counts, "int32") if counts is not None else None
+    _check(_lib.bh_learned_walk_potential(ctx, grid, m, net, float(shift), int(precision), float(G),
+                                          _dev(phi, "float64"), th, c), ctx)
+    return phi
 
 
 def bh_theta_infer(ctx, grid, m, net, theta, shift=0.0):

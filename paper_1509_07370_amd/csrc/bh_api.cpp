@@ -57,12 +57,12 @@ void free_grid_device(bh_grid *g) {
     hfree(g->d_leaves);
     hfree(g->d_internal_of_canon);
     hfree(g->d_combine);
-    hfree(g->d_combine_off);
+    hfree(g->d_combine_range);
     hfree(g->d_parent);
     g->d_parent = nullptr;
     g->d_geom = nullptr;
     g->d_child = g->d_flags = g->d_internal_of_canon = g->d_combine = nullptr;
-    g->d_combine_off = nullptr;
+    g->d_combine_range = nullptr;
     g->d_leaves = nullptr;
 }
 
@@ -163,7 +163,7 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
             (e = dalloc(&g->d_leaves, t.leaves.size())) != hipSuccess ||
             (e = dalloc(&g->d_internal_of_canon, t.internal_of_canon.size())) != hipSuccess ||
             (e = dalloc(&g->d_combine, t.combine_nodes.size())) != hipSuccess ||
-            (e = dalloc(&g->d_combine_off, t.combine_off.size())) != hipSuccess ||
+            (e = dalloc(&g->d_combine_range, t.combine_range.size())) != hipSuccess ||
             (e = dalloc(&g->d_parent, t.parent.size())) != hipSuccess) {
             free_grid_device(g);
             delete g;
@@ -179,7 +179,7 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
                   {g->d_leaves, t.leaves.data(), t.leaves.size() * sizeof(bh::LeafInfo)},
                   {g->d_internal_of_canon, t.internal_of_canon.data(), t.internal_of_canon.size() * sizeof(int32_t)},
                   {g->d_combine, t.combine_nodes.data(), t.combine_nodes.size() * sizeof(int32_t)},
-                  {g->d_combine_off, t.combine_off.data(), t.combine_off.size() * sizeof(int64_t)},
+                  {g->d_combine_range, t.combine_range.data(), t.combine_range.size() * sizeof(int32_t)},
                   {g->d_parent, t.parent.data(), t.parent.size() * sizeof(int32_t)}};
         for (auto &u : up) {
             if (u.n == 0) continue;
@@ -459,6 +459,25 @@ int bh_walk_potential(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double
     if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
     m->walk_epoch++;
     HIPX(ctx, bh::launch_walk_potential(g, m, theta, theta_group, precision, G, phi, counts, ctx->stream),
+         "fused walk + potential kernel");
+    return BH_OK;
+}
+
+int bh_walk_potential_ex(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                         int precision, double G, double *phi, int32_t *counts, const bh_walk_options *opts) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!g || !m || !phi) return fail(ctx, BH_EINVAL, "grid, moments or phi_dev is NULL");
+    if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
+    if (!theta_group && !(theta > 0.0 && theta <= 1.0)) return fail(ctx, BH_EINVAL, "theta must be in (0, 1]");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    const int mac = opts ? opts->mac : BH_MAC_CELLS, order = opts ? opts->order : 2;
+    if (mac != BH_MAC_CELLS && mac != BH_MAC_GROUP_BOX) return fail(ctx, BH_EINVAL, "unknown opening test (mac)");
+    if (order != 0 && order != 2) return fail(ctx, BH_EINVAL, "order must be 0 or 2");
+    m->walk_epoch++;
+    HIPX(ctx, bh::launch_walk_potential_opts(g, m, theta, theta_group, precision, G, phi, counts, mac, order,
+                                             ctx->stream),
          "fused walk + potential kernel");
     return BH_OK;
 }

@@ -96,8 +96,9 @@ struct Topology {
     std::vector<int32_t> parent;      // [n_nodes], -1 for the root
     std::vector<LeafInfo> leaves;     // internal leaf order
     std::vector<int32_t> internal_of_canon;  // canonical leaf -> internal leaf
-    std::vector<int32_t> combine_nodes;      // virtual + parent-block nodes, deepest depth first
-    std::vector<int64_t> combine_off;        // per depth bucket (deepest first), size n_buckets + 1
+    std::vector<int32_t> combine_nodes;      // virtual + parent-block nodes (above the leaf blocks)
+    // per combine node q: the range [first, end) of leaf ordinals below it
+    std::vector<int32_t> combine_range;      // [combine_nodes.size()][2]
 };
 
 // Returns "" on success, else the reason the block list is rejected.
@@ -126,7 +127,7 @@ struct bh_grid {
     bh::LeafInfo *d_leaves = nullptr;    // [n_leaf]
     int32_t *d_internal_of_canon = nullptr;
     int32_t *d_combine = nullptr;
-    int64_t *d_combine_off = nullptr;
+    int32_t *d_combine_range = nullptr;
     int32_t *d_parent = nullptr;         // [n_nodes]
 };
 
@@ -177,6 +178,10 @@ hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, doubl
 hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipStream_t s);
 hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                                  int precision, double G, double *phi, int32_t *counts, hipStream_t s);
+// fused walk with an opening test (BH_MAC_*) and far-field order (2 or 0)
+hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                                      int precision, double G, double *phi, int32_t *counts, int mac, int order,
+                                      hipStream_t s);
 // walk fused with potential (phi may be NULL) and acceleration sums
 hipError_t launch_walk_accel(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                              int precision, double G, double *phi, double *acc, int32_t *counts, hipStream_t s);

@@ -2,8 +2,8 @@
 //
 //   moments_leaf_kernel    one workgroup per leaf block: cells -> 64 bottom nodes
 //                          -> 8 octants -> block node by lane shuffles (fp64)
-//   moments_levels_kernel  the nodes above the leaf blocks, 8 lanes per node,
-//                          deepest depth first (parallel-axis rule)
+//   moments_upper_kernel   the nodes above the leaf blocks, one workgroup per
+//                          node, each from the leaf blocks below it
 //   walk_kernel            one wavefront per 64-cell group: breadth-limited
 //                          depth-first traversal with an LDS stack of sibling
 //                          sets; 64 lanes test 8 sibling sets at once, the
@@ -17,6 +17,7 @@
 
 #include "bh_device.h"
 #include "bh_internal.h"
+#include "bh_theta_net.h"
 
 namespace bh {
 
@@ -201,67 +202,63 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
     store_node(out, node, BM, BX, BY, BZ, BQ, geom + 4 * (int64_t)node, child_arr[node], 0);
 }
 
-// Nodes above the leaf blocks (virtual and parent-block nodes, 8 node
-// children each) in one workgroup, deepest depth first with a barrier between
-// depths: 8 lanes per node, lane c loads child c's row, and the node combines
-// by lane shuffles.  The leaf blocks' rows come from the previous launch.
-__global__ __launch_bounds__(1024) void moments_levels_kernel(const int32_t *__restrict__ nodes,
-                                                              const int64_t *__restrict__ off, int nbuckets,
-                                                              const double *__restrict__ geom,
-                                                              const int32_t *__restrict__ child_arr, MomOut out) {
-#pragma clang fp contract(off)
-    const int c = threadIdx.x & 7;
-    for (int b = 0; b < nbuckets; b++) {
-        const int64_t end = off[b + 1];
-        // whole groups of 8 lanes iterate together, so the shuffles see all 8
-        for (int64_t q0 = off[b]; q0 < end; q0 += blockDim.x / 8) {
-            const int64_t q = q0 + (threadIdx.x >> 3);
-            const bool live = q < end;
-            const int id = live ? nodes[q] : 0;
-            const int first = live ? child_arr[id] : 0;
-            double m = 0.0, x = 0.0, y = 0.0, z = 0.0, qc[6] = {0, 0, 0, 0, 0, 0};
-            if (live) {
-                const double *mo = out.mom + (int64_t)(first + c) * kMom;
-                x = mo[0];
-                y = mo[1];
-                z = mo[2];
-                m = mo[3];
-                for (int k = 0; k < 6; k++) qc[k] = mo[4 + k];
-            }
-            double M, X, Y, Z, Q[6];
-            combine_lanes(m, x, y, z, qc, M, X, Y, Z, Q);
-            if (live && c == 0) store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, first, 0);
-        }
-        __syncthreads();
-    }
+// Block-wide sum of one double per thread (256 threads), in a fixed order:
+// wavefront butterflies, then the four wavefront totals in order.  Every
+// thread gets the same value.
+__device__ __forceinline__ double block_sum256(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// One tree depth of the nodes above the leaf blocks, for grids with more of
-// them than one workgroup handles well.
-__global__ __launch_bounds__(256) void moments_combine_kernel(const int32_t *__restrict__ nodes, int64_t count,
-                                                              const double *__restrict__ geom,
-                                                              const int32_t *__restrict__ child_arr, MomOut out) {
+// Nodes above the leaf blocks (virtual and parent-block nodes), one
+// 256-thread workgroup per node, all at once: a node's moments are those of
+// the leaf blocks below it -- a contiguous range of leaf ordinals -- combined
+// directly (mass and centre of mass, then the quadrupole about it by the
+// parallel-axis rule), so no node waits for its children.  The leaf blocks'
+// rows come from moments_leaf_kernel.
+__global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__restrict__ nodes,
+                                                            const int32_t *__restrict__ range,
+                                                            const LeafInfo *__restrict__ leaves,
+                                                            const double *__restrict__ geom,
+                                                            const int32_t *__restrict__ child_arr, MomOut out) {
 #pragma clang fp contract(off)
-    const int c = threadIdx.x & 7;
-    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-    const bool live = q < count;
-    const int id = live ? nodes[q] : 0;
-    const int first = live ? child_arr[id] : 0;
-    double m = 0.0, x = 0.0, y = 0.0, z = 0.0, qc[6] = {0, 0, 0, 0, 0, 0};
-    if (live) {
-        const double *mo = out.mom + (int64_t)(first + c) * kMom;
-        x = mo[0];
-        y = mo[1];
-        z = mo[2];
-        m = mo[3];
-        for (int k = 0; k < 6; k++) qc[k] = mo[4 + k];
+    __shared__ double red[4];
+    const int q = blockIdx.x;
+    const int id = nodes[q];
+    const int f0 = range[2 * q], f1 = range[2 * q + 1];
+    double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
+        const double *r = out.mom + (int64_t)leaves[f].block_node * kMom;
+        const double mb = r[3];
+        m += mb;
+        sx += mb * r[0];
+        sy += mb * r[1];
+        sz += mb * r[2];
     }
-    double M, X, Y, Z, Q[6];
-    combine_lanes(m, x, y, z, qc, M, X, Y, Z, Q);
-    if (live && c == 0) store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, first, 0);
+    const double M = block_sum256(m, red);
+    const double SX = block_sum256(sx, red), SY = block_sum256(sy, red), SZ = block_sum256(sz, red);
+    const double X = M > 0.0 ? SX / M : 0.0, Y = M > 0.0 ? SY / M : 0.0, Z = M > 0.0 ? SZ / M : 0.0;
+    double qa[6] = {0, 0, 0, 0, 0, 0};
+    for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
+        const double *r = out.mom + (int64_t)leaves[f].block_node * kMom;
+        const double mb = r[3];
+        const double dx = r[0] - X, dy = r[1] - Y, dz = r[2] - Z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        qa[0] += r[4] + mb * (3.0 * dx * dx - r2);
+        qa[1] += r[5] + mb * (3.0 * dy * dy - r2);
+        qa[2] += r[6] + mb * (3.0 * dz * dz - r2);
+        qa[3] += r[7] + mb * (3.0 * dx * dy);
+        qa[4] += r[8] + mb * (3.0 * dx * dz);
+        qa[5] += r[9] + mb * (3.0 * dy * dz);
+    }
+    double Q[6];
+    for (int k = 0; k < 6; k++) Q[k] = block_sum256(qa[k], red);
+    if (threadIdx.x == 0) store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], 0);
 }
-
-constexpr int64_t kSingleWorkgroupCombine = 16384;
 
 hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int fixed_epoch) {
     MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32};
@@ -271,22 +268,11 @@ hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hi
                        m->d_cell64, m->d_cell32, m->d_flags, epoch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const auto &off = g->topo.combine_off;
-    const int nb = (int)off.size() - 1;
-    if (nb <= 0) return hipSuccess;
-    if (off[nb] <= kSingleWorkgroupCombine) {
-        hipLaunchKernelGGL(moments_levels_kernel, dim3(1), dim3(1024), 0, s, g->d_combine, g->d_combine_off, nb,
-                           g->d_geom, g->d_child, o);
-        return hipGetLastError();
-    }
-    for (int b = 0; b < nb; b++) {
-        const int64_t cnt = off[b + 1] - off[b];
-        const int blocks = (int)((8 * cnt + 255) / 256);
-        hipLaunchKernelGGL(moments_combine_kernel, dim3(blocks), dim3(256), 0, s, g->d_combine + off[b], cnt,
-                           g->d_geom, g->d_child, o);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int nupper = (int)g->topo.combine_nodes.size();
+    if (nupper == 0) return hipSuccess;
+    hipLaunchKernelGGL(moments_upper_kernel, dim3(nupper), dim3(256), 0, s, g->d_combine, g->d_combine_range,
+                       g->d_leaves, g->d_geom, g->d_child, o);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- walk
@@ -322,6 +308,14 @@ __device__ __forceinline__ real nearest_gap(real x0, real h, real X, int n) {
 }
 
 
+// distance from X to the interval [lo, hi] along one axis
+template <typename real>
+__device__ __forceinline__ real cube_gap(real lo, real hi, real X) {
+#pragma clang fp contract(off)
+    const real below = lo - X, above = X - hi;
+    return below > (real)0 ? below : (above > (real)0 ? above : (real)0);
+}
+
 // Group walk state of one wavefront.  The group vote of the potential kernel
 // (all lanes accept) needs, per node, the minimum over the group's cells of
 // d^2.  The group is an axis-aligned 4x4x4 lattice of cell centres, so that
@@ -332,7 +326,10 @@ __device__ __forceinline__ real nearest_gap(real x0, real h, real X, int n) {
 // of opened nodes; it pops 8 entries while it is short and 1 entry (plain
 // depth-first order, growth <= 7 per level) once it passes k8_threshold, so it
 // never exceeds k8_threshold + 56 + 7 (max_depth + 1) + 1 < kWalkStackCap.
-template <typename real>
+// MAC 0: the exact vote of every cell of the group (O(1) per node, above);
+// MAC 1: the paper's test between a node and a region -- the smallest
+// distance from the node's centre of mass to the group's cube (cell faces).
+template <typename real, int MAC = 0>
 struct Walker {
     using Rec = typename Prec<real>::Rec;
     const Rec *nodes;
@@ -340,9 +337,11 @@ struct Walker {
     int size;
     int k8;
     real x0, y0, z0, h, inv;
+    real blo[3], bhi[3];  // MAC 1 only
     bool overflow;
 
-    __device__ void init(const WalkArgs &a, const LeafInfo &L, int sub, int *stack, int lane) {
+    // theta_in > 0: this group's theta, given by the caller (as if read from a.theta_group)
+    __device__ void init(const WalkArgs &a, const LeafInfo &L, int sub, int *stack, int lane, float theta_in = -1.0f) {
         nodes = (const Rec *)a.nodes;
         stk = stack;
         k8 = a.k8_threshold;
@@ -352,8 +351,18 @@ struct Walker {
         x0 = (real)(L.lo[0] + (i0 + 0.5) * L.h);
         y0 = (real)(L.lo[1] + (j0 + 0.5) * L.h);
         z0 = (real)(L.lo[2] + (k0 + 0.5) * L.h);
-        if (a.theta_group) {
-            float th = a.theta_group[(int64_t)L.canon * 8 + sub];
+        if constexpr (MAC == 1) {  // cube [first centre - h/2, last centre + h/2] per axis
+#pragma clang fp contract(off)
+            const real half = (real)0.5 * h;
+            blo[0] = x0 - half;
+            blo[1] = y0 - half;
+            blo[2] = z0 - half;
+            bhi[0] = (x0 + (real)3 * h) + half;
+            bhi[1] = (y0 + (real)3 * h) + half;
+            bhi[2] = (z0 + (real)3 * h) + half;
+        }
+        if (theta_in > 0.0f || a.theta_group) {
+            float th = theta_in > 0.0f ? theta_in : a.theta_group[(int64_t)L.canon * 8 + sub];
             if (!(th == th)) th = 1e-3f;
             th = th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
             inv = (real)1 / (real)th;
@@ -389,9 +398,16 @@ struct Walker {
             const Rec r = nodes[id];
             if (!(r.flags & FLAG_EMPTY)) {
 #pragma clang fp contract(off)
-                real dx = nearest_gap<real>(x0, h, r.x, 4);
-                real dy = nearest_gap<real>(y0, h, r.y, 4);
-                real dz = nearest_gap<real>(z0, h, r.z, 4);
+                real dx, dy, dz;
+                if constexpr (MAC == 1) {
+                    dx = cube_gap<real>(blo[0], bhi[0], r.x);
+                    dy = cube_gap<real>(blo[1], bhi[1], r.y);
+                    dz = cube_gap<real>(blo[2], bhi[2], r.z);
+                } else {
+                    dx = nearest_gap<real>(x0, h, r.x, 4);
+                    dy = nearest_gap<real>(y0, h, r.y, 4);
+                    dz = nearest_gap<real>(z0, h, r.z, 4);
+                }
                 real d2 = dx * dx + dy * dy + dz * dz;
                 real s = r.l * inv + r.delta;
                 acc = d2 > s * s;
@@ -670,6 +686,18 @@ __device__ __forceinline__ double far_term(double px, double py, double pz, cons
     return part + (p.w * ri + quad * (ri2 * ri2 * ri));
 }
 
+// monopole only: M / d
+__device__ __forceinline__ float far_monopole(float px, float py, float pz, const float4 p, float part) {
+    const float dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    return fmaf(p.w, __builtin_amdgcn_rsqf(r2), part);
+}
+__device__ __forceinline__ double far_monopole(double px, double py, double pz, const double4 p, double part) {
+    const double dx = px - p.x, dy = py - p.y, dz = pz - p.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    return part + p.w * rsqrt64(r2);
+}
+
 __device__ __forceinline__ float near_pair(float px, float py, float pz, const float4 s, float part) {
     const float dx = px - s.x, dy = py - s.y, dz = pz - s.z;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
@@ -743,7 +771,9 @@ __device__ __forceinline__ void near_pair_acc(real px, real py, real pz, const V
 // Near tile: up to 8 bottom nodes = 64 cells.  Each tile is summed in `real`
 // and added to an fp64 accumulator (separate for far and near, so that every
 // path that forms the same tiles in the same order gives identical bits).
-template <typename real>
+// ORDER 2: monopole + quadrupole far terms; 0: monopole only (the paper's
+// own far field, for comparison)
+template <typename real, int ORDER = 2>
 struct Tiles {
     using V4 = typename Prec<real>::V4;
     V4 *T;
@@ -767,7 +797,10 @@ struct Tiles {
     }
     __device__ void sum_far(int n) {
         real part = 0;
-        for (int j = 0; j < n; j++) part = far_term(me.x, me.y, me.z, T[3 * j], T[3 * j + 1], T[3 * j + 2], part);
+        if (ORDER == 0)
+            for (int j = 0; j < n; j++) part = far_monopole(me.x, me.y, me.z, T[3 * j], part);
+        else
+            for (int j = 0; j < n; j++) part = far_term(me.x, me.y, me.z, T[3 * j], T[3 * j + 1], T[3 * j + 2], part);
         acc_far += (double)part;
         wave_lds_sync();
     }
@@ -962,13 +995,22 @@ struct FusedSmem {
 
 // one group g of the grid described by a, on wavefront w of the workgroup;
 // TL: the tile evaluator (potential, or potential and acceleration)
-template <typename real, typename TL = Tiles<real>>
-__device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w, int lane, FusedSmem<real> &sm) {
+// theta_net: NULL, or the network that gives this group's theta first (its
+// value is also written to theta_out when that is not NULL)
+template <typename real, typename TL = Tiles<real>, int MAC = 0>
+__device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w, int lane, FusedSmem<real> &sm,
+                                            const ThetaNetArgs *theta_net = nullptr, float *theta_out = nullptr) {
     using V4 = typename Prec<real>::V4;
     const int f = (int)(g >> 3), sub = (int)(g & 7);
     const LeafInfo L = a.leaves[f];
-    Walker<real> W;
-    W.init(a, L, sub, sm.stack[w], lane);
+    float th = -1.0f;
+    if (theta_net) {  // the tile buffer is free until the walk starts
+        float *buf = reinterpret_cast<float *>(sm.tile[w]);
+        th = group_theta(*theta_net, L, sub, lane, buf, buf + BH_MLP_INPUTS);
+        if (theta_out && lane == 0) theta_out[(int64_t)L.canon * 8 + sub] = th;
+    }
+    Walker<real, MAC> W;
+    W.init(a, L, sub, sm.stack[w], lane, th);
     TL S;
     S.T = sm.tile[w];
     S.rec = (const V4 *)a.far_rec;
@@ -1061,6 +1103,70 @@ __global__ __launch_bounds__(256, WAVES) void walk_potential_kernel(WalkArgs a) 
     const int64_t g = (int64_t)blockIdx.x * 4 + w;
     if (g >= a.n_groups) return;
     fused_group<real>(a, g, w, lane, sm);
+}
+
+// The fused walk with another opening test and/or far-field order (the
+// paper's own choices, for comparison); otherwise as walk_potential_kernel.
+template <typename real, int WAVES, int MAC, int ORDER>
+__global__ __launch_bounds__(256, WAVES) void walk_potential_opts_kernel(WalkArgs a) {
+    __shared__ FusedSmem<real> sm;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    fused_group<real, Tiles<real, ORDER>, MAC>(a, g, w, lane, sm);
+}
+
+hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
+                                      int precision, double G, double *phi, int32_t *counts, int mac, int order,
+                                      hipStream_t s) {
+    if (mac == BH_MAC_CELLS && order == 2)
+        return launch_walk_potential(g, m, theta, theta_group, precision, G, phi, counts, s);
+    WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
+    const dim3 grid((unsigned)((g->n_groups + 3) / 4)), block(256);
+#define BH_OPTS(T, W, M, O) hipLaunchKernelGGL((walk_potential_opts_kernel<T, W, M, O>), grid, block, 0, s, a)
+    if (precision == BH_FP64) {
+        if (mac == BH_MAC_GROUP_BOX && order == 2) BH_OPTS(double, kFusedDefaultWaves64, 1, 2);
+        else if (mac == BH_MAC_GROUP_BOX) BH_OPTS(double, kFusedDefaultWaves64, 1, 0);
+        else BH_OPTS(double, kFusedDefaultWaves64, 0, 0);
+    } else {
+        if (mac == BH_MAC_GROUP_BOX && order == 2) BH_OPTS(float, kFusedDefaultWaves32, 1, 2);
+        else if (mac == BH_MAC_GROUP_BOX) BH_OPTS(float, kFusedDefaultWaves32, 1, 0);
+        else BH_OPTS(float, kFusedDefaultWaves32, 0, 0);
+    }
+#undef BH_OPTS
+    return hipGetLastError();
+}
+
+// The learned-theta step in one kernel: each wavefront first evaluates the
+// network for its group (bh_theta_net.h), then walks and sums exactly as
+// walk_potential_kernel does with that theta.  The network's weight rows need
+// registers: at 6 waves per SIMD (80 VGPRs) it runs without spills or
+// scratch, faster than 8 waves with either.
+constexpr int kLearnedWaves32 = 6;
+template <typename real, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void walk_potential_learned_kernel(WalkArgs a, ThetaNetArgs net,
+                                                                            float *theta_out) {
+    __shared__ FusedSmem<real> sm;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= a.n_groups) return;
+    fused_group<real>(a, g, w, lane, sm, &net, theta_out);
+}
+
+hipError_t launch_learned_walk_potential(const bh_grid *g, const bh_moments *m, const ThetaNetArgs &net,
+                                         int precision, double G, double *phi, float *theta_out, int32_t *counts,
+                                         hipStream_t s) {
+    WalkArgs a = fused_args(g, m, 1.0, nullptr, precision, G, phi, counts, m->walk_epoch);
+    const int blocks = (int)((g->n_groups + 3) / 4);
+    if (precision == BH_FP64)
+        hipLaunchKernelGGL((walk_potential_learned_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0,
+                           s, a, net, theta_out);
+    else
+        hipLaunchKernelGGL((walk_potential_learned_kernel<float, kLearnedWaves32>), dim3(blocks), dim3(256), 0, s, a,
+                           net, theta_out);
+    return hipGetLastError();
 }
 
 // Walk fused with the potential and acceleration sums.  More live values than

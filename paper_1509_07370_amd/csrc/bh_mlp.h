@@ -7,6 +7,7 @@
 
 #include "bh.h"
 #include "bh_internal.h"
+#include "bh_theta_net.h"
 
 namespace bh {
 constexpr int kMlpIn = BH_MLP_INPUTS;
@@ -22,7 +23,6 @@ struct bh_mlp {
     bh_ctx *ctx = nullptr;
     float *d_params = nullptr;   // [kMlpParams]
     uint16_t *d_bf16 = nullptr;  // bf16 copy of the parameters
-    uint16_t *d_w2t = nullptr;   // bf16 W2 transposed, [k][u] = W2[u][k] (inference staging)
     float *d_mean = nullptr, *d_scale = nullptr;  // [kMlpIn]
     float *d_m = nullptr, *d_v = nullptr;         // Adam moments
     float *d_partials = nullptr;                  // [kMlpChunks][kMlpParams + 1]
@@ -31,6 +31,10 @@ struct bh_mlp {
 
 namespace bh {
 hipError_t launch_mlp_bf16(bh_mlp *net, hipStream_t s);
+ThetaNetArgs theta_net_args(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift);
+hipError_t launch_learned_walk_potential(const bh_grid *g, const bh_moments *m, const ThetaNetArgs &net,
+                                         int precision, double G, double *phi, float *theta_out, int32_t *counts,
+                                         hipStream_t s);
 hipError_t launch_theta_infer(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift, float *theta,
                               hipStream_t s);
 hipError_t launch_mlp_forward(const bh_mlp *net, const float *feat, int64_t n, bool bf16, float shift, float *theta,

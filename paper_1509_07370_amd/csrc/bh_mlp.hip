@@ -10,17 +10,10 @@
 #include "bh_device.h"
 #include "bh_internal.h"
 #include "bh_mlp.h"
+#include "bh_theta_net.h"
 
 namespace bh {
 
-__device__ __forceinline__ float wave_sum(float v) {
-    // fixed butterfly order: deterministic
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ double log_floor(double x, double floor) { return log(x > floor ? x : floor); }
 
 // ---------------------------------------------------------------- features
 
@@ -104,24 +97,11 @@ hipError_t launch_group_rms(const bh_grid *g, const double *phi, const double *r
 
 // ---------------------------------------------------------------- MLP
 
-constexpr int OW1 = 0, OB1 = 768, OW2 = 832, OB2 = 4928, OW3 = 4992, OB3 = 5056;
 
-__device__ __forceinline__ float bf16_round(float x) {
-    uint32_t u = __float_as_uint(x);
-    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;  // round to nearest even
-    return __uint_as_float(u);
-}
-__device__ __forceinline__ float bf16_load(const uint16_t *p, int i) { return __uint_as_float((uint32_t)p[i] << 16); }
-
-// bf16 copy of the parameters, plus W2 transposed for the inference kernel
-__global__ void to_bf16_kernel(const float *__restrict__ p, uint16_t *__restrict__ q, uint16_t *__restrict__ w2t,
-                               int n) {
+// bf16 copy of the parameters
+__global__ void to_bf16_kernel(const float *__restrict__ p, uint16_t *__restrict__ q, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint16_t b = (uint16_t)(__float_as_uint(bf16_round(p[i])) >> 16);
-    q[i] = b;
-    const int r = i - OW2;
-    if (r >= 0 && r < kMlpHidden * kMlpHidden) w2t[(r % kMlpHidden) * kMlpHidden + r / kMlpHidden] = b;
+    if (i < n) q[i] = (uint16_t)(__float_as_uint(bf16_round(p[i])) >> 16);
 }
 
 // One wavefront per sample, lane j = hidden unit j.  BF16: weights, inputs and
@@ -245,138 +225,46 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ P, fl
     P[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-// Features and bf16 network in one pass, four lanes per group (64 groups per
-// 256-thread workgroup).  The features come from node rows only (the largest
-// cell mass of the group's node is kept by the moments kernel in slot 11 of
-// its row): lane 0 of a group derives the group-level features, lanes 1..3
-// those of the three ancestor nodes.  Each lane then evaluates 16 hidden
-// units of both layers (16 independent accumulators) with the bf16 weights
-// staged once per workgroup in LDS -- W2 transposed, so that a lane reads its
-// 16 weights of one input in two 16-byte loads -- and the four partial output
-// sums of a group are added across its lanes.
-constexpr int kInferGroups = 64;   // groups per workgroup
-constexpr int kInferUnits = 16;    // hidden units per lane
-
-__device__ __forceinline__ void bf16x8_to_f32(const uint4 v, float *o) {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        o[2 * i] = __uint_as_float(w[i] << 16);
-        o[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
-    }
+// Features and bf16 network in one pass, one wavefront per group (the code
+// the walk kernel runs before walking a group, see bh_theta_net.h).
+__global__ __launch_bounds__(256) void theta_infer_kernel(const LeafInfo *__restrict__ leaves, int64_t n_groups,
+                                                          ThetaNetArgs net, float *__restrict__ theta) {
+    __shared__ float buf[4][BH_MLP_INPUTS + BH_MLP_HIDDEN];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= n_groups) return;
+    const LeafInfo L = leaves[g >> 3];
+    const int sub = (int)(g & 7);
+    const float th = group_theta(net, L, sub, lane, buf[w], buf[w] + BH_MLP_INPUTS);
+    if (lane == 0) theta[(int64_t)L.canon * 8 + sub] = th;
 }
 
-__global__ __launch_bounds__(256) void theta_infer_kernel(const LeafInfo *__restrict__ leaves,
-                                                          const double *__restrict__ mom,
-                                                          const double *__restrict__ geom,
-                                                          const int32_t *__restrict__ parent, int64_t n_groups,
-                                                          int root, double box, int nbase,
-                                                          const uint16_t *__restrict__ Pb,
-                                                          const uint4 *__restrict__ W2t,
-                                                          const float *__restrict__ mean,
-                                                          const float *__restrict__ scale, float shift,
-                                                          float *__restrict__ theta) {
-    __shared__ __align__(16) uint16_t w2t[kMlpHidden * kMlpHidden];  // [k][u] = W2[u][k]
-    __shared__ uint16_t w1[kMlpHidden * kMlpIn + kMlpHidden];        // W1 then b1
-    __shared__ uint16_t w23[2 * kMlpHidden + 1];                     // b2, w3, b3
-    __shared__ float xs[kInferGroups][kMlpIn + 1];
-    __shared__ float h1s[kInferGroups][kMlpHidden + 1];
-    for (int i = threadIdx.x; i < kMlpHidden * kMlpHidden / 8; i += blockDim.x)
-        reinterpret_cast<uint4 *>(w2t)[i] = W2t[i];
-    for (int i = threadIdx.x; i < kMlpHidden * kMlpIn + kMlpHidden; i += blockDim.x) w1[i] = Pb[OW1 + i];
-    for (int i = threadIdx.x; i < 2 * kMlpHidden + 1; i += blockDim.x) w23[i] = Pb[OB2 + i];
-    const int gl = threadIdx.x >> 2, q = threadIdx.x & 3;
-    const int64_t g = (int64_t)blockIdx.x * kInferGroups + gl;
-    const bool valid = g < n_groups;
-    LeafInfo L{};
-    int sub = 0;
-    if (valid) {
-        const int f = (int)(g >> 3);
-        sub = (int)(g & 7);
-        L = leaves[f];
-        const int gnode = L.oct_first + sub;
-        const double Mg = mom[(int64_t)gnode * kMom + 3];
-        float ft[3];
-        int nft, first;
-        if (q == 0) {
-            const double Mroot = mom[(int64_t)root * kMom + 3];
-            const double Mb = mom[(int64_t)L.block_node * kMom + 3];
-            const double mmax = mom[(int64_t)gnode * kMom + 11];
-            xs[gl][0] = 6.0f;
-            xs[gl][1] = (float)log_floor(Mroot > 0.0 ? Mg / Mroot : 0.0, 1e-30);
-            xs[gl][2] = (float)log(4.0 * L.h / box);
-            xs[gl][3] = (float)rint(log2(box / ((double)nbase * kNB * L.h)));
-            xs[gl][4] = (float)(Mg > 0.0 ? log(mmax / (Mg / 64.0)) : 0.0);
-            ft[0] = (float)(Mb > 0.0 ? log_floor(8.0 * Mg / Mb, 1e-30) : 0.0);
-            nft = 1;
-            first = 11;
-        } else {
-            const int a = q - 1;
-            const int pn = parent[L.block_node];
-            const int node = a == 0 ? gnode : (a == 1 ? L.block_node : (pn >= 0 ? pn : L.block_node));
-            const double *r = mom + (int64_t)node * kMom;
-            const double l = geom[4 * (int64_t)node + 3];
-            const double M = r[3];
-            const double qf = sqrt(r[4] * r[4] + r[5] * r[5] + r[6] * r[6] +
-                                   2.0 * (r[7] * r[7] + r[8] * r[8] + r[9] * r[9]));
-            ft[0] = (float)log(r[10] / l + 1e-6);
-            ft[1] = (float)log((M > 0.0 ? qf / (M * l * l) : 0.0) + 1e-6);
-            nft = 2;
-            first = 5 + 2 * a;
-        }
-        for (int i = 0; i < nft; i++) xs[gl][first + i] = ft[i];
-    }
-    __syncthreads();
-    if (valid && q == 0)
-        for (int i = 0; i < kMlpIn; i++) xs[gl][i] = bf16_round((xs[gl][i] - mean[i]) * scale[i]);
-    __syncthreads();
-    const int u0 = q * kInferUnits;
-    if (valid) {
-        float x[kMlpIn];
-        for (int i = 0; i < kMlpIn; i++) x[i] = xs[gl][i];
-        for (int j = 0; j < kInferUnits; j++) {
-            const int u = u0 + j;
-            float a1 = bf16_load(w1, kMlpHidden * kMlpIn + u);
-            for (int i = 0; i < kMlpIn; i++) a1 = fmaf(bf16_load(w1, u * kMlpIn + i), x[i], a1);
-            h1s[gl][u] = bf16_round(tanhf(a1));
-        }
-    }
-    __syncthreads();
-    if (!valid) return;
-    float acc[kInferUnits];
-    for (int j = 0; j < kInferUnits; j++) acc[j] = bf16_load(w23, u0 + j);
-    for (int k = 0; k < kMlpHidden; k++) {
-        const float hk = h1s[gl][k];
-        const uint4 *row = reinterpret_cast<const uint4 *>(w2t + k * kMlpHidden + u0);
-        float w[kInferUnits];
-        bf16x8_to_f32(row[0], w);
-        bf16x8_to_f32(row[1], w + 8);
-#pragma unroll
-        for (int j = 0; j < kInferUnits; j++) acc[j] = fmaf(w[j], hk, acc[j]);
-    }
-    float z = 0.0f;
-    for (int j = 0; j < kInferUnits; j++) z = fmaf(bf16_load(w23, kMlpHidden + u0 + j), bf16_round(tanhf(acc[j])), z);
-    z += __shfl_xor(z, 1, 64);
-    z += __shfl_xor(z, 2, 64);
-    if (q == 0) {
-        z += bf16_load(w23, 2 * kMlpHidden);
-        const float th = 0.2f + 0.8f / (1.0f + expf(-z)) - shift;
-        theta[(int64_t)L.canon * 8 + sub] = th < 0.05f ? 0.05f : (th > 1.0f ? 1.0f : th);
-    }
+ThetaNetArgs theta_net_args(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift) {
+    ThetaNetArgs a;
+    a.w = net->d_bf16;
+    a.mean = net->d_mean;
+    a.scale = net->d_scale;
+    a.shift = shift;
+    a.mom = m->d_mom;
+    a.geom = g->d_geom;
+    a.parent = g->d_parent;
+    a.root = g->topo.root;
+    a.nbase = g->topo.nbase;
+    a.box = g->topo.box;
+    return a;
 }
 
 hipError_t launch_theta_infer(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift, float *theta,
                               hipStream_t s) {
-    const int blocks = (int)((g->n_groups + kInferGroups - 1) / kInferGroups);
-    hipLaunchKernelGGL(theta_infer_kernel, dim3(blocks), dim3(256), 0, s, g->d_leaves, m->d_mom, g->d_geom,
-                       g->d_parent, g->n_groups, g->topo.root, g->topo.box, g->topo.nbase, net->d_bf16,
-                       reinterpret_cast<const uint4 *>(net->d_w2t), net->d_mean, net->d_scale, shift, theta);
+    const int blocks = (int)((g->n_groups + 3) / 4);
+    hipLaunchKernelGGL(theta_infer_kernel, dim3(blocks), dim3(256), 0, s, g->d_leaves, g->n_groups,
+                       theta_net_args(g, m, net, shift), theta);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_bf16(bh_mlp *net, hipStream_t s) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, net->d_params, net->d_bf16,
-                       net->d_w2t, kMlpParams);
+                       kMlpParams);
     return hipGetLastError();
 }
 

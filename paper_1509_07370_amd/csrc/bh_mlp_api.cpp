@@ -64,7 +64,6 @@ int bh_mlp_destroy(bh_mlp *net) {
     if (net->ctx && net->ctx->device >= 0) (void)hipSetDevice(net->ctx->device);
     hfree(net->d_params);
     hfree(net->d_bf16);
-    hfree(net->d_w2t);
     hfree(net->d_mean);
     hfree(net->d_scale);
     hfree(net->d_m);
@@ -90,7 +89,6 @@ int bh_mlp_create(bh_ctx *ctx, bh_mlp **out, const float *params, const float *m
     hipError_t e;
     if ((e = hipMalloc((void **)&n->d_params, P * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_bf16, P * sizeof(uint16_t))) != hipSuccess ||
-        (e = hipMalloc((void **)&n->d_w2t, bh::kMlpHidden * bh::kMlpHidden * sizeof(uint16_t))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_mean, bh::kMlpIn * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_scale, bh::kMlpIn * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void **)&n->d_m, P * sizeof(float))) != hipSuccess ||
@@ -140,6 +138,22 @@ int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat, int64_t n,
     if (!std::isfinite(theta_shift)) return fail(ctx, BH_EINVAL, "theta_shift must be finite");
     HIPX(ctx, bh::launch_mlp_forward(net, feat, n, bf16 != 0, theta_shift, theta, ctx->stream),
          "network forward kernel");
+    return BH_OK;
+}
+
+int bh_learned_walk_potential(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift,
+                              int precision, double G, double *phi, float *theta, int32_t *counts) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!g || !m || !net || !phi) return fail(ctx, BH_EINVAL, "grid, moments, network or phi_dev is NULL");
+    if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
+    if (!std::isfinite(shift)) return fail(ctx, BH_EINVAL, "theta_shift must be finite");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    m->walk_epoch++;
+    HIPX(ctx, bh::launch_learned_walk_potential(g, m, bh::theta_net_args(g, m, net, shift), precision, G, phi, theta,
+                                                counts, ctx->stream),
+         "learned-theta walk + potential kernel");
     return BH_OK;
 }
 

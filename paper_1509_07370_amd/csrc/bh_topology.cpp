@@ -13,6 +13,7 @@
 // neighbours and walk similar parts of the tree.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <functional>
 #include <unordered_map>
 
@@ -225,16 +226,26 @@ std::string build_topology(Topology &t, int n, const int32_t *level, const doubl
         t.geom[4 * i + 2] = box_lo[2] + ((double)d.iz + 0.5) * l;
         t.geom[4 * i + 3] = l;
     }
-    // nodes whose moments combine 8 node children (virtual, parent blocks), by depth, deepest first
-    std::vector<std::vector<int32_t>> by_depth(maxd + 1);
-    for (size_t i = 0; i < nodes.size(); i++)
-        if (nodes[i].kind == VIRTUAL || nodes[i].kind == PARENT_BLOCK) by_depth[nodes[i].depth].push_back((int32_t)i);
+    // nodes above the leaf blocks (virtual, parent blocks): their moments come
+    // from the leaf blocks below them
     t.combine_nodes.clear();
-    t.combine_off.assign(1, 0);
-    for (int d = maxd; d >= 0; d--) {
-        if (by_depth[d].empty()) continue;
-        t.combine_nodes.insert(t.combine_nodes.end(), by_depth[d].begin(), by_depth[d].end());
-        t.combine_off.push_back((int64_t)t.combine_nodes.size());
+    for (size_t i = 0; i < nodes.size(); i++)
+        if (nodes[i].kind == VIRTUAL || nodes[i].kind == PARENT_BLOCK) t.combine_nodes.push_back((int32_t)i);
+    // leaves are numbered depth-first, so the leaf blocks below any node form
+    // one contiguous range of leaf ordinals
+    std::vector<int32_t> lo_leaf(nodes.size(), INT32_MAX), hi_leaf(nodes.size(), -1), n_below(nodes.size(), 0);
+    for (int f = 0; f < nleaf; f++)
+        for (int32_t a = t.parent[t.leaves[f].block_node]; a >= 0; a = t.parent[a]) {
+            lo_leaf[a] = std::min(lo_leaf[a], (int32_t)f);
+            hi_leaf[a] = std::max(hi_leaf[a], (int32_t)f);
+            n_below[a]++;
+        }
+    t.combine_range.assign(t.combine_nodes.size() * 2, 0);
+    for (size_t q = 0; q < t.combine_nodes.size(); q++) {
+        const int32_t a = t.combine_nodes[q];
+        if (hi_leaf[a] < 0 || hi_leaf[a] - lo_leaf[a] + 1 != n_below[a]) return "leaf order is not depth-first";
+        t.combine_range[2 * q + 0] = lo_leaf[a];
+        t.combine_range[2 * q + 1] = hi_leaf[a] + 1;
     }
     return "";
 }

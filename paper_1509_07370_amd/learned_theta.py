@@ -146,8 +146,16 @@ class ThetaNet:
 
 def solve_learned(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi: torch.Tensor, feat: torch.Tensor,
                   theta: torch.Tensor, precision=B.BH_FP32, G=1.0):
-    """moments -> features + bf16 network (one kernel) -> fused walk + sums with per-group theta.
-    ``feat`` is unused (kept for callers that stage features separately)."""
+    """moments -> one kernel: per group, features + bf16 network, then the walk + sums with that theta
+    (the thetas used land in ``theta``).  ``feat`` is unused (kept for callers that stage features)."""
+    bh.build_moments(rho)
+    B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, precision, G, phi, theta)
+    return phi
+
+
+def solve_learned_two_step(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi: torch.Tensor, theta: torch.Tensor,
+                           precision=B.BH_FP32, G=1.0):
+    """The same step in two launches: bh_theta_infer, then bh_walk_potential with the theta array."""
     bh.build_moments(rho)
     B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, theta, net.shift)
     B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta, precision, G, phi, None)

@@ -1,0 +1,104 @@
+"""bh_walk_potential_ex (the paper's opening test and far field) vs the oracle.
+
+* group-cube opening test (O5b) and monopole-only far field, in every
+  combination, fp64 and fp32: far/near counts equal to the oracle's walk
+  with the same test and potentials within 1e-12 (fp64) / 1e-5 (fp32) of the
+  oracle's sum, except in groups holding a marginal decision (exact lattice
+  ties included), of which at most 1% may differ;
+* the default options give bh_walk_potential's bits; bad options are refused.
+"""
+import numpy as np
+import pytest
+
+from amr_inputs import maclaurin_spheroid, random_amr
+from oracle import OracleTree
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1509_07370_amd import binding as B  # noqa: E402
+from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
+
+TAU = {B.BH_FP64: 1e-12, B.BH_FP32: 2e-6}
+TOL = {B.BH_FP64: 1e-12, B.BH_FP32: 1e-5}
+GRIDS = {
+    "random_amr": lambda: random_amr(21, nbase=2, max_level=3, p_refine=0.3, zero_fraction=0.1),
+    "maclaurin_l1": lambda: maclaurin_spheroid(max_level=1),
+}
+_cache = {}
+
+
+def setup(name):
+    if name not in _cache:
+        g = GRIDS[name]()
+        bh = BarnesHut(g)
+        rho = torch.tensor(g.rho, device="cuda")
+        bh.build_moments(rho)
+        _cache[name] = (g, bh, rho, OracleTree(g))
+    return _cache[name]
+
+
+def _group_of_cell(nleaf):
+    k, j, i = np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij")
+    m = np.zeros_like(i)
+    for b in range(3):
+        m |= ((i >> b) & 1) << (3 * b)
+        m |= ((j >> b) & 1) << (3 * b + 1)
+        m |= ((k >> b) & 1) << (3 * b + 2)
+    return np.arange(nleaf)[:, None, None, None] * 8 + (m // 64)[None]
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+@pytest.mark.parametrize("precision", [B.BH_FP64, B.BH_FP32])
+@pytest.mark.parametrize("mac,order", [(B.BH_MAC_GROUP_BOX, 2), (B.BH_MAC_CELLS, 0), (B.BH_MAC_GROUP_BOX, 0)])
+@pytest.mark.parametrize("theta", [0.5, 0.9])
+def test_options_match_oracle(name, precision, mac, order, theta):
+    g, bh, rho, t = setup(name)
+    ng = bh.info["n_groups"]
+    phi = torch.full_like(rho, float("nan"))
+    counts = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, theta, None, precision, 1.0, phi, counts, mac=mac, order=order)
+    bh.check()
+    ow = t.walk(64, theta, tau=TAU[precision], mac=mac)
+    ref = t.potential(order=order)
+    # on lattice-aligned meshes the cube test meets exact ties often (flagged marginal, decided
+    # alike by both sides: equality opens); a group may differ from the oracle only if it holds
+    # a marginal decision, and only a few may
+    marginal = ow["marginal"] > 0
+    c = counts.cpu().numpy()
+    differ = (c[:, 0] != ow["n_far"]) | (c[:, 1] != ow["n_near"])
+    p = phi.cpu().numpy()
+    rel = (np.abs(p - ref) / np.abs(ref)).reshape(g.nleaf, -1)
+    grp = _group_of_cell(g.nleaf).reshape(g.nleaf, -1)
+    worst = np.zeros(ng)
+    np.maximum.at(worst, grp.ravel(), rel.ravel())
+    bad = differ | (worst > TOL[precision])
+    assert np.all(marginal[bad]), worst[bad & ~marginal].max() if (bad & ~marginal).any() else None
+    assert bad.sum() <= max(3, ng // 100), (bad.sum(), ng)
+
+
+def test_group_box_opens_more_than_the_cell_vote():
+    g, bh, rho, t = setup("maclaurin_l1")
+    ng = bh.info["n_groups"]
+    phi = torch.empty_like(rho)
+    c_cell = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    c_box = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, 0.7, None, B.BH_FP32, 1.0, phi, c_cell)
+    B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, 0.7, None, B.BH_FP32, 1.0, phi, c_box, mac=B.BH_MAC_GROUP_BOX)
+    cell, box = c_cell.cpu().numpy().astype(np.int64), c_box.cpu().numpy().astype(np.int64)
+    work = lambda c: 64 * c[:, 0] + 512 * c[:, 1]  # noqa: E731
+    assert work(box).sum() > work(cell).sum()
+
+
+def test_default_options_are_the_default_path_and_bad_options_fail():
+    g, bh, rho, t = setup("random_amr")
+    a, b = torch.empty_like(rho), torch.empty_like(rho)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.6, None, B.BH_FP32, 1.0, a, None)
+    B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, 0.6, None, B.BH_FP32, 1.0, b, None)
+    assert torch.equal(a, b)
+    for bad in (dict(mac=2), dict(order=1), dict(order=4)):
+        with pytest.raises(B.BHError):
+            B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, 0.6, None, B.BH_FP32, 1.0, b, None, **bad)
