@@ -292,11 +292,15 @@ struct Prec<double> {
 
 // min over k in [0, n) of |fl(x0 + k h - X)|.  x0 + k h is exact (dyadic), and
 // fl(a - X) is monotone in a, so the minimum sits at one of the two lattice
-// points around X; both are evaluated exactly as a per-cell test would.
+// points around X; both are evaluated exactly as a per-cell test would.  The
+// bracketing index needs only to be right to within one: (X - x0) * (1/h)
+// instead of a division can move floor() by one only where X is within
+// rounding of a lattice point, and that point is still one of the two
+// candidates.
 template <typename real>
-__device__ __forceinline__ real nearest_gap(real x0, real h, real X, int n) {
+__device__ __forceinline__ real nearest_gap(real x0, real h, real hinv, real X, int n) {
 #pragma clang fp contract(off)
-    real t = (X - x0) / h;
+    real t = (X - x0) * hinv;
     int k = (int)floor(t);
     k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
     int k2 = k + 1 > n - 1 ? n - 1 : k + 1;
@@ -336,7 +340,7 @@ struct Walker {
     int *stk;
     int size;
     int k8;
-    real x0, y0, z0, h, inv;
+    real x0, y0, z0, h, hinv, inv;
     real blo[3], bhi[3];  // MAC 1 only
     bool overflow;
 
@@ -348,6 +352,7 @@ struct Walker {
         overflow = false;
         const int i0 = (sub & 1) * 4, j0 = ((sub >> 1) & 1) * 4, k0 = ((sub >> 2) & 1) * 4;
         h = (real)L.h;
+        hinv = (real)1 / h;
         x0 = (real)(L.lo[0] + (i0 + 0.5) * L.h);
         y0 = (real)(L.lo[1] + (j0 + 0.5) * L.h);
         z0 = (real)(L.lo[2] + (k0 + 0.5) * L.h);
@@ -404,9 +409,9 @@ struct Walker {
                     dy = cube_gap<real>(blo[1], bhi[1], r.y);
                     dz = cube_gap<real>(blo[2], bhi[2], r.z);
                 } else {
-                    dx = nearest_gap<real>(x0, h, r.x, 4);
-                    dy = nearest_gap<real>(y0, h, r.y, 4);
-                    dz = nearest_gap<real>(z0, h, r.z, 4);
+                    dx = nearest_gap<real>(x0, h, hinv, r.x, 4);
+                    dy = nearest_gap<real>(y0, h, hinv, r.y, 4);
+                    dz = nearest_gap<real>(z0, h, hinv, r.z, 4);
                 }
                 real d2 = dx * dx + dy * dy + dz * dz;
                 real s = r.l * inv + r.delta;

@@ -302,7 +302,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train", "evaluate"])
     ap.add_argument("--weights", default=None)
-    ap.add_argument("--target", type=float, default=1e-3)
+    ap.add_argument("--target", default="1e-3", help="RMS target, as it appears in the weights file name")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=None)
@@ -314,14 +314,15 @@ def main(argv=None):
 
     ctx = B.bh_ctx_create(0)
     if args.cmd == "evaluate":
-        net = ThetaNet.load(ctx, args.weights or os.path.join(DATA_DIR, "theta_mlp_%g.npz" % args.target))
-        res = evaluate(net, evaluation_grids(), float(net.meta.get("target", args.target)), log=log)
+        net = ThetaNet.load(ctx, args.weights or os.path.join(DATA_DIR, "theta_mlp_%s.npz" % args.target))
+        res = evaluate(net, evaluation_grids(), float(net.meta.get("target", float(args.target))), log=log)
         print(json.dumps(dict(target=net.meta.get("target"), shift=net.shift, results=res)))
         return 0
-    F, Y, E = build_dataset(training_grids(), args.target, log)
+    target = float(args.target)
+    F, Y, E = build_dataset(training_grids(), target, log)
     X, y = np.concatenate(F), np.concatenate(Y)
     net = ThetaNet.fresh(ctx, X, glorot_init(42).astype(np.float32),
-                         meta=dict(target=args.target, epochs=args.epochs, lr=args.lr, n_train=int(len(y)), seed=42))
+                         meta=dict(target=target, epochs=args.epochs, lr=args.lr, n_train=int(len(y)), seed=42))
     fx = torch.tensor(X, device="cuda")
     fy = torch.tensor(y, device="cuda")
     t0 = time.time()
@@ -330,9 +331,9 @@ def main(argv=None):
     pred = net.predict(fx, bf16=True).cpu().numpy()
     log("train mse %.3e, mean |pred - label| %.3f, label mean %.3f" % (
         float(np.mean((pred - y) ** 2)), float(np.mean(np.abs(pred - y))), float(y.mean())))
-    net.meta["theta_shift"] = calibrate_shift(net, F, E, args.target)
+    net.meta["theta_shift"] = calibrate_shift(net, F, E, target)
     log("calibrated output shift %.3f" % net.meta["theta_shift"])
-    out = args.out or os.path.join(DATA_DIR, "theta_mlp_%g.npz" % args.target)
+    out = args.out or os.path.join(DATA_DIR, "theta_mlp_%s.npz" % args.target)
     net.save(out)
     log("saved " + out)
     return 0
