@@ -30,6 +30,10 @@
  *  - Group order ("canonical group order"): leaf-major, then the aligned
  *    Morton runs of group_cells cells inside the block (Morton bit 0 = x).
  *  - Results are deterministic for a fixed grid, input and parameter set.
+ *  - Calls that use one moments handle must not overlap (issue them on one
+ *    stream, or synchronise between streams): they share its device
+ *    workspace (status flags, the per-group costs that each fused walk
+ *    records, and the dispatch order built from them).
  */
 #ifndef BH_H
 #define BH_H
@@ -127,7 +131,14 @@ int bh_grid_node_keys(const bh_grid *grid, uint64_t *keys);
  * rho_dev: fp64 caller layout, read only.  *m is created on first use (pass
  * *m == NULL) and reused when non-NULL (it must belong to `grid`).
  * Densities must be finite and >= 0: a violation is detected on the device;
- * bh_walk (or bh_moments_check) then fails with BH_EINVAL. */
+ * bh_walk (or bh_moments_check) then fails with BH_EINVAL.
+ * Dispatch schedule: once a fused walk (bh_walk_potential[_ex],
+ * bh_walk_accel, bh_learned_walk_potential) has run on *m, this call also
+ * sorts the groups by the work that walk recorded for each (heaviest first);
+ * later fused walks start their groups in that order, which balances the
+ * end of the launch and leaves every result unchanged bit for bit.  The sort
+ * runs inside the moments kernels (no extra launch) and leaves no state that
+ * a replay of a captured graph would have to reset. */
 int bh_build_moments(bh_ctx *ctx, const bh_grid *grid, const double *rho_dev, bh_moments **m);
 /* Synchronise and report device-side conditions: BH_EINVAL if the densities
  * seen by the last bh_build_moments were invalid, BH_ECAPACITY if the last walk

@@ -236,6 +236,9 @@ int bh_moments_destroy(bh_moments *m) {
     hfree(m->d_cell64);
     hfree(m->d_cell32);
     hfree(m->d_flags);
+    hfree(m->d_cost);
+    hfree(m->d_order);
+    hfree(m->d_sched);
     delete m;
     return BH_OK;
 }
@@ -257,13 +260,21 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
             (e = dalloc(&m->d_w32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_w64, (size_t)nn)) != hipSuccess ||
             (e = dalloc(&m->d_f32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_cell64, (size_t)nc)) != hipSuccess ||
             (e = dalloc(&m->d_cell32, (size_t)nc)) != hipSuccess || (e = dalloc(&m->d_flags, 2)) != hipSuccess ||
-            (e = hipMemset(m->d_flags, 0, 2 * sizeof(int))) != hipSuccess) {
+            (e = hipMemset(m->d_flags, 0, 2 * sizeof(int))) != hipSuccess ||
+            (e = dalloc(&m->d_cost, (size_t)g->n_groups)) != hipSuccess ||
+            (e = dalloc(&m->d_order, (size_t)g->n_groups)) != hipSuccess ||
+            (e = dalloc(&m->d_sched, 2 * 256 + 1)) != hipSuccess ||
+            (e = hipMemset(m->d_sched, 0, (2 * 256 + 1) * sizeof(int))) != hipSuccess) {
             bh_moments_destroy(m);
             return hip_fail(ctx, e, "device allocation of the moments");
         }
         *mp = m;
     }
-    HIPX(ctx, bh::launch_moments(g, m, rho, ctx->stream), "moments kernels");
+    // once a fused walk has recorded its costs, the upward pass also sorts the
+    // groups by them, for the dispatch order of the next fused walks
+    const bool schedule = m->cost_valid && g->n_groups > 1;
+    HIPX(ctx, bh::launch_moments(g, m, rho, ctx->stream, 0, schedule), "moments kernels");
+    if (schedule) m->order_valid = true;
     return BH_OK;
 }
 

@@ -82,6 +82,10 @@ struct WalkArgs {
     double *phi;
     int32_t *counts;
     double *acc;  // accelerations [cell][3] (acceleration kernels only)
+    // single-grid fused kernels: dispatch order of the groups (NULL: natural)
+    // and each group's algorithmic cost, written for the next call's order
+    const int32_t *order;
+    uint32_t *cost_out;
 };
 
 // Host-side octree topology built from the block list.
@@ -145,6 +149,14 @@ struct bh_moments {
     int *d_flags = nullptr;
     int mom_epoch = 0;
     mutable int walk_epoch = 0;
+    // dispatch schedule of the fused walks (single-grid calls): each fused
+    // walk records the cost of every group; the next upward pass sorts the
+    // groups by it into the order that the following fused walks dispatch
+    uint32_t *d_cost = nullptr;   // [n_groups], internal group order
+    int32_t *d_order = nullptr;   // [n_groups]
+    int *d_sched = nullptr;       // bin histogram [256], placement cursors [256], finished count: zero between passes
+    mutable bool cost_valid = false;  // d_cost holds a walk's costs
+    bool order_valid = false;         // d_order holds a permutation
 };
 
 struct bh_lists {
@@ -163,7 +175,10 @@ struct bh_lists {
 namespace bh {
 // kernel launchers (bh_kernels.hip); all enqueue on `s`.
 // epoch > 0: stamp invalid densities with that value instead of a new epoch
-hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int epoch = 0);
+// Upward pass.  schedule: also sort the groups by the costs that the last
+// fused walk recorded, into the dispatch order of the next fused walks.
+hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int epoch = 0,
+                          bool schedule = false);
 WalkArgs fused_args(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group, int precision,
                     double G, double *phi, int32_t *counts, int epoch);
 hipError_t launch_batch_reset(const WalkArgs *grids, int n, unsigned long long *counter, hipStream_t s);

@@ -3,7 +3,8 @@
 //   moments_leaf_kernel    one workgroup per leaf block: cells -> 64 bottom nodes
 //                          -> 8 octants -> block node by lane shuffles (fp64)
 //   moments_upper_kernel   the nodes above the leaf blocks, one workgroup per
-//                          node, each from the leaf blocks below it
+//                          node, each from the leaf blocks below it; beside
+//                          them, the placement of the walks' dispatch order
 //   walk_kernel            one wavefront per 64-cell group: breadth-limited
 //                          depth-first traversal with an LDS stack of sibling
 //                          sets; 64 lanes test 8 sibling sets at once, the
@@ -133,6 +134,117 @@ __device__ __forceinline__ void combine_lanes(double m, double x, double y, doub
     Q[5] = sum8(qc[5] + m * (3.0 * dy * dz));
 }
 
+// ---------------------------------------------------------------- dispatch schedule
+//
+// The fused walks dispatch their groups heaviest first (the longest start
+// first and short ones fill the end of the launch), in the order of the work
+// that the previous fused walk recorded per group.  The upward pass builds
+// that order as a counting sort over 256 bins of log2 cost (1/8 octave
+// each), with no launch of its own: the leaf-block kernel counts each block's
+// groups into a histogram, and the upper-node kernel, once the histogram is
+// complete, places every group at its bin's start plus a cursor taken with an
+// atomic.  The last workgroup of the placement to finish returns the
+// histogram and the cursors to zero, so that every pass -- also each replay
+// of a captured graph -- starts from zero.  The order within a bin follows
+// the atomics; it decides which wavefront computes a group, not what it
+// computes.
+struct SchedArgs {
+    const uint32_t *cost;  // [n_groups] from the last fused walk; NULL: no schedule in this pass
+    int *hist;             // [256] bin counts (zero between passes)
+    int *cursor;           // [256] placement cursors (zero between passes)
+    int *done;             // workgroups of the placement that have finished (zero between passes)
+    int32_t *order;        // [n_groups] dispatch order
+    int64_t n_groups;
+    int parts;             // workgroups of the placement, the first ones of the upper-node launch
+};
+
+__device__ __forceinline__ int cost_bin(uint32_t c) {
+    const int b = (int)(log2f((float)c + 1.0f) * 8.0f);
+    return 255 - (b > 255 ? 255 : b);
+}
+
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Lanes of a wavefront grouped by equal key: each active lane gets the lowest
+// lane with its key (the leader), its rank among those lanes and their
+// number.  One pass per distinct key; called by the whole wavefront.
+__device__ __forceinline__ void wave_key_groups(int key, bool active, int &leader, int &rank, int &count) {
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t todo = __ballot(active);
+    leader = lane;
+    rank = 0;
+    count = 0;
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const int k = __shfl(key, l);
+        const bool mine = active && key == k;
+        const uint64_t same = __ballot(mine);
+        if (mine) {
+            leader = l;
+            rank = __popcll(same & below);
+            count = __popcll(same);
+        }
+        todo &= ~same;
+    }
+}
+
+// Histogram of the 8 groups of leaf block f (first 8 lanes of a wavefront;
+// one atomic per distinct bin).  Called by whole wavefronts.
+__device__ __forceinline__ void sched_count(const SchedArgs &sa, int f, int lane) {
+    const bool act = lane < 8;
+    const int b = cost_bin(sa.cost[(int64_t)f * 8 + (act ? lane : 0)]);
+    int leader, rank, count;
+    wave_key_groups(b, act, leader, rank, count);
+    if (act && leader == lane) atomicAdd(&sa.hist[b], count);
+}
+
+// Places the groups [q0, q1) (one 256-thread workgroup): exclusive scan of
+// the complete histogram into bin starts, then per wavefront one atomic per
+// distinct bin reserves consecutive slots.  The workgroup that finishes last
+// clears the histogram, the cursors and the counter: every other workgroup's
+// reads of the histogram and cursor atomics have returned before its count
+// is taken, so nothing is read after the clearing.
+__device__ void sched_place(const SchedArgs &sa, int64_t q0, int64_t q1, int *start, int *wave_total) {
+    const int t = threadIdx.x, lane = t & 63;
+    const int v = sa.hist[t];
+    const int incl = wave_inclusive_scan(v);
+    if (lane == 63) wave_total[t >> 6] = incl;
+    __syncthreads();
+    int base = incl - v;
+    for (int w = 0; w < (t >> 6); w++) base += wave_total[w];
+    start[t] = base;
+    __syncthreads();
+    for (int64_t qb = q0; qb < q1; qb += 256) {
+        const int64_t q = qb + t;
+        const bool act = q < q1;
+        const int b = cost_bin(sa.cost[act ? q : q0]);
+        int leader, rank, count;
+        wave_key_groups(b, act, leader, rank, count);
+        int old = 0;
+        if (act && leader == lane) old = atomicAdd(&sa.cursor[b], count);
+        old = __shfl(old, leader);
+        if (act) sa.order[start[b] + old + rank] = (int32_t)q;
+    }
+    __shared__ int last;
+    __syncthreads();
+    if (t == 0) last = atomicAdd(sa.done, 1) == sa.parts - 1;
+    __syncthreads();
+    if (last) {
+        sa.hist[t] = 0;
+        sa.cursor[t] = 0;
+        if (t == 0) *sa.done = 0;
+    }
+}
+
 // In-block part of the upward pass, one 512-thread workgroup per leaf block.
 // Thread t owns cell t of the block in Morton order, so the 8 cells of bottom
 // node b sit in lanes 8b..8b+7 and combine by lane shuffles; the 64 bottom
@@ -143,7 +255,7 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
                                                            const double *__restrict__ geom,
                                                            const int32_t *__restrict__ child_arr, MomOut out,
                                                            double4 *__restrict__ cell64, float4 *__restrict__ cell32,
-                                                           int *__restrict__ flags, int epoch) {
+                                                           int *__restrict__ flags, int epoch, SchedArgs sa) {
 #pragma clang fp contract(off)
     __shared__ double bM[64], bX[64], bY[64], bZ[64], bQ[64][6], bmax[64];
     const int f = blockIdx.x;
@@ -178,7 +290,10 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
         }
     }
     __syncthreads();
-    if (t >= 64) return;
+    if (t >= 64) {
+        if (sa.cost && t < 128) sched_count(sa, f, t - 64);  // the dispatch schedule's histogram
+        return;
+    }
     // octant t >> 3 from its 8 bottom nodes (lane t holds bottom node t)
     double M, X, Y, Z, Q[6];
     combine_lanes(bM[t], bX[t], bY[t], bZ[t], bQ[t], M, X, Y, Z, Q);
@@ -224,10 +339,17 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
                                                             const int32_t *__restrict__ range,
                                                             const LeafInfo *__restrict__ leaves,
                                                             const double *__restrict__ geom,
-                                                            const int32_t *__restrict__ child_arr, MomOut out) {
+                                                            const int32_t *__restrict__ child_arr, MomOut out,
+                                                            SchedArgs sa) {
 #pragma clang fp contract(off)
     __shared__ double red[4];
-    const int q = blockIdx.x;
+    if (sa.cost && (int)blockIdx.x < sa.parts) {  // a share of the dispatch schedule's placement
+        __shared__ int start[256], wave_total[4];
+        const int64_t n = sa.n_groups, p = blockIdx.x;
+        sched_place(sa, n * p / sa.parts, n * (p + 1) / sa.parts, start, wave_total);
+        return;
+    }
+    const int q = blockIdx.x - (sa.cost ? sa.parts : 0);
     const int id = nodes[q];
     const int f0 = range[2 * q], f1 = range[2 * q + 1];
     double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
@@ -260,18 +382,26 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
     if (threadIdx.x == 0) store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], 0);
 }
 
-hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int fixed_epoch) {
+hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int fixed_epoch,
+                          bool schedule) {
     MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32};
     const int nleaf = (int)g->topo.leaves.size();
     const int epoch = fixed_epoch > 0 ? fixed_epoch : ++m->mom_epoch;
+    SchedArgs sa{};
+    if (schedule) {
+        if (g->n_groups != 8 * (int64_t)nleaf) return hipErrorInvalidValue;
+        // one placement workgroup per 256 groups, launched beside the node workgroups
+        sa = SchedArgs{m->d_cost, m->d_sched, m->d_sched + 256, m->d_sched + 512, m->d_order, g->n_groups,
+                       (int)((g->n_groups + 255) / 256)};
+    }
     hipLaunchKernelGGL(moments_leaf_kernel, dim3(nleaf), dim3(512), 0, s, rho, g->d_leaves, g->d_geom, g->d_child, o,
-                       m->d_cell64, m->d_cell32, m->d_flags, epoch);
+                       m->d_cell64, m->d_cell32, m->d_flags, epoch, sa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nupper = (int)g->topo.combine_nodes.size();
-    if (nupper == 0) return hipSuccess;
-    hipLaunchKernelGGL(moments_upper_kernel, dim3(nupper), dim3(256), 0, s, g->d_combine, g->d_combine_range,
-                       g->d_leaves, g->d_geom, g->d_child, o);
+    const int64_t blocks = (int64_t)g->topo.combine_nodes.size() + sa.parts;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(moments_upper_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g->d_combine,
+                       g->d_combine_range, g->d_leaves, g->d_geom, g->d_child, o, sa);
     return hipGetLastError();
 }
 
@@ -998,6 +1128,20 @@ struct FusedSmem {
     V4 tile[4][64 * 3];
 };
 
+// The wavefront's group: slot q of the dispatch order (groups by decreasing
+// cost of the previous walk, so that the longest start first and the end of
+// the launch is filled with short ones), or q itself; -1 past the end.
+__device__ __forceinline__ int64_t dispatch_group(const WalkArgs &a, int64_t q) {
+    if (q >= a.n_groups) return -1;
+    return a.order ? (int64_t)a.order[q] : q;
+}
+
+// algorithmic cost of a group from its counts: 35 flop x 64 cells per far node,
+// 11 flop x 512 pairs per near bottom node
+__device__ __forceinline__ uint32_t group_cost(int nfar, int nnear) {
+    return 35u * 64u * (uint32_t)nfar + 11u * 512u * (uint32_t)nnear;
+}
+
 // one group g of the grid described by a, on wavefront w of the workgroup;
 // TL: the tile evaluator (potential, or potential and acceleration)
 // theta_net: NULL, or the network that gives this group's theta first (its
@@ -1098,6 +1242,17 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
         a.counts[2 * cg + 0] = ftot;
         a.counts[2 * cg + 1] = ntot;
     }
+    if (a.cost_out && lane == 0) a.cost_out[g] = group_cost(ftot, ntot);
+}
+
+// Attach the schedule to a single-grid fused walk: dispatch in the order that
+// the last upward pass built (natural order before there is one), and record
+// this walk's costs for the next.
+static hipError_t attach_schedule(const bh_grid *, const bh_moments *m, WalkArgs &a, hipStream_t) {
+    a.cost_out = m->d_cost;
+    a.order = m->order_valid ? m->d_order : nullptr;
+    m->cost_valid = true;
+    return hipSuccess;
 }
 
 template <typename real, int WAVES>
@@ -1105,8 +1260,8 @@ __global__ __launch_bounds__(256, WAVES) void walk_potential_kernel(WalkArgs a) 
     __shared__ FusedSmem<real> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
+    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
+    if (g < 0) return;
     fused_group<real>(a, g, w, lane, sm);
 }
 
@@ -1117,8 +1272,8 @@ __global__ __launch_bounds__(256, WAVES) void walk_potential_opts_kernel(WalkArg
     __shared__ FusedSmem<real> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
+    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
+    if (g < 0) return;
     fused_group<real, Tiles<real, ORDER>, MAC>(a, g, w, lane, sm);
 }
 
@@ -1128,6 +1283,8 @@ hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, dou
     if (mac == BH_MAC_CELLS && order == 2)
         return launch_walk_potential(g, m, theta, theta_group, precision, G, phi, counts, s);
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
+    hipError_t e0 = attach_schedule(g, m, a, s);
+    if (e0 != hipSuccess) return e0;
     const dim3 grid((unsigned)((g->n_groups + 3) / 4)), block(256);
 #define BH_OPTS(T, W, M, O) hipLaunchKernelGGL((walk_potential_opts_kernel<T, W, M, O>), grid, block, 0, s, a)
     if (precision == BH_FP64) {
@@ -1155,8 +1312,8 @@ __global__ __launch_bounds__(256, WAVES) void walk_potential_learned_kernel(Walk
     __shared__ FusedSmem<real> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
+    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
+    if (g < 0) return;
     fused_group<real>(a, g, w, lane, sm, &net, theta_out);
 }
 
@@ -1164,6 +1321,8 @@ hipError_t launch_learned_walk_potential(const bh_grid *g, const bh_moments *m, 
                                          int precision, double G, double *phi, float *theta_out, int32_t *counts,
                                          hipStream_t s) {
     WalkArgs a = fused_args(g, m, 1.0, nullptr, precision, G, phi, counts, m->walk_epoch);
+    hipError_t e0 = attach_schedule(g, m, a, s);
+    if (e0 != hipSuccess) return e0;
     const int blocks = (int)((g->n_groups + 3) / 4);
     if (precision == BH_FP64)
         hipLaunchKernelGGL((walk_potential_learned_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0,
@@ -1183,8 +1342,8 @@ __global__ __launch_bounds__(256, WAVES) void walk_accel_kernel(WalkArgs a) {
     __shared__ FusedSmem<real> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
+    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
+    if (g < 0) return;
     fused_group<real, TilesAcc<real>>(a, g, w, lane, sm);
 }
 
@@ -1192,6 +1351,8 @@ hipError_t launch_walk_accel(const bh_grid *g, const bh_moments *m, double theta
                              int precision, double G, double *phi, double *acc, int32_t *counts, hipStream_t s) {
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     a.acc = acc;
+    hipError_t e0 = attach_schedule(g, m, a, s);
+    if (e0 != hipSuccess) return e0;
     const int blocks = (int)((g->n_groups + 3) / 4);
     if (precision == BH_FP64)
         hipLaunchKernelGGL((walk_accel_kernel<double, kAccelWaves64>), dim3(blocks), dim3(256), 0, s, a);
@@ -1240,6 +1401,8 @@ __global__ void batch_reset_kernel(const WalkArgs *__restrict__ grids, int n, un
 hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                                  int precision, double G, double *phi, int32_t *counts, hipStream_t s) {
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
+    hipError_t e0 = attach_schedule(g, m, a, s);
+    if (e0 != hipSuccess) return e0;
     const int blocks = (int)((g->n_groups + 3) / 4);
     if (precision == BH_FP64)
         hipLaunchKernelGGL((walk_potential_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0, s, a);
