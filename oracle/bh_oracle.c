@@ -43,6 +43,8 @@
  *  O8 accel   - g_i = -grad_i phi_i, the gradient of O7 term by term (an
  *               extension: the paper's method yields the potential only;
  *               forces are the item its section 3.1 writes back next to it).
+ *  O9 Ewald   - the periodic Green's function of the appendix (below).
+ *  O10 periodic BH - O5-O7 in a periodic box (below).
  *
  * Tree shape: the box is the root (depth 0); log2(nbase) virtual levels lead
  * down to the level-0 blocks; an AMR block of level L sits at depth
@@ -68,6 +70,7 @@ typedef struct {
     int child[8];   /* node ids (internal) */
     int64_t cell[8]; /* canonical cell ids (bottom) */
     double M, X[3], Q[6], delta; /* Q order: xx yy zz xy xz yz */
+    double S;                    /* sum m |r - X|^2 (trace of the second moments about X) */
 } onode;
 
 typedef struct {
@@ -342,7 +345,7 @@ static void acc1_fn(const otree *t, int64_t c, void *p) {
     nadd(&a->sy, m * t->cy[c]);
     nadd(&a->sz, m * t->cz[c]);
 }
-typedef struct { double X[3]; nsum q[6]; } acc2;
+typedef struct { double X[3]; nsum q[6]; nsum s; } acc2;
 static void acc2_fn(const otree *t, int64_t c, void *p) {
     acc2 *a = (acc2 *)p;
     double m = t->cm[c];
@@ -354,6 +357,7 @@ static void acc2_fn(const otree *t, int64_t c, void *p) {
     nadd(&a->q[3], m * (3.0 * dx * dy));
     nadd(&a->q[4], m * (3.0 * dx * dz));
     nadd(&a->q[5], m * (3.0 * dy * dz));
+    nadd(&a->s, m * r2);
 }
 
 /* O3: every node's moments straight from its own cells */
@@ -375,14 +379,21 @@ void ot_moments(otree *t) {
             for (int d = 0; d < 3; d++) s2.X[d] = a->X[d];
             for_cells(t, n, acc2_fn, &s2);
             for (int q = 0; q < 6; q++) a->Q[q] = nval(&s2.q[q]);
+            a->S = nval(&s2.s);
             double ex = a->X[0] - a->c[0], ey = a->X[1] - a->c[1], ez = a->X[2] - a->c[2];
             a->delta = sqrt(ex * ex + ey * ey + ez * ez);
         } else {
             for (int d = 0; d < 3; d++) a->X[d] = a->c[d];
             for (int q = 0; q < 6; q++) a->Q[q] = 0.0;
             a->delta = 0.0;
+            a->S = 0.0;
         }
     }
+}
+
+/* S of every node (see onode), by node id */
+void ot_get_trace(const otree *t, double *S) {
+    for (int n = 0; n < t->nnodes; n++) S[n] = t->nodes[n].S;
 }
 
 void ot_get_moments(const otree *t, double *M, double *X, double *Q, double *delta) {
@@ -866,57 +877,137 @@ void ot_direct_at(const otree *t, const double *p, const int64_t *exclude, int64
  * near r = 0, with D(0) the self term psi_0.  Sums run over |n_i| <= nreal and
  * 0 < |m_i| <= nrecip (each component).
  */
-static void ewald_at(double L, double a, int nreal, int nrecip, const double *r, double *D, double *g) {
-    const double sqpi = 1.7724538509055160273;
-    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    nsum s = {0.0, 0.0}, gx = {0.0, 0.0}, gy = {0.0, 0.0}, gz = {0.0, 0.0};
-    /* image n = 0 minus 1/r: -erf(a r)/r, a smooth even function */
-    if (a * rr < 1e-4) {
-        double x2 = a * a * rr * rr;
-        nadd(&s, -2.0 * a / sqpi * (1.0 - x2 / 3.0 + x2 * x2 / 10.0));
-        double c = 4.0 * a * a * a / (3.0 * sqpi) * (1.0 - 3.0 * x2 / 5.0);
-        nadd(&gx, c * r[0]); nadd(&gy, c * r[1]); nadd(&gz, c * r[2]);
-    } else {
-        nadd(&s, -erf(a * rr) / rr);
-        double f1 = erf(a * rr) / (rr * rr) - 2.0 * a / sqpi * exp(-a * a * rr * rr) / rr;  /* d/dr */
-        nadd(&gx, f1 * r[0] / rr); nadd(&gy, f1 * r[1] / rr); nadd(&gz, f1 * r[2] / rr);
+/* Adds the value, gradient and Hessian (order xx yy zz xy xz yz) of a radial
+ * function f(|p|) given f, f' and f'' at d = |p| > 0. */
+static void add_radial(const double *p, double d, double f, double f1, double f2, nsum *s, nsum *g, nsum *h) {
+    nadd(s, f);
+    for (int k = 0; k < 3; k++) nadd(&g[k], f1 * p[k] / d);
+    if (!h) return;
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int q = 0; q < 6; q++) {
+        double pp = p[ia[q]] * p[ib[q]] / (d * d);
+        nadd(&h[q], f2 * pp + f1 * ((ia[q] == ib[q] ? 1.0 : 0.0) - pp) / d);
     }
+}
+
+static void ewald_at(double L, double a, int nreal, int nrecip, const double *r, double *D, double *g, double *H) {
+    const double sqpi = 1.7724538509055160273;
+    const double c = 2.0 * a / sqpi;
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    nsum s = {0.0, 0.0}, gs[3], hs[6];
+    memset(gs, 0, sizeof(gs));
+    memset(hs, 0, sizeof(hs));
+    /* image n = 0 minus 1/r: g(r) = -erf(a r)/r, a smooth even function.
+     * Near 0 by its series, g = -c sum_k a_k u^k, u = (a r)^2,
+     * a_k = (-1)^k / (k! (2k + 1)), with grad g = G1 r and
+     * Hessian G1 I + G2 r r^T (G1 = g'/r, G2 = G1'/r); terms to u^7 leave
+     * below 1e-16 for a r < 0.1.  Elsewhere from erf directly. */
+    if (a * rr < 0.1) {
+        double u = a * a * rr * rr;
+        double gv = 0.0, g1 = 0.0, g2 = 0.0;
+        double ak = 1.0, uk = 1.0, uk1 = 1.0, uk2 = 1.0;  /* (-1)^k / k!, u^k, u^(k-1), u^(k-2) */
+        for (int k = 0; k <= 7; k++) {
+            if (k > 0) ak *= -1.0 / k;
+            double coef = ak / (2 * k + 1);
+            gv += coef * uk;
+            if (k >= 1) {
+                g1 += coef * 2.0 * k * a * a * uk1;
+                uk1 *= u;
+            }
+            if (k >= 2) {
+                g2 += coef * 2.0 * k * (2.0 * k - 2.0) * a * a * a * a * uk2;
+                uk2 *= u;
+            }
+            uk *= u;
+        }
+        nadd(&s, -c * gv);
+        for (int k = 0; k < 3; k++) nadd(&gs[k], -c * g1 * r[k]);
+        if (H) {
+            const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+            for (int q = 0; q < 6; q++)
+                nadd(&hs[q], -c * ((ia[q] == ib[q] ? g1 : 0.0) + g2 * r[ia[q]] * r[ib[q]]));
+        }
+    } else {
+        double E = exp(-a * a * rr * rr), ef = erf(a * rr);
+        double f = -ef / rr;
+        double f1 = ef / (rr * rr) - c * E / rr;
+        double f2 = 2.0 * c * a * a * E + 2.0 * c * E / (rr * rr) - 2.0 * ef / (rr * rr * rr);
+        add_radial(r, rr, f, f1, f2, &s, gs, H ? hs : NULL);
+    }
+    /* images n != 0; beyond a |r + nL| of 6.5, erfc is below 1e-19 and the
+     * image is left out */
     for (int i = -nreal; i <= nreal; i++)
         for (int j = -nreal; j <= nreal; j++)
             for (int k = -nreal; k <= nreal; k++) {
                 if (i == 0 && j == 0 && k == 0) continue;
                 double p[3] = {r[0] + i * L, r[1] + j * L, r[2] + k * L};
                 double d = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-                nadd(&s, erfc(a * d) / d);
-                double f1 = -erfc(a * d) / (d * d) - 2.0 * a / sqpi * exp(-a * a * d * d) / d;
-                nadd(&gx, f1 * p[0] / d); nadd(&gy, f1 * p[1] / d); nadd(&gz, f1 * p[2] / d);
+                if (a * d > 6.5) continue;
+                double E = exp(-a * a * d * d), ec = erfc(a * d);
+                double f1 = -ec / (d * d) - c * E / d;
+                double f2 = 2.0 * c * a * a * E + 2.0 * c * E / (d * d) + 2.0 * ec / (d * d * d);
+                add_radial(p, d, ec / d, f1, f2, &s, gs, H ? hs : NULL);
             }
+    /* wave vectors m != 0: the weight exp(-pi^2 |m|^2 / (aL)^2) and the phase
+     * exp(2 pi i m.r / L) both factor over the axes, so each term is a
+     * product of per-axis tables */
     const double pi = 3.14159265358979323846;
+    const double kk = 2.0 * pi / L;
+    enum { NM = 16 };
+    double ew[2 * NM + 1], cph[3][2 * NM + 1], sph[3][2 * NM + 1];
+    if (nrecip > NM) nrecip = NM;
+    for (int i = -nrecip; i <= nrecip; i++) {
+        ew[i + NM] = exp(-pi * pi * (double)(i * i) / (a * a * L * L));
+        for (int d = 0; d < 3; d++) {
+            cph[d][i + NM] = cos(kk * i * r[d]);
+            sph[d][i + NM] = sin(kk * i * r[d]);
+        }
+    }
     for (int i = -nrecip; i <= nrecip; i++)
-        for (int j = -nrecip; j <= nrecip; j++)
+        for (int j = -nrecip; j <= nrecip; j++) {
+            /* phase of the x and y factors: (cx + i sx)(cy + i sy) */
+            double cxy = cph[0][i + NM] * cph[1][j + NM] - sph[0][i + NM] * sph[1][j + NM];
+            double sxy = sph[0][i + NM] * cph[1][j + NM] + cph[0][i + NM] * sph[1][j + NM];
             for (int k = -nrecip; k <= nrecip; k++) {
                 if (i == 0 && j == 0 && k == 0) continue;
                 double m2 = (double)(i * i + j * j + k * k);
-                double w = exp(-pi * pi * m2 / (a * a * L * L)) / (pi * L * m2);
-                double ph = 2.0 * pi * (i * r[0] + j * r[1] + k * r[2]) / L;
-                nadd(&s, w * cos(ph));
-                double gs = -w * sin(ph) * 2.0 * pi / L;
-                nadd(&gx, gs * i); nadd(&gy, gs * j); nadd(&gz, gs * k);
+                double w = ew[i + NM] * ew[j + NM] * ew[k + NM] / (pi * L * m2);
+                double cs = cxy * cph[2][k + NM] - sxy * sph[2][k + NM];
+                double sn = sxy * cph[2][k + NM] + cxy * sph[2][k + NM];
+                nadd(&s, w * cs);
+                double m[3] = {(double)i, (double)j, (double)k};
+                for (int q = 0; q < 3; q++) nadd(&gs[q], -w * sn * kk * m[q]);
+                if (H) {
+                    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+                    for (int q = 0; q < 6; q++) nadd(&hs[q], -w * cs * kk * kk * m[ia[q]] * m[ib[q]]);
+                }
             }
+        }
     nadd(&s, -pi / (a * a * L * L * L));
     *D = nval(&s);
-    g[0] = nval(&gx); g[1] = nval(&gy); g[2] = nval(&gz);
+    for (int q = 0; q < 3; q++) g[q] = nval(&gs[q]);
+    if (H)
+        for (int q = 0; q < 6; q++) H[q] = nval(&hs[q]);
 }
 
 /* D and grad D at n points r[n][3] (any r: the sums are periodic). */
 void ot_ewald(double L, double alpha, int nreal, int nrecip, const double *r, int64_t n, double *D, double *grad) {
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t q = 0; q < n; q++) ewald_at(L, alpha, nreal, nrecip, r + 3 * q, D + q, grad + 3 * q);
+    for (int64_t q = 0; q < n; q++) ewald_at(L, alpha, nreal, nrecip, r + 3 * q, D + q, grad + 3 * q, NULL);
 }
 
+/* D, grad D and the Hessian H[n][6] (xx yy zz xy xz yz) at n points. */
+void ot_ewald_hessian(double L, double alpha, int nreal, int nrecip, const double *r, int64_t n, double *D,
+                      double *grad, double *H) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n; q++) ewald_at(L, alpha, nreal, nrecip, r + 3 * q, D + q, grad + 3 * q, H + 6 * q);
+}
+
+/* splitting constant a = 2 / L: images beyond 3 boxes and wave vectors with a
+ * component beyond 4 add less than 1e-17 relative */
 #define EW_ALPHA 2.0
-#define EW_NREAL 4
-#define EW_NRECIP 5
+#define EW_NREAL 3
+#define EW_NRECIP 4
 
 /* Exact periodic direct sum at selected cells:
  *   phi_i = -G [ sum_{j != i} m_j psi(r_i - r_j) + m_i psi_0 ],
@@ -924,7 +1015,7 @@ void ot_ewald(double L, double alpha, int nreal, int nrecip, const double *r, in
 void ot_direct_periodic(const otree *t, const int64_t *targets, int64_t ntargets, double Gc, double *phi) {
     const double L = t->box;
     double D0, g0[3], zero[3] = {0.0, 0.0, 0.0};
-    ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, zero, &D0, g0);
+    ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, zero, &D0, g0, NULL);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < ntargets; q++) {
         int64_t i = targets[q];
@@ -935,9 +1026,205 @@ void ot_direct_periodic(const otree *t, const int64_t *targets, int64_t ntargets
             double r[3] = {t->cx[i] - t->cx[j], t->cy[i] - t->cy[j], t->cz[i] - t->cz[j]};
             for (int d = 0; d < 3; d++) r[d] -= L * nearbyint(r[d] / L);
             double D, gr[3];
-            ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, r, &D, gr);
+            ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, r, &D, gr, NULL);
             nadd(&acc, t->cm[j] * (1.0 / sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) + D));
         }
         phi[q] = -Gc * nval(&acc);
     }
+}
+
+/*
+ * O10 periodic Barnes-Hut: O5-O7 in a box of side L repeated in every
+ * direction (appendix "Periodic boundaries": every node or cell contributes
+ * through the periodic Green's function psi = 1/|r| + D(r) of O9; read here
+ * with this method's group walk and quadrupoles).
+ *  - Images: for group g, with c_g the centre of its cells' cube and e_g half
+ *    the span of their centres, a point x is taken at its image
+ *    x' = x - L rint((x - c_g) / L), per axis.
+ *  - MAC: node n (image X') is accepted iff every cell of g has
+ *    |r_i - X'|^2 > s^2 (O5) and n is contained: on every axis
+ *    |X'_a - c_g,a| + delta + l/2 + e_g < L/2, so that all of the node's
+ *    mass lies in the nearest-image cube of every cell of the group (the
+ *    expansion below is about one image).  A rejected bottom node goes to the
+ *    near list, any other rejected node is opened.
+ *  - Far node, R = r_i - X':
+ *      M (1/|R| + D(R)) + R^T Q R / (2 |R|^5) + Q:H(R) / 6 + (2 pi / (3 L^3)) S,
+ *    the second-order expansion of sum_j m_j psi(r_i - x_j) about X': the
+ *    quadrupole meets the Hessian H of 1/|r| and of D, and the trace of the
+ *    second moments (S) meets the Laplacian 4 pi / L^3 of D.
+ *  - Near node n, its cells at their images x'_j: the periodic Green's
+ *    function cell by cell,
+ *      sum_{j != i} m_j / |r_i - x'_j| + sum_j m_j D(r_i - x'_j),
+ *    the cell itself included in the second sum (D(0) = psi_0, its images).
+ *  - phi_i = -G (far + near), compensated sums.
+ * Marginal: a test within tau of its threshold (the MAC as in O5; the
+ * containment within tau L).
+ */
+typedef struct {
+    const otree *t;
+    const int64_t *cells;
+    int G;
+    double inv_theta, tau, L, cg[3], eg;
+    ivec *far, *near;
+    int64_t visited, marginal;
+} pwalkctx;
+
+static void image_of(const double *x, const double *cg, double L, double *out) {
+    for (int d = 0; d < 3; d++) out[d] = x[d] - L * nearbyint((x[d] - cg[d]) / L);
+}
+
+/* containment of node a (image Xp) for a group; *tie set when within tau L */
+static int contained(const onode *a, const double *Xp, const double *cg, double eg, double L, double tau, int *tie) {
+    int in = 1;
+    for (int d = 0; d < 3; d++) {
+        double v = fabs(Xp[d] - cg[d]) + a->delta + 0.5 * a->l + eg;
+        if (!(v < 0.5 * L)) in = 0;
+        if (tie && fabs(v - 0.5 * L) <= tau * L) *tie = 1;
+    }
+    return in;
+}
+
+static void pwalk_node(pwalkctx *w, int n) {
+    const otree *t = w->t;
+    const onode *a = &t->nodes[n];
+    if (a->M == 0.0) return;
+    w->visited++;
+    double Xp[3];
+    image_of(a->X, w->cg, w->L, Xp);
+    double s = a->l * w->inv_theta + a->delta;
+    double s2 = s * s;
+    int accept = 1, tie = 0;
+    double dmin2 = INFINITY;
+    for (int q = 0; q < w->G; q++) {
+        int64_t c = w->cells[q];
+        double dx = t->cx[c] - Xp[0], dy = t->cy[c] - Xp[1], dz = t->cz[c] - Xp[2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 > s2)) accept = 0;
+        if (d2 < dmin2) dmin2 = d2;
+    }
+    if (fabs(dmin2 - s2) <= w->tau * s2) tie = 1;
+    if (!contained(a, Xp, w->cg, w->eg, w->L, w->tau, &tie)) accept = 0;
+    if (tie) w->marginal++;
+    if (accept) {
+        ivec_push(w->far, n);
+    } else if (a->bottom) {
+        ivec_push(w->near, n);
+    } else {
+        for (int o = 0; o < 8; o++) pwalk_node(w, a->child[o]);
+    }
+}
+
+static void group_centre(const otree *t, const int64_t *cells, int G, double *cg, double *eg) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int q = 0; q < G; q++) {
+        double p[3] = {t->cx[cells[q]], t->cy[cells[q]], t->cz[cells[q]]};
+        for (int d = 0; d < 3; d++) {
+            if (p[d] < lo[d]) lo[d] = p[d];
+            if (p[d] > hi[d]) hi[d] = p[d];
+        }
+    }
+    for (int d = 0; d < 3; d++) cg[d] = 0.5 * (lo[d] + hi[d]);
+    *eg = 0.5 * (hi[0] - lo[0]);
+}
+
+/* the smooth part of node a at R: M D(R) + Q:H(R)/6 + (2 pi/(3 L^3)) S */
+static double smooth_node(const onode *a, const double *R, double L) {
+    double D, g[3], H[6];
+    ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, R, &D, g, H);
+    double qh = a->Q[0] * H[0] + a->Q[1] * H[1] + a->Q[2] * H[2] + 2.0 * (a->Q[3] * H[3] + a->Q[4] * H[4] + a->Q[5] * H[5]);
+    const double pi = 3.14159265358979323846;
+    return a->M * D + qh / 6.0 + 2.0 * pi / (3.0 * L * L * L) * a->S;
+}
+
+static void psum_group(const otree *t, const int64_t *cells, int G, const double *cg, const ivec *far,
+                       const ivec *near, double Gc, double *phi) {
+    const double L = t->box;
+    for (int q = 0; q < G; q++) {
+        int64_t i = cells[q];
+        double ri[3] = {t->cx[i], t->cy[i], t->cz[i]};
+        nsum acc = {0.0, 0.0};
+        for (int f = 0; f < far->n; f++) {
+            const onode *a = &t->nodes[far->v[f]];
+            double Xp[3], R[3];
+            image_of(a->X, cg, L, Xp);
+            for (int d = 0; d < 3; d++) R[d] = ri[d] - Xp[d];
+            double d2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+            double dd = sqrt(d2);
+            double rqr = a->Q[0] * R[0] * R[0] + a->Q[1] * R[1] * R[1] + a->Q[2] * R[2] * R[2]
+                         + 2.0 * (a->Q[3] * R[0] * R[1] + a->Q[4] * R[0] * R[2] + a->Q[5] * R[1] * R[2]);
+            nadd(&acc, a->M / dd);
+            nadd(&acc, rqr / (2.0 * d2 * d2 * dd));
+            nadd(&acc, smooth_node(a, R, L));
+        }
+        for (int b = 0; b < near->n; b++) {
+            const onode *a = &t->nodes[near->v[b]];
+            for (int o = 0; o < 8; o++) {
+                int64_t j = a->cell[o];
+                if (t->cm[j] == 0.0) continue;
+                double xj[3] = {t->cx[j], t->cy[j], t->cz[j]}, xp[3], R[3];
+                image_of(xj, cg, L, xp);
+                for (int d = 0; d < 3; d++) R[d] = ri[d] - xp[d];
+                if (j != i) nadd(&acc, t->cm[j] / sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]));
+                double D, g[3];
+                ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, R, &D, g, NULL);
+                nadd(&acc, t->cm[j] * D);
+            }
+        }
+        phi[q] = -Gc * nval(&acc);
+    }
+}
+
+/* O10 for selected canonical groups: phi[q * G + c] for the group's c-th cell
+ * in Morton order, counts[4 q + ...] = visited, far, near, marginal. */
+void ot_solve_groups_periodic(const otree *t, int group_cells, const double *theta_group, const int64_t *groups,
+                              int64_t n, double tau, double Gc, int64_t *counts, double *phi) {
+    int G = group_cells;
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)G);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < n; q++) {
+            int64_t g = groups[q];
+            group_cells_of(t, g, G, cells);
+            ivec far = {0, 0, NULL}, near = {0, 0, NULL};
+            pwalkctx w;
+            w.t = t; w.cells = cells; w.G = G;
+            w.inv_theta = 1.0 / theta_group[g];
+            w.tau = tau;
+            w.L = t->box;
+            group_centre(t, cells, G, w.cg, &w.eg);
+            w.far = &far; w.near = &near;
+            w.visited = 0; w.marginal = 0;
+            pwalk_node(&w, t->root);
+            counts[4 * q + 0] = w.visited;
+            counts[4 * q + 1] = far.n;
+            counts[4 * q + 2] = near.n;
+            counts[4 * q + 3] = w.marginal;
+            psum_group(t, cells, G, w.cg, &far, &near, Gc, phi + q * G);
+            free(far.v);
+            free(near.v);
+        }
+        free(cells);
+    }
+}
+
+/* O10 far term of node n at point p (image nearest to p), by part:
+ * out = [M (1/|R| + D(R)), R^T Q R / (2 |R|^5), Q:H(R) / 6, 2 pi S / (3 L^3)]. */
+void ot_node_far_periodic(const otree *t, int n, const double *p, double *out) {
+    const onode *a = &t->nodes[n];
+    const double L = t->box;
+    double Xp[3], R[3];
+    image_of(a->X, p, L, Xp);
+    for (int d = 0; d < 3; d++) R[d] = p[d] - Xp[d];
+    double d2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2], dd = sqrt(d2);
+    double D, g[3], H[6];
+    ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, R, &D, g, H);
+    double rqr = a->Q[0] * R[0] * R[0] + a->Q[1] * R[1] * R[1] + a->Q[2] * R[2] * R[2]
+                 + 2.0 * (a->Q[3] * R[0] * R[1] + a->Q[4] * R[0] * R[2] + a->Q[5] * R[1] * R[2]);
+    double qh = a->Q[0] * H[0] + a->Q[1] * H[1] + a->Q[2] * H[2] + 2.0 * (a->Q[3] * H[3] + a->Q[4] * H[4] + a->Q[5] * H[5]);
+    const double pi = 3.14159265358979323846;
+    out[0] = a->M * (1.0 / dd + D);
+    out[1] = rqr / (2.0 * d2 * d2 * dd);
+    out[2] = qh / 6.0;
+    out[3] = 2.0 * pi / (3.0 * L * L * L) * a->S;
 }

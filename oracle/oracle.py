@@ -2,7 +2,8 @@
 
 Test infrastructure only: nothing in the product package imports this module.
 Each method names the definition it follows (see the header of bh_oracle.c):
-O1 cells, O2 direct sum, O3 node moments, O4-O6 group walk, O7 potential sum.
+O1 cells, O2 direct sum, O3 node moments, O4-O6 group walk, O7 potential sum,
+O8 accelerations, O9 the periodic Green's function, O10 the periodic walk and sum.
 """
 from __future__ import annotations
 
@@ -86,6 +87,11 @@ def _load():
         lib.ot_direct_at.argtypes = [P, P, P, i64, ctypes.c_double, P]
         lib.ot_ewald.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, i64, P, P]
         lib.ot_direct_periodic.argtypes = [P, P, i64, ctypes.c_double, P]
+        lib.ot_get_trace.argtypes = [P, P]
+        lib.ot_ewald_hessian.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, i64, P, P,
+                                         P]
+        lib.ot_solve_groups_periodic.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double, P, P]
+        lib.ot_node_far_periodic.argtypes = [P, ctypes.c_int, P, P]
         _lib = lib
         return lib
 
@@ -175,8 +181,10 @@ class OracleTree:
         Q = np.empty((n, 6))
         d = np.empty(n)
         self.lib.ot_get_moments(self.h, _p(M), _p(X), _p(Q), _p(d))
+        S = np.empty(n)
+        self.lib.ot_get_trace(self.h, _p(S))
         info = self.node_info()
-        info.update(M=M, X=X, Q=Q, delta=d)
+        info.update(M=M, X=X, Q=Q, delta=d, S=S)
         return info
 
     # -- O4-O6 -----------------------------------------------------------------
@@ -260,6 +268,31 @@ class OracleTree:
         self.lib.ot_direct_periodic(self.h, _p(t), int(t.size), float(G), _p(phi))
         return phi
 
+    # -- O10 ---------------------------------------------------------------------
+    def solve_groups_periodic(self, groups, group_cells=64, theta=0.5, tau=0.0, G=1.0):
+        """O10 (periodic walk and sum) for selected canonical groups.  Returns
+        (phi[n, G] in the group's Morton order, counts[n, 4] = visited, far, near, marginal)."""
+        if not self._moments_done:
+            self.moments()
+        ng = self.n_groups(group_cells)
+        th = np.broadcast_to(np.asarray(theta, np.float64), (ng,)).copy()
+        gs = np.ascontiguousarray(groups, np.int64)
+        phi = np.empty((gs.size, group_cells))
+        counts = np.empty((gs.size, 4), np.int64)
+        self.lib.ot_solve_groups_periodic(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau),
+                                          float(G), _p(counts), _p(phi))
+        return phi, counts
+
+    def node_far_periodic(self, node, point):
+        """O10 far term of node id ``node`` at ``point`` by part: M (1/|R| + D), R^T Q R / (2 |R|^5),
+        Q:H / 6, 2 pi S / (3 L^3)."""
+        if not self._moments_done:
+            self.moments()
+        p = np.ascontiguousarray(point, np.float64).reshape(3)
+        out = np.empty(4)
+        self.lib.ot_node_far_periodic(self.h, int(node), _p(p), _p(out))
+        return out
+
     # -- O8 ----------------------------------------------------------------------
     def accel(self, G=1.0, order=2):
         """O8 with the lists of the last walk; returns g[nleaf, 8, 8, 8, 3]."""
@@ -322,3 +355,15 @@ def ewald(points, L=1.0, alpha=None, nreal=4, nrecip=5):
     a = 2.0 / L if alpha is None else float(alpha)
     lib.ot_ewald(float(L), a, int(nreal), int(nrecip), _p(p), int(p.shape[0]), _p(D), _p(g))
     return D, g
+
+
+def ewald_hessian(points, L=1.0, alpha=None, nreal=4, nrecip=5):
+    """O9 with second derivatives: (D[n], grad[n, 3], H[n, 6] in the order xx yy zz xy xz yz)."""
+    lib = _load()
+    p = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+    D = np.empty(p.shape[0])
+    g = np.empty((p.shape[0], 3))
+    H = np.empty((p.shape[0], 6))
+    a = 2.0 / L if alpha is None else float(alpha)
+    lib.ot_ewald_hessian(float(L), a, int(nreal), int(nrecip), _p(p), int(p.shape[0]), _p(D), _p(g), _p(H))
+    return D, g, H
