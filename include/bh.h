@@ -63,6 +63,7 @@ typedef struct bh_moments bh_moments;
 typedef struct bh_lists bh_lists;
 typedef struct bh_mlp bh_mlp;
 typedef struct bh_batch bh_batch;
+typedef struct bh_ewald bh_ewald;
 
 /* ---------------------------------------------------------------- context */
 
@@ -249,6 +250,58 @@ int bh_direct(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const int64
  * Arguments and errors as bh_direct. */
 int bh_direct_accel(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const int64_t *targets_dev,
                     int64_t n_targets, double G, double *acc_dev);
+
+/* ---------------------------------------------------------------- periodic boxes
+ *
+ * Appendix "Periodic boundaries": in a box of side L repeated in every
+ * direction, every contribution goes through the periodic Green's function
+ * psi(r) = 1/|r| + D(r) (Ewald's split into short- and long-range sums, the
+ * mean density removed).  This library tabulates the smooth part D on the
+ * octant [0, L/2]^3 with its derivatives to third order and evaluates it by a
+ * third-order Taylor expansion about the nearest table point (in place of the
+ * paper's nested grids with quadratic interpolation of the whole field: the
+ * singular 1/|r| is exact here, so one uniform grid suffices).
+ *
+ * The periodic walk and sum: every pair is taken at its nearest image, R
+ * the nearest image of r_i - X.  A node is accepted iff the opening test of
+ * bh_walk passes at every cell of the group with that distance; a far node
+ * adds
+ *   M (1/|R| + D(R)) + R^T Q R / (2 |R|^5) + Q:H(R) / 6 + 2 pi S / (3 L^3)
+ * (H the Hessian of D, S = sum m |r - X|^2: the expansion of its cells'
+ * periodic potentials to second order), a near cell m (1/|R| + D(R)),
+ * the cell itself m D(0).  phi_i = -G (sum). */
+
+/* Upper bound of n_points for bh_ewald_create. */
+#define BH_EWALD_MAX_POINTS 129
+
+/* Build the table for box side box_size on n_points^3 points (spacing
+ * box_size / (2 (n_points - 1))) on the context's device and stream
+ * (asynchronous; fp64 and fp32 copies, 160 + 80 bytes per point).  Errors:
+ * BH_EINVAL (box_size <= 0 or not finite, n_points outside
+ * [3, BH_EWALD_MAX_POINTS]), BH_ENOMEM, BH_EDEVICE. */
+int bh_ewald_create(bh_ctx *ctx, double box_size, int n_points, bh_ewald **table);
+int bh_ewald_destroy(bh_ewald *table);
+/* Synchronising host copy of the fp64 table, values[n^3][20] indexed
+ * ((k n + j) n + i) for the point (i, j, k) spacing: D; D_x D_y D_z;
+ * D_xx D_yy D_zz D_xy D_xz D_yz; D_xxx D_yyy D_zzz D_xxy D_xxz D_xyy D_yyz
+ * D_xzz D_yzz D_xyz. */
+int bh_ewald_export(bh_ctx *ctx, const bh_ewald *table, double *values);
+/* Synchronising host copy of S = sum m |r - X|^2 of every node (by node id),
+ * as built by the last bh_build_moments. */
+int bh_moments_export_trace(bh_ctx *ctx, const bh_moments *m, double *S);
+/* The periodic walk and sum (above) in one launch; arguments as
+ * bh_walk_potential.  The grid's box must be the table's (to 1e-12).  The
+ * fused walks' dispatch order and cost records apply as for
+ * bh_walk_potential.  Errors: BH_EINVAL (theta, precision, G, box size),
+ * BH_ESTATE, BH_EDEVICE; stack overflow as bh_walk_potential. */
+int bh_walk_potential_periodic(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_ewald *table,
+                               double theta, const float *theta_group_dev, int precision, double G, double *phi_dev,
+                               int32_t *counts_dev);
+/* Periodic direct sum at canonical cell ids targets_dev[n] (fp64):
+ * phi_dev[n] = -G [sum_{j != i} m_j / |R_ij| + sum_j m_j D(R_ij)], R_ij the
+ * nearest image of r_i - r_j, D from the table.  Errors as bh_direct. */
+int bh_direct_periodic(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_ewald *table,
+                       const int64_t *targets_dev, int64_t n_targets, double G, double *phi_dev);
 
 /* ---------------------------------------------------------------- batches
  *

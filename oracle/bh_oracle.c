@@ -1037,51 +1037,42 @@ void ot_direct_periodic(const otree *t, const int64_t *targets, int64_t ntargets
  * O10 periodic Barnes-Hut: O5-O7 in a box of side L repeated in every
  * direction (appendix "Periodic boundaries": every node or cell contributes
  * through the periodic Green's function psi = 1/|r| + D(r) of O9; read here
- * with this method's group walk and quadrupoles).
- *  - Images: for group g, with c_g the centre of its cells' cube and e_g half
- *    the span of their centres, a point x is taken at its image
- *    x' = x - L rint((x - c_g) / L), per axis.
- *  - MAC: node n (image X') is accepted iff every cell of g has
- *    |r_i - X'|^2 > s^2 (O5) and n is contained: on every axis
- *    |X'_a - c_g,a| + delta + l/2 + e_g < L/2, so that all of the node's
- *    mass lies in the nearest-image cube of every cell of the group (the
- *    expansion below is about one image).  A rejected bottom node goes to the
- *    near list, any other rejected node is opened.
- *  - Far node, R = r_i - X':
+ * with this method's group walk and quadrupoles).  Every pair (cell, node)
+ * and (cell, cell) is taken at its nearest image: R = r_i - X reduced per
+ * axis by L rint(R_a / L).
+ *  - MAC: node n is accepted iff every cell of g has |R|^2 > s^2 (O5 with the
+ *    nearest-image distance).  All other images are then farther, and so is
+ *    every singularity of psi seen from R, so the expansion below converges
+ *    as the isolated one does.  A rejected bottom node goes to the near list,
+ *    any other rejected node is opened.
+ *  - Far node:
  *      M (1/|R| + D(R)) + R^T Q R / (2 |R|^5) + Q:H(R) / 6 + (2 pi / (3 L^3)) S,
- *    the second-order expansion of sum_j m_j psi(r_i - x_j) about X': the
- *    quadrupole meets the Hessian H of 1/|r| and of D, and the trace of the
- *    second moments (S) meets the Laplacian 4 pi / L^3 of D.
- *  - Near node n, its cells at their images x'_j: the periodic Green's
- *    function cell by cell,
- *      sum_{j != i} m_j / |r_i - x'_j| + sum_j m_j D(r_i - x'_j),
+ *    the expansion of sum_j m_j psi(r_i - x_j) about X to second order: the
+ *    quadrupole meets the Hessians of 1/|r| and of D (H), the trace of the
+ *    second moments (S) the Laplacian 4 pi / L^3 of D.  Near the half-box
+ *    planes D holds the neighbouring image's 1/|r|, and its Hessian term is
+ *    of the same order as the quadrupole term of 1/|r|.
+ *  - Near node n: the periodic Green's function cell by cell,
+ *      sum_{j != i} m_j / |R_ij| + sum_j m_j D(R_ij),
  *    the cell itself included in the second sum (D(0) = psi_0, its images).
  *  - phi_i = -G (far + near), compensated sums.
- * Marginal: a test within tau of its threshold (the MAC as in O5; the
- * containment within tau L).
+ * Marginal: an opening test within tau of its threshold, as in O5.
  */
 typedef struct {
     const otree *t;
     const int64_t *cells;
     int G;
-    double inv_theta, tau, L, cg[3], eg;
+    double inv_theta, tau, L;
     ivec *far, *near;
     int64_t visited, marginal;
 } pwalkctx;
 
-static void image_of(const double *x, const double *cg, double L, double *out) {
-    for (int d = 0; d < 3; d++) out[d] = x[d] - L * nearbyint((x[d] - cg[d]) / L);
-}
-
-/* containment of node a (image Xp) for a group; *tie set when within tau L */
-static int contained(const onode *a, const double *Xp, const double *cg, double eg, double L, double tau, int *tie) {
-    int in = 1;
+/* nearest image of the vector a - b */
+static void nearest_image(const double *a, const double *b, double L, double *R) {
     for (int d = 0; d < 3; d++) {
-        double v = fabs(Xp[d] - cg[d]) + a->delta + 0.5 * a->l + eg;
-        if (!(v < 0.5 * L)) in = 0;
-        if (tie && fabs(v - 0.5 * L) <= tau * L) *tie = 1;
+        R[d] = a[d] - b[d];
+        R[d] -= L * nearbyint(R[d] / L);
     }
-    return in;
 }
 
 static void pwalk_node(pwalkctx *w, int n) {
@@ -1089,22 +1080,19 @@ static void pwalk_node(pwalkctx *w, int n) {
     const onode *a = &t->nodes[n];
     if (a->M == 0.0) return;
     w->visited++;
-    double Xp[3];
-    image_of(a->X, w->cg, w->L, Xp);
     double s = a->l * w->inv_theta + a->delta;
     double s2 = s * s;
-    int accept = 1, tie = 0;
+    int accept = 1;
     double dmin2 = INFINITY;
     for (int q = 0; q < w->G; q++) {
         int64_t c = w->cells[q];
-        double dx = t->cx[c] - Xp[0], dy = t->cy[c] - Xp[1], dz = t->cz[c] - Xp[2];
-        double d2 = dx * dx + dy * dy + dz * dz;
+        double r[3] = {t->cx[c], t->cy[c], t->cz[c]}, R[3];
+        nearest_image(r, a->X, w->L, R);
+        double d2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
         if (!(d2 > s2)) accept = 0;
         if (d2 < dmin2) dmin2 = d2;
     }
-    if (fabs(dmin2 - s2) <= w->tau * s2) tie = 1;
-    if (!contained(a, Xp, w->cg, w->eg, w->L, w->tau, &tie)) accept = 0;
-    if (tie) w->marginal++;
+    if (fabs(dmin2 - s2) <= w->tau * s2) w->marginal++;
     if (accept) {
         ivec_push(w->far, n);
     } else if (a->bottom) {
@@ -1112,19 +1100,6 @@ static void pwalk_node(pwalkctx *w, int n) {
     } else {
         for (int o = 0; o < 8; o++) pwalk_node(w, a->child[o]);
     }
-}
-
-static void group_centre(const otree *t, const int64_t *cells, int G, double *cg, double *eg) {
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int q = 0; q < G; q++) {
-        double p[3] = {t->cx[cells[q]], t->cy[cells[q]], t->cz[cells[q]]};
-        for (int d = 0; d < 3; d++) {
-            if (p[d] < lo[d]) lo[d] = p[d];
-            if (p[d] > hi[d]) hi[d] = p[d];
-        }
-    }
-    for (int d = 0; d < 3; d++) cg[d] = 0.5 * (lo[d] + hi[d]);
-    *eg = 0.5 * (hi[0] - lo[0]);
 }
 
 /* the smooth part of node a at R: M D(R) + Q:H(R)/6 + (2 pi/(3 L^3)) S */
@@ -1136,8 +1111,8 @@ static double smooth_node(const onode *a, const double *R, double L) {
     return a->M * D + qh / 6.0 + 2.0 * pi / (3.0 * L * L * L) * a->S;
 }
 
-static void psum_group(const otree *t, const int64_t *cells, int G, const double *cg, const ivec *far,
-                       const ivec *near, double Gc, double *phi) {
+static void psum_group(const otree *t, const int64_t *cells, int G, const ivec *far, const ivec *near, double Gc,
+                       double *phi) {
     const double L = t->box;
     for (int q = 0; q < G; q++) {
         int64_t i = cells[q];
@@ -1145,9 +1120,8 @@ static void psum_group(const otree *t, const int64_t *cells, int G, const double
         nsum acc = {0.0, 0.0};
         for (int f = 0; f < far->n; f++) {
             const onode *a = &t->nodes[far->v[f]];
-            double Xp[3], R[3];
-            image_of(a->X, cg, L, Xp);
-            for (int d = 0; d < 3; d++) R[d] = ri[d] - Xp[d];
+            double R[3];
+            nearest_image(ri, a->X, L, R);
             double d2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
             double dd = sqrt(d2);
             double rqr = a->Q[0] * R[0] * R[0] + a->Q[1] * R[1] * R[1] + a->Q[2] * R[2] * R[2]
@@ -1161,9 +1135,8 @@ static void psum_group(const otree *t, const int64_t *cells, int G, const double
             for (int o = 0; o < 8; o++) {
                 int64_t j = a->cell[o];
                 if (t->cm[j] == 0.0) continue;
-                double xj[3] = {t->cx[j], t->cy[j], t->cz[j]}, xp[3], R[3];
-                image_of(xj, cg, L, xp);
-                for (int d = 0; d < 3; d++) R[d] = ri[d] - xp[d];
+                double xj[3] = {t->cx[j], t->cy[j], t->cz[j]}, R[3];
+                nearest_image(ri, xj, L, R);
                 if (j != i) nadd(&acc, t->cm[j] / sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]));
                 double D, g[3];
                 ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, R, &D, g, NULL);
@@ -1175,9 +1148,12 @@ static void psum_group(const otree *t, const int64_t *cells, int G, const double
 }
 
 /* O10 for selected canonical groups: phi[q * G + c] for the group's c-th cell
- * in Morton order, counts[4 q + ...] = visited, far, near, marginal. */
+ * in Morton order, counts[4 q + ...] = visited, far, near, marginal, and
+ * (if qsum is not NULL) qsum[q] = sum over the group's far nodes of
+ * sum_ab |Q_ab| / 6 (the weight of the Hessian in the far terms, for error
+ * bounds). */
 void ot_solve_groups_periodic(const otree *t, int group_cells, const double *theta_group, const int64_t *groups,
-                              int64_t n, double tau, double Gc, int64_t *counts, double *phi) {
+                              int64_t n, double tau, double Gc, int64_t *counts, double *phi, double *qsum) {
     int G = group_cells;
 #pragma omp parallel
     {
@@ -1192,7 +1168,6 @@ void ot_solve_groups_periodic(const otree *t, int group_cells, const double *the
             w.inv_theta = 1.0 / theta_group[g];
             w.tau = tau;
             w.L = t->box;
-            group_centre(t, cells, G, w.cg, &w.eg);
             w.far = &far; w.near = &near;
             w.visited = 0; w.marginal = 0;
             pwalk_node(&w, t->root);
@@ -1200,7 +1175,15 @@ void ot_solve_groups_periodic(const otree *t, int group_cells, const double *the
             counts[4 * q + 1] = far.n;
             counts[4 * q + 2] = near.n;
             counts[4 * q + 3] = w.marginal;
-            psum_group(t, cells, G, w.cg, &far, &near, Gc, phi + q * G);
+            psum_group(t, cells, G, &far, &near, Gc, phi + q * G);
+            if (qsum) {
+                double w = 0.0;
+                for (int f = 0; f < far.n; f++) {
+                    const double *Q = t->nodes[far.v[f]].Q;
+                    w += (fabs(Q[0]) + fabs(Q[1]) + fabs(Q[2]) + 2.0 * (fabs(Q[3]) + fabs(Q[4]) + fabs(Q[5]))) / 6.0;
+                }
+                qsum[q] = w;
+            }
             free(far.v);
             free(near.v);
         }
@@ -1213,9 +1196,8 @@ void ot_solve_groups_periodic(const otree *t, int group_cells, const double *the
 void ot_node_far_periodic(const otree *t, int n, const double *p, double *out) {
     const onode *a = &t->nodes[n];
     const double L = t->box;
-    double Xp[3], R[3];
-    image_of(a->X, p, L, Xp);
-    for (int d = 0; d < 3; d++) R[d] = p[d] - Xp[d];
+    double R[3];
+    nearest_image(p, a->X, L, R);
     double d2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2], dd = sqrt(d2);
     double D, g[3], H[6];
     ewald_at(L, EW_ALPHA / L, EW_NREAL, EW_NRECIP, R, &D, g, H);

@@ -90,7 +90,8 @@ def _load():
         lib.ot_get_trace.argtypes = [P, P]
         lib.ot_ewald_hessian.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, i64, P, P,
                                          P]
-        lib.ot_solve_groups_periodic.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double, P, P]
+        lib.ot_solve_groups_periodic.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double, P, P,
+                                                 P]
         lib.ot_node_far_periodic.argtypes = [P, ctypes.c_int, P, P]
         _lib = lib
         return lib
@@ -269,9 +270,10 @@ class OracleTree:
         return phi
 
     # -- O10 ---------------------------------------------------------------------
-    def solve_groups_periodic(self, groups, group_cells=64, theta=0.5, tau=0.0, G=1.0):
+    def solve_groups_periodic(self, groups, group_cells=64, theta=0.5, tau=0.0, G=1.0, with_qsum=False):
         """O10 (periodic walk and sum) for selected canonical groups.  Returns
-        (phi[n, G] in the group's Morton order, counts[n, 4] = visited, far, near, marginal)."""
+        (phi[n, G] in the group's Morton order, counts[n, 4] = visited, far, near, marginal), and with
+        ``with_qsum`` also qsum[n] = sum over far nodes of sum_ab |Q_ab| / 6."""
         if not self._moments_done:
             self.moments()
         ng = self.n_groups(group_cells)
@@ -279,9 +281,10 @@ class OracleTree:
         gs = np.ascontiguousarray(groups, np.int64)
         phi = np.empty((gs.size, group_cells))
         counts = np.empty((gs.size, 4), np.int64)
+        qsum = np.empty(gs.size)
         self.lib.ot_solve_groups_periodic(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau),
-                                          float(G), _p(counts), _p(phi))
-        return phi, counts
+                                          float(G), _p(counts), _p(phi), _p(qsum))
+        return (phi, counts, qsum) if with_qsum else (phi, counts)
 
     def node_far_periodic(self, node, point):
         """O10 far term of node id ``node`` at ``point`` by part: M (1/|R| + D), R^T Q R / (2 |R|^5),

@@ -72,6 +72,12 @@ _SIGS = {
     "bh_walk_accel": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P, P]),
     "bh_direct_accel": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
     "bh_direct": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
+    "bh_ewald_create": (ctypes.c_int, [P, f64, ctypes.c_int, PP]),
+    "bh_ewald_destroy": (ctypes.c_int, [P]),
+    "bh_ewald_export": (ctypes.c_int, [P, P, P]),
+    "bh_moments_export_trace": (ctypes.c_int, [P, P, P]),
+    "bh_walk_potential_periodic": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64, P, P]),
+    "bh_direct_periodic": (ctypes.c_int, [P, P, P, P, P, i64, f64, P]),
     "bh_batch_create": (ctypes.c_int, [P, PP, ctypes.c_int, P]),
     "bh_batch_destroy": (ctypes.c_int, [P]),
     "bh_batch_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64)]),
@@ -309,6 +315,49 @@ def bh_direct_accel(ctx, grid, m, targets, G, acc):
 def bh_direct(ctx, grid, m, targets, G, phi):
     n = int(targets.numel())
     _check(_lib.bh_direct(ctx, grid, m, _dev(targets, "int64"), n, float(G), _dev(phi, "float64")), ctx)
+    return phi
+
+
+# ------------------------------------------------------------------ periodic boxes
+
+EWALD_VALUES = 20
+
+
+def bh_ewald_create(ctx, box_size, n_points=33):
+    h = ctypes.c_void_p()
+    _check(_lib.bh_ewald_create(ctx, float(box_size), int(n_points), ctypes.byref(h)), ctx)
+    return h
+
+
+def bh_ewald_destroy(table):
+    _lib.bh_ewald_destroy(table)
+
+
+def bh_ewald_export(ctx, table, n_points):
+    """fp64 table [n, n, n, 20] indexed [k][j][i] (z, y, x)."""
+    v = np.empty((n_points, n_points, n_points, EWALD_VALUES))
+    _check(_lib.bh_ewald_export(ctx, table, _ptr(v)), ctx)
+    return v
+
+
+def bh_moments_export_trace(ctx, m, n_nodes):
+    S = np.empty(n_nodes)
+    _check(_lib.bh_moments_export_trace(ctx, m, _ptr(S)), ctx)
+    return S
+
+
+def bh_walk_potential_periodic(ctx, grid, m, table, theta, theta_group, precision, G, phi, counts=None):
+    tg = _dev(theta_group, "float32") if theta_group is not None else None
+    cn = _dev(counts, "int32") if counts is not None else None
+    _check(_lib.bh_walk_potential_periodic(ctx, grid, m, table, float(theta), tg, int(precision), float(G),
+                                           _dev(phi, "float64"), cn), ctx)
+    return phi
+
+
+def bh_direct_periodic(ctx, grid, m, table, targets, G, phi):
+    n = int(targets.numel())
+    _check(_lib.bh_direct_periodic(ctx, grid, m, table, _dev(targets, "int64"), n, float(G), _dev(phi, "float64")),
+           ctx)
     return phi
 
 

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbh.so")
-SOURCES = ["bh_api.cpp", "bh_topology.cpp", "bh_mlp_api.cpp", "bh_batch_api.cpp", "bh_kernels.hip", "bh_mlp.hip"]
+SOURCES = ["bh_api.cpp", "bh_topology.cpp", "bh_mlp_api.cpp", "bh_batch_api.cpp", "bh_kernels.hip", "bh_mlp.hip",
+           "bh_periodic.hip"]
 ARCH = os.environ.get("BH_OFFLOAD_ARCH", "gfx950")
 
 

@@ -230,6 +230,7 @@ int bh_moments_destroy(bh_moments *m) {
     if (!m) return BH_OK;
     if (m->grid && m->grid->ctx && m->grid->ctx->device >= 0) (void)hipSetDevice(m->grid->ctx->device);
     hfree(m->d_mom);
+    hfree(m->d_s);
     hfree(m->d_w32);
     hfree(m->d_w64);
     hfree(m->d_f32);
@@ -256,7 +257,7 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
         m->grid = g;
         const int64_t nn = g->topo.n_nodes, nc = g->n_cells;
         hipError_t e;
-        if ((e = dalloc(&m->d_mom, (size_t)nn * bh::kMom)) != hipSuccess ||
+        if ((e = dalloc(&m->d_mom, (size_t)nn * bh::kMom)) != hipSuccess || (e = dalloc(&m->d_s, (size_t)nn)) != hipSuccess ||
             (e = dalloc(&m->d_w32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_w64, (size_t)nn)) != hipSuccess ||
             (e = dalloc(&m->d_f32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_cell64, (size_t)nc)) != hipSuccess ||
             (e = dalloc(&m->d_cell32, (size_t)nc)) != hipSuccess || (e = dalloc(&m->d_flags, 2)) != hipSuccess ||
@@ -531,6 +532,104 @@ int bh_direct_accel(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const in
     if (n > 0 && (!targets || !acc)) return fail(ctx, BH_EINVAL, "targets_dev or acc_dev is NULL");
     if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
     HIPX(ctx, bh::launch_direct(g, m, targets, n, G, acc, true, ctx->stream), "direct-sum acceleration kernel");
+    return BH_OK;
+}
+
+// ------------------------------------------------------------------ periodic boxes
+
+int bh_moments_export_trace(bh_ctx *ctx, const bh_moments *m, double *S) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!m || !S) return fail(ctx, BH_EINVAL, "moments handle or S is NULL");
+    const int64_t nn = m->grid->topo.n_nodes;
+    HIPX(ctx, hipMemcpyAsync(S, m->d_s, (size_t)nn * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+         "copy of S");
+    HIPX(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    return BH_OK;
+}
+
+int bh_ewald_create(bh_ctx *ctx, double box_size, int n_points, bh_ewald **out) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!out) return fail(ctx, BH_EINVAL, "output handle pointer is NULL");
+    *out = nullptr;
+    if (!(box_size > 0.0) || !std::isfinite(box_size)) return fail(ctx, BH_EINVAL, "box_size must be finite and > 0");
+    if (n_points < 3 || n_points > BH_EWALD_MAX_POINTS)
+        return fail(ctx, BH_EINVAL, "n_points must be in [3, BH_EWALD_MAX_POINTS]");
+    bh_ewald *e = new (std::nothrow) bh_ewald();
+    if (!e) return fail(ctx, BH_ENOMEM, "host allocation of the table handle");
+    e->ctx = ctx;
+    e->L = box_size;
+    e->n = n_points;
+    e->sp = 0.5 * box_size / (n_points - 1);
+    const size_t count = (size_t)n_points * n_points * n_points * bh::kEwaldValues;
+    hipError_t err;
+    if ((err = dalloc(&e->d_t64, count)) != hipSuccess || (err = dalloc(&e->d_t32, count)) != hipSuccess) {
+        bh_ewald_destroy(e);
+        return hip_fail(ctx, err, "device allocation of the table");
+    }
+    if ((err = bh::launch_ewald_table(e, ctx->stream)) != hipSuccess) {
+        bh_ewald_destroy(e);
+        return hip_fail(ctx, err, "table kernel");
+    }
+    *out = e;
+    return BH_OK;
+}
+
+int bh_ewald_destroy(bh_ewald *e) {
+    if (!e) return BH_OK;
+    if (e->ctx && e->ctx->device >= 0) (void)hipSetDevice(e->ctx->device);
+    hfree(e->d_t64);
+    hfree(e->d_t32);
+    delete e;
+    return BH_OK;
+}
+
+int bh_ewald_export(bh_ctx *ctx, const bh_ewald *e, double *values) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!e || !values) return fail(ctx, BH_EINVAL, "table handle or values is NULL");
+    const size_t count = (size_t)e->n * e->n * e->n * bh::kEwaldValues;
+    HIPX(ctx, hipMemcpyAsync(values, e->d_t64, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+         "copy of the table");
+    HIPX(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    return BH_OK;
+}
+
+namespace {
+int check_periodic(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const bh_ewald *e) {
+    if (!g || !m || !e) return fail(ctx, BH_EINVAL, "grid, moments or table is NULL");
+    if (m->grid != g) return fail(ctx, BH_ESTATE, "moments belong to another grid");
+    if (std::fabs(g->topo.box - e->L) > 1e-12 * e->L)
+        return fail(ctx, BH_EINVAL, "the table was made for another box size");
+    return BH_OK;
+}
+}  // namespace
+
+int bh_walk_potential_periodic(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
+                               const float *theta_group, int precision, double G, double *phi, int32_t *counts) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if ((rc = check_periodic(ctx, g, m, e))) return rc;
+    if (!phi) return fail(ctx, BH_EINVAL, "phi_dev is NULL");
+    if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
+    if (!theta_group && !(theta > 0.0 && theta <= 1.0)) return fail(ctx, BH_EINVAL, "theta must be in (0, 1]");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    m->walk_epoch++;
+    HIPX(ctx, bh::launch_walk_potential_periodic(g, m, e, theta, theta_group, precision, G, phi, counts, ctx->stream),
+         "periodic walk + potential kernel");
+    return BH_OK;
+}
+
+int bh_direct_periodic(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const bh_ewald *e, const int64_t *targets,
+                       int64_t n, double G, double *phi) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if ((rc = check_periodic(ctx, g, m, e))) return rc;
+    if (n < 0) return fail(ctx, BH_EINVAL, "n_targets must be >= 0");
+    if (n > 0 && (!targets || !phi)) return fail(ctx, BH_EINVAL, "targets_dev or phi_dev is NULL");
+    if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
+    HIPX(ctx, bh::launch_direct_periodic(g, m, e, targets, n, G, phi, ctx->stream), "periodic direct-sum kernel");
     return BH_OK;
 }
 

@@ -41,7 +41,7 @@ struct alignas(16) WalkRec64 {
 struct alignas(16) FarRec32 {
     float x, y, z, m;
     float a, b, f, c;
-    float d, e, pad0, pad1;
+    float d, e, s, pad1;  // s = sum m |r - X|^2 (periodic sums)
 };
 // fp64 node moments, 12 doubles per node:
 //   0 X, 1 Y, 2 Z, 3 M, 4 Qxx, 5 Qyy, 6 Qzz, 7 Qxy, 8 Qxz, 9 Qyz, 10 delta,
@@ -86,6 +86,13 @@ struct WalkArgs {
     // and each group's algorithmic cost, written for the next call's order
     const int32_t *order;
     uint32_t *cost_out;
+    // periodic kernels: box side, the Green's function table (fp32 or fp64 to
+    // match the path) and its spacing, and the fp64 S of every node
+    double box;
+    const void *ewald;
+    double ewald_sp;
+    int ewald_n;
+    const double *node_s;
 };
 
 // Host-side octree topology built from the block list.
@@ -118,6 +125,19 @@ struct bh_ctx {
     std::string err;
 };
 
+namespace bh {
+constexpr int kEwaldValues = 20;  // D, gradient (3), Hessian (6), third derivatives (10)
+}
+
+struct bh_ewald {
+    bh_ctx *ctx = nullptr;
+    double L = 0.0;   // box side
+    int n = 0;        // points per axis over [0, L/2]
+    double sp = 0.0;  // spacing (L/2) / (n - 1)
+    double *d_t64 = nullptr;  // [n^3][20] D and its derivatives to third order
+    float *d_t32 = nullptr;
+};
+
 struct bh_grid {
     bh_ctx *ctx = nullptr;
     bh::Topology topo;
@@ -138,6 +158,7 @@ struct bh_grid {
 struct bh_moments {
     const bh_grid *grid = nullptr;
     double *d_mom = nullptr;              // [n_nodes][kMom]
+    double *d_s = nullptr;                // [n_nodes] sum m |r - X|^2
     bh::WalkRec32 *d_w32 = nullptr;
     bh::WalkRec64 *d_w64 = nullptr;
     bh::FarRec32 *d_f32 = nullptr;
@@ -191,6 +212,14 @@ bool fused_variant_exists(int precision, int waves);
 hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
                        int precision, bool fill, hipStream_t s);
 hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipStream_t s);
+// Periodic Green's function table, periodic fused walk + sums, periodic
+// direct sum.
+hipError_t launch_ewald_table(const bh_ewald *e, hipStream_t s);
+hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
+                                          const float *theta_group, int precision, double G, double *phi,
+                                          int32_t *counts, hipStream_t s);
+hipError_t launch_direct_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, const int64_t *targets,
+                                  int64_t n, double G, double *out, hipStream_t s);
 hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                                  int precision, double G, double *phi, int32_t *counts, hipStream_t s);
 // fused walk with an opening test (BH_MAC_*) and far-field order (2 or 0)

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bh_device.h"
+#include "bh_ewald.h"
 #include "bh_internal.h"
 #include "bh_theta_net.h"
 
@@ -29,10 +30,11 @@ struct MomOut {
     WalkRec32 *w32;
     WalkRec64 *w64;
     FarRec32 *f32;
+    double *s;  // [n] sum m |r - X|^2
 };
 
 // Write every derived record of node `id` from its fp64 moments.
-__device__ void store_node(const MomOut &o, int id, double M, double X, double Y, double Z, const double *Q,
+__device__ void store_node(const MomOut &o, int id, double M, double X, double Y, double Z, const double *Q, double S,
                            const double *geom, int child, int sflags, double mmax = 0.0) {
 #pragma clang fp contract(off)
     double cx = geom[0], cy = geom[1], cz = geom[2], l = geom[3];
@@ -51,7 +53,9 @@ __device__ void store_node(const MomOut &o, int id, double M, double X, double Y
         for (int c = 0; c < 6; c++) q[c] = 0.0;
         flags |= FLAG_EMPTY;
         M = 0.0;
+        S = 0.0;
     }
+    o.s[id] = S;
     double *mo = o.mom + (int64_t)id * kMom;
     mo[0] = X;
     mo[1] = Y;
@@ -90,7 +94,7 @@ __device__ void store_node(const MomOut &o, int id, double M, double X, double Y
     f.c = (float)q[3];
     f.d = (float)q[4];
     f.e = (float)q[5];
-    f.pad0 = 0.f;
+    f.s = (float)S;
     f.pad1 = 0.f;
     o.f32[id] = f;
 }
@@ -114,10 +118,11 @@ __device__ __forceinline__ double max8(double v) {
 }
 
 // One node from its 8 children held by the 8 lanes of a group (child c in
-// lane c): M, centre of mass, quadrupole about it by the parallel-axis rule.
-// Cells enter as children with Q = 0.  Every lane of the group gets the node.
-__device__ __forceinline__ void combine_lanes(double m, double x, double y, double z, const double *qc, double &M,
-                                              double &X, double &Y, double &Z, double *Q) {
+// lane c): M, centre of mass, quadrupole and S = sum m |r - X|^2 about it by
+// the parallel-axis rule.  Cells enter as children with Q = 0 and S = 0.
+// Every lane of the group gets the node.
+__device__ __forceinline__ void combine_lanes(double m, double x, double y, double z, const double *qc, double sc,
+                                              double &M, double &X, double &Y, double &Z, double *Q, double &S) {
 #pragma clang fp contract(off)
     M = sum8(m);
     const double sx = sum8(m * x), sy = sum8(m * y), sz = sum8(m * z);
@@ -132,6 +137,7 @@ __device__ __forceinline__ void combine_lanes(double m, double x, double y, doub
     Q[3] = sum8(qc[3] + m * (3.0 * dx * dy));
     Q[4] = sum8(qc[4] + m * (3.0 * dx * dz));
     Q[5] = sum8(qc[5] + m * (3.0 * dy * dz));
+    S = sum8(sc + m * r2);
 }
 
 // ---------------------------------------------------------------- dispatch schedule
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
                                                            double4 *__restrict__ cell64, float4 *__restrict__ cell32,
                                                            int *__restrict__ flags, int epoch, SchedArgs sa) {
 #pragma clang fp contract(off)
-    __shared__ double bM[64], bX[64], bY[64], bZ[64], bQ[64][6], bmax[64];
+    __shared__ double bM[64], bX[64], bY[64], bZ[64], bQ[64][6], bS[64], bmax[64];
     const int f = blockIdx.x;
     const int t = threadIdx.x;
     const LeafInfo L = leaves[f];
@@ -275,17 +281,18 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
     cell32[c] = make_float4((float)x, (float)y, (float)z, (float)mass);
     {  // bottom node t >> 3 from its 8 cells
         const double q0[6] = {0, 0, 0, 0, 0, 0};
-        double M, X, Y, Z, Q[6];
-        combine_lanes(mass, x, y, z, q0, M, X, Y, Z, Q);
+        double M, X, Y, Z, Q[6], S;
+        combine_lanes(mass, x, y, z, q0, 0.0, M, X, Y, Z, Q, S);
         const double mx = max8(mass);
         if ((t & 7) == 0) {
             const int b = t >> 3, id = L.bot_first + b;
-            store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], FLAG_BOTTOM, mx);
+            store_node(out, id, M, X, Y, Z, Q, S, geom + 4 * (int64_t)id, child_arr[id], FLAG_BOTTOM, mx);
             bM[b] = M;
             bX[b] = M > 0.0 ? X : geom[4 * (int64_t)id + 0];
             bY[b] = M > 0.0 ? Y : geom[4 * (int64_t)id + 1];
             bZ[b] = M > 0.0 ? Z : geom[4 * (int64_t)id + 2];
             for (int q = 0; q < 6; q++) bQ[b][q] = M > 0.0 ? Q[q] : 0.0;
+            bS[b] = M > 0.0 ? S : 0.0;
             bmax[b] = mx;
         }
     }
@@ -295,12 +302,12 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
         return;
     }
     // octant t >> 3 from its 8 bottom nodes (lane t holds bottom node t)
-    double M, X, Y, Z, Q[6];
-    combine_lanes(bM[t], bX[t], bY[t], bZ[t], bQ[t], M, X, Y, Z, Q);
+    double M, X, Y, Z, Q[6], S;
+    combine_lanes(bM[t], bX[t], bY[t], bZ[t], bQ[t], bS[t], M, X, Y, Z, Q, S);
     const double mx = max8(bmax[t]);
     const int o = t >> 3;
     const int oid = L.oct_first + o;
-    if ((t & 7) == 0) store_node(out, oid, M, X, Y, Z, Q, geom + 4 * (int64_t)oid, child_arr[oid], 0, mx);
+    if ((t & 7) == 0) store_node(out, oid, M, X, Y, Z, Q, S, geom + 4 * (int64_t)oid, child_arr[oid], 0, mx);
     // block node from the 8 octants: lane c of the first group takes octant c
     const double e = M > 0.0 ? 1.0 : 0.0;
     const double oX = M > 0.0 ? X : geom[4 * (int64_t)oid + 0];
@@ -309,12 +316,12 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
     const int src = 8 * (t & 7);
     double oq[6];
     for (int q = 0; q < 6; q++) oq[q] = __shfl(Q[q] * e, src, 64);
-    double BM, BX, BY, BZ, BQ[6];
-    combine_lanes(__shfl(M, src, 64), __shfl(oX, src, 64), __shfl(oY, src, 64), __shfl(oZ, src, 64), oq, BM, BX, BY,
-                  BZ, BQ);
+    double BM, BX, BY, BZ, BQ[6], BS;
+    combine_lanes(__shfl(M, src, 64), __shfl(oX, src, 64), __shfl(oY, src, 64), __shfl(oZ, src, 64), oq,
+                  __shfl(S * e, src, 64), BM, BX, BY, BZ, BQ, BS);
     if (t != 0) return;
     const int node = L.block_node;
-    store_node(out, node, BM, BX, BY, BZ, BQ, geom + 4 * (int64_t)node, child_arr[node], 0);
+    store_node(out, node, BM, BX, BY, BZ, BQ, BS, geom + 4 * (int64_t)node, child_arr[node], 0);
 }
 
 // Block-wide sum of one double per thread (256 threads), in a fixed order:
@@ -364,12 +371,14 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
     const double M = block_sum256(m, red);
     const double SX = block_sum256(sx, red), SY = block_sum256(sy, red), SZ = block_sum256(sz, red);
     const double X = M > 0.0 ? SX / M : 0.0, Y = M > 0.0 ? SY / M : 0.0, Z = M > 0.0 ? SZ / M : 0.0;
-    double qa[6] = {0, 0, 0, 0, 0, 0};
+    double qa[6] = {0, 0, 0, 0, 0, 0}, sa_ = 0.0;
     for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
-        const double *r = out.mom + (int64_t)leaves[f].block_node * kMom;
+        const int bn = leaves[f].block_node;
+        const double *r = out.mom + (int64_t)bn * kMom;
         const double mb = r[3];
         const double dx = r[0] - X, dy = r[1] - Y, dz = r[2] - Z;
         const double r2 = dx * dx + dy * dy + dz * dz;
+        sa_ += out.s[bn] + mb * r2;
         qa[0] += r[4] + mb * (3.0 * dx * dx - r2);
         qa[1] += r[5] + mb * (3.0 * dy * dy - r2);
         qa[2] += r[6] + mb * (3.0 * dz * dz - r2);
@@ -379,12 +388,13 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
     }
     double Q[6];
     for (int k = 0; k < 6; k++) Q[k] = block_sum256(qa[k], red);
-    if (threadIdx.x == 0) store_node(out, id, M, X, Y, Z, Q, geom + 4 * (int64_t)id, child_arr[id], 0);
+    const double S = block_sum256(sa_, red);
+    if (threadIdx.x == 0) store_node(out, id, M, X, Y, Z, Q, S, geom + 4 * (int64_t)id, child_arr[id], 0);
 }
 
 hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int fixed_epoch,
                           bool schedule) {
-    MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32};
+    MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32, m->d_s};
     const int nleaf = (int)g->topo.leaves.size();
     const int epoch = fixed_epoch > 0 ? fixed_epoch : ++m->mom_epoch;
     SchedArgs sa{};
@@ -472,7 +482,18 @@ struct Walker {
     int k8;
     real x0, y0, z0, h, hinv, inv;
     real blo[3], bhi[3];  // MAC 1 only
+    real cg[3], box, box_inv;  // MAC 2 (periodic) only
     bool overflow;
+
+    // min over the group's 4 cell centres x0 + k h on one axis of the
+    // nearest-image distance to X
+    __device__ real periodic_gap(real x0_, real X, real c) const {
+#pragma clang fp contract(off)
+        const real Xn = X - box * rint((X - c) * box_inv);  // image nearest the centre
+        const real Xo = Xn < c ? Xn + box : Xn - box;         // the next one on the other side
+        const real g1 = nearest_gap<real>(x0_, h, hinv, Xn, 4), g2 = nearest_gap<real>(x0_, h, hinv, Xo, 4);
+        return g1 < g2 ? g1 : g2;
+    }
 
     // theta_in > 0: this group's theta, given by the caller (as if read from a.theta_group)
     __device__ void init(const WalkArgs &a, const LeafInfo &L, int sub, int *stack, int lane, float theta_in = -1.0f) {
@@ -495,6 +516,14 @@ struct Walker {
             bhi[0] = (x0 + (real)3 * h) + half;
             bhi[1] = (y0 + (real)3 * h) + half;
             bhi[2] = (z0 + (real)3 * h) + half;
+        }
+        if constexpr (MAC == 2) {  // group centre, box
+#pragma clang fp contract(off)
+            cg[0] = x0 + (real)1.5 * h;
+            cg[1] = y0 + (real)1.5 * h;
+            cg[2] = z0 + (real)1.5 * h;
+            box = (real)a.box;
+            box_inv = (real)(1.0 / a.box);
         }
         if (theta_in > 0.0f || a.theta_group) {
             float th = theta_in > 0.0f ? theta_in : a.theta_group[(int64_t)L.canon * 8 + sub];
@@ -538,6 +567,12 @@ struct Walker {
                     dx = cube_gap<real>(blo[0], bhi[0], r.x);
                     dy = cube_gap<real>(blo[1], bhi[1], r.y);
                     dz = cube_gap<real>(blo[2], bhi[2], r.z);
+                } else if constexpr (MAC == 2) {
+                    // nearest-image distance from every cell: per axis the smaller gap of
+                    // the image nearest the group centre and the next one towards the group
+                    dx = periodic_gap(x0, r.x, cg[0]);
+                    dy = periodic_gap(y0, r.y, cg[1]);
+                    dz = periodic_gap(z0, r.z, cg[2]);
                 } else {
                     dx = nearest_gap<real>(x0, h, hinv, r.x, 4);
                     dy = nearest_gap<real>(y0, h, hinv, r.y, 4);
@@ -921,6 +956,11 @@ struct Tiles {
 
     __device__ void init() { acc_far = acc_near = 0.0; }
 
+    __device__ void load(int64_t id, V4 &a, V4 &b, V4 &c) const {
+        a = rec[3 * id + 0];
+        b = rec[3 * id + 1];
+        c = rec[3 * id + 2];
+    }
     __device__ void put(int lane, const V4 a, const V4 b, const V4 c) {
         T[3 * lane + 0] = a;
         T[3 * lane + 1] = b;
@@ -980,6 +1020,11 @@ struct TilesAcc {
         else
             return q;
     }
+    __device__ void load(int64_t id, V4 &a, V4 &b, V4 &c) const {
+        a = rec[3 * id + 0];
+        b = rec[3 * id + 1];
+        c = rec[3 * id + 2];
+    }
     __device__ void put(int lane, const V4 a, const V4 b, const V4 c) {
         T[3 * lane + 0] = a;
         T[3 * lane + 1] = full_q(b);
@@ -1023,6 +1068,125 @@ struct TilesAcc {
         a.acc[3 * cell + 1] = a.G * gy;
         a.acc[3 * cell + 2] = a.G * gz;
     }
+};
+
+// The tiles of the periodic kernels.  Every pair is taken at its nearest
+// image (far nodes are staged at the image nearest the group centre, which
+// leaves each lane at most one box length to remove).  A far pair adds,
+// beside the 1/|R| and quadrupole terms, the smooth part of the periodic
+// Green's function from the table, its Hessian against the quadrupole and
+// the background curvature against S: M D(R) + Q:H(R) / 6 + 2 pi S / (3 L^3).
+// A near pair adds m psi(R) = m (1/|R| + D(R)), the cell itself m D(0).
+// The staged far record: (X', M), the quadrupole as in the path's far
+// record, and S in the third vector's third slot.
+template <typename real>
+struct TilesPeriodic {
+    using V4 = typename Prec<real>::V4;
+    V4 *T;
+    const V4 *rec;
+    const V4 *cells;
+    const int32_t *child;
+    const double *node_s;
+    V4 me;
+    int own_lo;
+    double acc_far, acc_near;
+    EwaldView<real> ew;
+    real cg[3], box, box_inv, bg;
+
+    __device__ void setup(const WalkArgs &a, const LeafInfo &L, int sub) {
+#pragma clang fp contract(off)
+        const real h = (real)L.h;
+        const int i0 = (sub & 1) * 4, j0 = ((sub >> 1) & 1) * 4, k0 = ((sub >> 2) & 1) * 4;
+        const real eg = (real)1.5 * h;
+        cg[0] = (real)(L.lo[0] + (i0 + 0.5) * L.h) + eg;
+        cg[1] = (real)(L.lo[1] + (j0 + 0.5) * L.h) + eg;
+        cg[2] = (real)(L.lo[2] + (k0 + 0.5) * L.h) + eg;
+        box = (real)a.box;
+        box_inv = (real)(1.0 / a.box);
+        bg = (real)(2.0 * 3.14159265358979323846 / (3.0 * a.box * a.box * a.box));
+        ew.tab = (const real *)a.ewald;
+        ew.sp = (real)a.ewald_sp;
+        ew.inv_sp = (real)(1.0 / a.ewald_sp);
+        ew.n = a.ewald_n;
+        node_s = a.node_s;
+    }
+    __device__ void init() { acc_far = acc_near = 0.0; }
+    __device__ real image(real x, real c) const { return x - box * rint((x - c) * box_inv); }
+
+    __device__ void load(int64_t id, V4 &a, V4 &b, V4 &c) const {
+        a = rec[3 * id + 0];
+        b = rec[3 * id + 1];
+        c = rec[3 * id + 2];
+        if constexpr (sizeof(real) == 8) c.z = node_s[id];  // the fp64 row keeps delta there
+    }
+    __device__ void put(int lane, V4 a, const V4 b, const V4 c) {
+        a.x = image(a.x, cg[0]);
+        a.y = image(a.y, cg[1]);
+        a.z = image(a.z, cg[2]);
+        T[3 * lane + 0] = a;
+        T[3 * lane + 1] = b;
+        T[3 * lane + 2] = c;
+    }
+    __device__ void stage_far(int lane, int n, int id) {
+        if (lane < n) {
+            V4 a, b, c;
+            load(id, a, b, c);
+            put(lane, a, b, c);
+        }
+        wave_lds_sync();
+    }
+    // M (1/|R| + D) + R^T Q R / (2 |R|^5) + Q:H / 6 + bg S of one staged node,
+    // R the nearest image of the cell from the node
+    __device__ real far_periodic(const V4 p, const V4 q, const V4 u) const {
+#pragma clang fp contract(off)
+        real dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
+        dx -= box * rint(dx * box_inv);
+        dy -= box * rint(dy * box_inv);
+        dz -= box * rint(dz * box_inv);
+        const real r2 = dx * dx + dy * dy + dz * dz;
+        const real ri = rsq_any(r2);
+        const real ri2 = ri * ri;
+        const EwaldPoint<real> ep = ewald_point(ew, dx, dy, dz);
+        const real D = ewald_value(ep);
+        real H[6];
+        ewald_hessian(ep, H);
+        real quad, qh;
+        if constexpr (sizeof(real) == 4) {  // q = (Qxx/2, Qyy/2, Qzz/2, Qxy), u = (Qxz, Qyz, S, -)
+            quad = (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) + (q.w * dx * dy + u.x * dx * dz + u.y * dy * dz);
+            qh = ((q.x * H[0] + q.y * H[1] + q.z * H[2]) + (q.w * H[3] + u.x * H[4] + u.y * H[5])) * ((real)1 / (real)3);
+        } else {  // q = (Qxx, Qyy, Qzz, Qxy), u = (Qxz, Qyz, S, -)
+            quad = (real)0.5 * (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) +
+                   (q.w * dx * dy + u.x * dx * dz + u.y * dy * dz);
+            qh = ((q.x * H[0] + q.y * H[1] + q.z * H[2]) + (real)2 * (q.w * H[3] + u.x * H[4] + u.y * H[5])) *
+                 ((real)1 / (real)6);
+        }
+        return p.w * (ri + D) + quad * (ri2 * ri2 * ri) + qh + bg * u.z;
+    }
+    __device__ void sum_far(int n) {
+        real part = 0;
+        for (int j = 0; j < n; j++) part += far_periodic(T[3 * j], T[3 * j + 1], T[3 * j + 2]);
+        acc_far += (double)part;
+        wave_lds_sync();
+    }
+    // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]
+    __device__ void near_tile(int lane, int n, int id) {
+        if (lane < 8 * n) T[lane] = cells[(int64_t)child[id] + (lane & 7)];
+        wave_lds_sync();
+        real part = 0;
+        for (int j = 0; j < 8 * n; j++) {
+            const V4 s = T[j];
+            real dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+            dx -= box * rint(dx * box_inv);
+            dy -= box * rint(dy * box_inv);
+            dz -= box * rint(dz * box_inv);
+            const real r2 = dx * dx + dy * dy + dz * dz;
+            const real ri = r2 > (real)0 ? rsq_any(r2) : (real)0;  // the cell itself: D(0) only
+            part += s.w * (ri + ewald_value(ewald_point(ew, dx, dy, dz)));
+        }
+        acc_near += (double)part;
+        wave_lds_sync();
+    }
+    __device__ void finish(const WalkArgs &a, int64_t cell) const { a.phi[cell] = -a.G * (acc_far + acc_near); }
 };
 
 struct PotArgs {
@@ -1167,6 +1331,7 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
     S.child = a.child;
     S.own_lo = L.bot_first + sub * 8;
     S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
+    if constexpr (MAC == 2) S.setup(a, L, sub);
     S.init();
     int *FB = sm.fbuf[w];
     int *NB = sm.nbuf[w];
@@ -1193,10 +1358,7 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
         ntot += __popcll(mn);
         wave_lds_sync();
         if (fcnt >= 64) {  // issue the loads of the next full tile; summed after the next step
-            const int64_t rid = FB[lane];
-            p0 = S.rec[3 * rid + 0];
-            p1 = S.rec[3 * rid + 1];
-            p2 = S.rec[3 * rid + 2];
+            S.load(FB[lane], p0, p1, p2);
             pending = true;
             const int rest = fcnt - 64;
             int v = lane < rest ? FB[64 + lane] : 0;
@@ -1297,6 +1459,39 @@ hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, dou
         else BH_OPTS(float, kFusedDefaultWaves32, 0, 0);
     }
 #undef BH_OPTS
+    return hipGetLastError();
+}
+
+// Periodic box (appendix "Periodic boundaries"): the walk with nearest images
+// (MAC mode 2), the sums through the periodic Green's function table
+// (TilesPeriodic).
+constexpr int kPeriodicWaves32 = 4, kPeriodicWaves64 = 2;
+template <typename real, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void walk_potential_periodic_kernel(WalkArgs a) {
+    __shared__ FusedSmem<real> sm;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
+    if (g < 0) return;
+    fused_group<real, TilesPeriodic<real>, 2>(a, g, w, lane, sm);
+}
+
+hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
+                                          const float *theta_group, int precision, double G, double *phi,
+                                          int32_t *counts, hipStream_t s) {
+    WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
+    a.box = g->topo.box;
+    a.ewald = precision == BH_FP64 ? (const void *)e->d_t64 : (const void *)e->d_t32;
+    a.ewald_sp = e->sp;
+    a.ewald_n = e->n;
+    a.node_s = m->d_s;
+    hipError_t e0 = attach_schedule(g, m, a, s);
+    if (e0 != hipSuccess) return e0;
+    const dim3 grid((unsigned)((g->n_groups + 3) / 4)), block(256);
+    if (precision == BH_FP64)
+        hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -86,6 +86,21 @@ class BarnesHut:
         B.bh_walk_accel(self.ctx, self.grid, self.m, theta, theta_group, precision, G, phi, acc, counts)
         return acc
 
+    def solve_periodic(self, rho: torch.Tensor, table, theta=0.5, theta_group=None, precision=B.BH_FP32, G=1.0,
+                       phi=None, counts=None):
+        """moments -> periodic walk + potential (``table`` from bh_ewald_create for this grid's box)."""
+        if phi is None:
+            phi = torch.empty_like(rho)
+        self.build_moments(rho)
+        B.bh_walk_potential_periodic(self.ctx, self.grid, self.m, table, theta, theta_group, precision, G, phi,
+                                     counts)
+        return phi
+
+    def direct_periodic(self, table, targets: torch.Tensor, G=1.0, out=None):
+        if out is None:
+            out = torch.empty(targets.numel(), dtype=torch.float64, device=targets.device)
+        return B.bh_direct_periodic(self.ctx, self.grid, self.m, table, targets, G, out)
+
     def check(self):
         B.bh_moments_check(self.ctx, self.m)
 
