@@ -46,14 +46,14 @@ F_NEAR_ACC = 19             # flop per (cell, near cell) pair with potential + a
 RMS_GATE = 1e-3
 EWALD_POINTS = 33  # periodic Green's function table: points per axis over half the box
 WEIGHTS = os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz")
-PROFILE = os.path.join(ROOT, "profiles", "walk_potential_learned_fp32_maclaurin_1p4M.md")
+PROFILE = os.path.join(ROOT, "profiles", "walk_potential_theta_fp32_maclaurin_1p4M.md")
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("bh_kernels.hip", "bh_theta_net.h", "bh_internal.h", "bh_device.h")
+KERNEL_SOURCES = ("bh_kernels.hip", "bh_ewald.h", "bh_internal.h", "bh_device.h")
 
 
 def kernel_source_sha256():
@@ -420,16 +420,17 @@ def main():
             learned["speedup_vs_fixed_fp32"] = fixed["fp32"]["ms_per_step"] / ms_step
             learned["speedup_vs_fixed_fp64"] = fixed["fp64"]["ms_per_step"] / ms_step
 
-    # ---- dominant kernel of the step: per-group theta + walk + far/near sums in one launch, timed inside
-    # whole steps (upward pass, then the kernel between two hipEvents on the library's stream, torch's
-    # current stream), as it runs in the step
+    # ---- dominant kernel of the step: the walk + far/near sums with the inferred per-group theta, timed
+    # inside whole steps (upward pass and inference, then the kernel between two hipEvents on the library's
+    # stream, torch's current stream), as it runs in the step
     stream = torch.cuda.current_stream()
     nrep = max(args.steps, 10)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrep)]
     for e0, e1 in evs:
         bh.build_moments(rho)
+        B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, theta_g, net.shift)
         e0.record(stream)
-        B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, B.BH_FP32, 1.0, phi, None)
+        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 1.0, theta_g, B.BH_FP32, 1.0, phi, None)
         e1.record(stream)
     torch.cuda.synchronize()
     pot_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / nrep
@@ -552,7 +553,7 @@ def main():
         "ablation": ablation,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
-                     "kernel": "walk_potential_learned_kernel<float, 6>", "kernel_ms": pot_ms,
+                     "kernel": "walk_potential_theta_kernel<float, 8>", "kernel_ms": pot_ms,
                      "flop_per_launch": flops,
                      "far_interactions": far_int, "near_pairs": near_pairs},
         "cpu_baseline": cpu,

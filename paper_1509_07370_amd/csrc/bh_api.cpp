@@ -239,6 +239,7 @@ int bh_moments_destroy(bh_moments *m) {
     hfree(m->d_flags);
     hfree(m->d_cost);
     hfree(m->d_order);
+    hfree(m->d_theta);
     hfree(m->d_sched);
     delete m;
     return BH_OK;
@@ -263,6 +264,7 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
             (e = dalloc(&m->d_cell32, (size_t)nc)) != hipSuccess || (e = dalloc(&m->d_flags, 2)) != hipSuccess ||
             (e = hipMemset(m->d_flags, 0, 2 * sizeof(int))) != hipSuccess ||
             (e = dalloc(&m->d_cost, (size_t)g->n_groups)) != hipSuccess ||
+            (e = dalloc(&m->d_theta, (size_t)g->n_groups)) != hipSuccess ||
             (e = dalloc(&m->d_order, (size_t)g->n_groups)) != hipSuccess ||
             (e = dalloc(&m->d_sched, 2 * 256 + 1)) != hipSuccess ||
             (e = hipMemset(m->d_sched, 0, (2 * 256 + 1) * sizeof(int))) != hipSuccess) {

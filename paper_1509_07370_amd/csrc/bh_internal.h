@@ -173,6 +173,7 @@ struct bh_moments {
     // dispatch schedule of the fused walks (single-grid calls): each fused
     // walk records the cost of every group; the next upward pass sorts the
     // groups by it into the order that the following fused walks dispatch
+    float *d_theta = nullptr;     // [n_groups] canonical order: the learned step's thetas
     uint32_t *d_cost = nullptr;   // [n_groups], internal group order
     int32_t *d_order = nullptr;   // [n_groups]
     int *d_sched = nullptr;       // bin histogram [256], placement cursors [256], finished count: zero between passes
@@ -220,6 +221,9 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
                                           int32_t *counts, hipStream_t s);
 hipError_t launch_direct_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, const int64_t *targets,
                                   int64_t n, double G, double *out, hipStream_t s);
+// The fused walk with a per-group theta array (a kernel of its own name).
+hipError_t launch_walk_potential_theta(const bh_grid *g, const bh_moments *m, const float *theta_group,
+                                       int precision, double G, double *phi, int32_t *counts, hipStream_t s);
 hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                                  int precision, double G, double *phi, int32_t *counts, hipStream_t s);
 // fused walk with an opening test (BH_MAC_*) and far-field order (2 or 0)

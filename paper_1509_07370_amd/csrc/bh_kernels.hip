@@ -19,7 +19,6 @@
 #include "bh_device.h"
 #include "bh_ewald.h"
 #include "bh_internal.h"
-#include "bh_theta_net.h"
 
 namespace bh {
 
@@ -495,8 +494,7 @@ struct Walker {
         return g1 < g2 ? g1 : g2;
     }
 
-    // theta_in > 0: this group's theta, given by the caller (as if read from a.theta_group)
-    __device__ void init(const WalkArgs &a, const LeafInfo &L, int sub, int *stack, int lane, float theta_in = -1.0f) {
+    __device__ void init(const WalkArgs &a, const LeafInfo &L, int sub, int *stack, int lane) {
         nodes = (const Rec *)a.nodes;
         stk = stack;
         k8 = a.k8_threshold;
@@ -525,8 +523,8 @@ struct Walker {
             box = (real)a.box;
             box_inv = (real)(1.0 / a.box);
         }
-        if (theta_in > 0.0f || a.theta_group) {
-            float th = theta_in > 0.0f ? theta_in : a.theta_group[(int64_t)L.canon * 8 + sub];
+        if (a.theta_group) {
+            float th = a.theta_group[(int64_t)L.canon * 8 + sub];
             if (!(th == th)) th = 1e-3f;
             th = th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
             inv = (real)1 / (real)th;
@@ -1307,23 +1305,14 @@ __device__ __forceinline__ uint32_t group_cost(int nfar, int nnear) {
 }
 
 // one group g of the grid described by a, on wavefront w of the workgroup;
-// TL: the tile evaluator (potential, or potential and acceleration)
-// theta_net: NULL, or the network that gives this group's theta first (its
-// value is also written to theta_out when that is not NULL)
+// TL: the tile evaluator (potential, potential and acceleration, periodic)
 template <typename real, typename TL = Tiles<real>, int MAC = 0>
-__device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w, int lane, FusedSmem<real> &sm,
-                                            const ThetaNetArgs *theta_net = nullptr, float *theta_out = nullptr) {
+__device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w, int lane, FusedSmem<real> &sm) {
     using V4 = typename Prec<real>::V4;
     const int f = (int)(g >> 3), sub = (int)(g & 7);
     const LeafInfo L = a.leaves[f];
-    float th = -1.0f;
-    if (theta_net) {  // the tile buffer is free until the walk starts
-        float *buf = reinterpret_cast<float *>(sm.tile[w]);
-        th = group_theta(*theta_net, L, sub, lane, buf, buf + BH_MLP_INPUTS);
-        if (theta_out && lane == 0) theta_out[(int64_t)L.canon * 8 + sub] = th;
-    }
     Walker<real, MAC> W;
-    W.init(a, L, sub, sm.stack[w], lane, th);
+    W.init(a, L, sub, sm.stack[w], lane);
     TL S;
     S.T = sm.tile[w];
     S.rec = (const V4 *)a.far_rec;
@@ -1495,36 +1484,31 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     return hipGetLastError();
 }
 
-// The learned-theta step in one kernel: each wavefront first evaluates the
-// network for its group (bh_theta_net.h), then walks and sums exactly as
-// walk_potential_kernel does with that theta.  The network's weight rows need
-// registers: at 6 waves per SIMD (80 VGPRs) it runs without spills or
-// scratch, faster than 8 waves with either.
-constexpr int kLearnedWaves32 = 6;
+// walk_potential_kernel with each group's theta read from an array (the
+// learned-theta step's walk, after the inference kernel): a kernel of its own
+// name, so that profiles tell per-group-theta walks from fixed-theta ones.
 template <typename real, int WAVES>
-__global__ __launch_bounds__(256, WAVES) void walk_potential_learned_kernel(WalkArgs a, ThetaNetArgs net,
-                                                                            float *theta_out) {
+__global__ __launch_bounds__(256, WAVES) void walk_potential_theta_kernel(WalkArgs a) {
     __shared__ FusedSmem<real> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
     if (g < 0) return;
-    fused_group<real>(a, g, w, lane, sm, &net, theta_out);
+    fused_group<real>(a, g, w, lane, sm);
 }
 
-hipError_t launch_learned_walk_potential(const bh_grid *g, const bh_moments *m, const ThetaNetArgs &net,
-                                         int precision, double G, double *phi, float *theta_out, int32_t *counts,
-                                         hipStream_t s) {
-    WalkArgs a = fused_args(g, m, 1.0, nullptr, precision, G, phi, counts, m->walk_epoch);
+hipError_t launch_walk_potential_theta(const bh_grid *g, const bh_moments *m, const float *theta_group,
+                                       int precision, double G, double *phi, int32_t *counts, hipStream_t s) {
+    WalkArgs a = fused_args(g, m, 1.0, theta_group, precision, G, phi, counts, m->walk_epoch);
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;
     const int blocks = (int)((g->n_groups + 3) / 4);
     if (precision == BH_FP64)
-        hipLaunchKernelGGL((walk_potential_learned_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0,
-                           s, a, net, theta_out);
+        hipLaunchKernelGGL((walk_potential_theta_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0,
+                           s, a);
     else
-        hipLaunchKernelGGL((walk_potential_learned_kernel<float, kLearnedWaves32>), dim3(blocks), dim3(256), 0, s, a,
-                           net, theta_out);
+        hipLaunchKernelGGL((walk_potential_theta_kernel<float, kFusedDefaultWaves32>), dim3(blocks), dim3(256), 0,
+                           s, a);
     return hipGetLastError();
 }
 
@@ -1595,6 +1579,7 @@ __global__ void batch_reset_kernel(const WalkArgs *__restrict__ grids, int n, un
 
 hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
                                  int precision, double G, double *phi, int32_t *counts, hipStream_t s) {
+    if (theta_group) return launch_walk_potential_theta(g, m, theta_group, precision, G, phi, counts, s);
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;

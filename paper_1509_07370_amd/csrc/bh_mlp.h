@@ -32,9 +32,6 @@ struct bh_mlp {
 namespace bh {
 hipError_t launch_mlp_bf16(bh_mlp *net, hipStream_t s);
 ThetaNetArgs theta_net_args(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift);
-hipError_t launch_learned_walk_potential(const bh_grid *g, const bh_moments *m, const ThetaNetArgs &net,
-                                         int precision, double G, double *phi, float *theta_out, int32_t *counts,
-                                         hipStream_t s);
 hipError_t launch_theta_infer(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift, float *theta,
                               hipStream_t s);
 hipError_t launch_mlp_forward(const bh_mlp *net, const float *feat, int64_t n, bool bf16, float shift, float *theta,

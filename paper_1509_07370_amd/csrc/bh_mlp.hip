@@ -225,18 +225,19 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ P, fl
     P[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-// Features and bf16 network in one pass, one wavefront per group (the code
-// the walk kernel runs before walking a group, see bh_theta_net.h).
-__global__ __launch_bounds__(256) void theta_infer_kernel(const LeafInfo *__restrict__ leaves, int64_t n_groups,
-                                                          ThetaNetArgs net, float *__restrict__ theta) {
-    __shared__ float buf[4][BH_MLP_INPUTS + BH_MLP_HIDDEN];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= n_groups) return;
-    const LeafInfo L = leaves[g >> 3];
-    const int sub = (int)(g & 7);
-    const float th = group_theta(net, L, sub, lane, buf[w], buf[w] + BH_MLP_INPUTS);
-    if (lane == 0) theta[(int64_t)L.canon * 8 + sub] = th;
+// Features and bf16 network in one pass (bh_theta_net.h), 16 groups per
+// single-wavefront workgroup; the weights are read from global memory (10 KB,
+// cached).
+__global__ __launch_bounds__(64) void theta_infer_kernel(const LeafInfo *__restrict__ leaves, int64_t n_groups,
+                                                         ThetaNetArgs net, float *__restrict__ theta) {
+    const int lane = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * 16;
+    const int cnt = (int)(n_groups - g0 < 16 ? n_groups - g0 : 16);
+    const float th = groups_theta16(net, leaves, g0, cnt, lane);
+    if (lane < cnt) {
+        const int64_t g = g0 + lane;
+        theta[(int64_t)leaves[g >> 3].canon * 8 + (g & 7)] = th;
+    }
 }
 
 ThetaNetArgs theta_net_args(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift) {
@@ -256,8 +257,9 @@ ThetaNetArgs theta_net_args(const bh_grid *g, const bh_moments *m, const bh_mlp 
 
 hipError_t launch_theta_infer(const bh_grid *g, const bh_moments *m, const bh_mlp *net, float shift, float *theta,
                               hipStream_t s) {
-    const int blocks = (int)((g->n_groups + 3) / 4);
-    hipLaunchKernelGGL(theta_infer_kernel, dim3(blocks), dim3(256), 0, s, g->d_leaves, g->n_groups,
+    if (g->n_groups == 0) return hipSuccess;
+    const int64_t blocks = (g->n_groups + 15) / 16;
+    hipLaunchKernelGGL(theta_infer_kernel, dim3((unsigned)blocks), dim3(64), 0, s, g->d_leaves, g->n_groups,
                        theta_net_args(g, m, net, shift), theta);
     return hipGetLastError();
 }

@@ -151,9 +151,10 @@ int bh_learned_walk_potential(bh_ctx *ctx, const bh_grid *g, const bh_moments *m
     if (!std::isfinite(shift)) return fail(ctx, BH_EINVAL, "theta_shift must be finite");
     if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
     m->walk_epoch++;
-    HIPX(ctx, bh::launch_learned_walk_potential(g, m, bh::theta_net_args(g, m, net, shift), precision, G, phi, theta,
-                                                counts, ctx->stream),
-         "learned-theta walk + potential kernel");
+    float *th = theta ? theta : m->d_theta;
+    HIPX(ctx, bh::launch_theta_infer(g, m, net, shift, th, ctx->stream), "theta inference kernel");
+    HIPX(ctx, bh::launch_walk_potential_theta(g, m, th, precision, G, phi, counts, ctx->stream),
+         "walk + potential kernel");
     return BH_OK;
 }
 

@@ -1,8 +1,6 @@
-// The per-group opening-angle network evaluated by one wavefront: group
-// features from node rows, then the bf16 network 12 -> 64 -> 64 -> 1 with one
-// hidden unit per lane.  Shared by the stand-alone inference kernel and the
-// walk kernel that infers each group's theta before walking it, so that both
-// produce the same theta bit for bit.
+// The per-group opening-angle network evaluated by one wavefront for up to 16
+// groups: group features from node rows, then the bf16 network
+// 12 -> 64 -> 64 -> 1 on the matrix cores.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,101 +46,123 @@ struct ThetaNetArgs {
     double box;
 };
 
-// theta of group (L, sub) on one wavefront; xs: 12 floats, hs: 64 floats of
-// this wavefront's LDS.  Feature order as in the features kernel.
-__device__ inline float group_theta(const ThetaNetArgs &n, const LeafInfo &L, int sub, int lane,
-                                                      float *xs, float *hs) {
-    // this lane's weights first, all loads independent: W1 row (12 bf16 as
-    // three 8-byte loads), W2 row (64 bf16 as eight 16-byte loads), biases
-    const uint2 *r1 = reinterpret_cast<const uint2 *>(n.w + OW1 + lane * BH_MLP_INPUTS);
-    const uint4 *r2 = reinterpret_cast<const uint4 *>(n.w + OW2 + lane * BH_MLP_HIDDEN);
-    uint2 w1[3];
-    uint4 w2[8];
-#pragma unroll
-    for (int q = 0; q < 3; q++) w1[q] = r1[q];
-#pragma unroll
-    for (int q = 0; q < 8; q++) w2[q] = r2[q];
-    const float b1 = bf16_load(n.w, OB1 + lane), b2 = bf16_load(n.w, OB2 + lane);
-    const float w3 = bf16_load(n.w, OW3 + lane), b3 = bf16_load(n.w, OB3);
-    const float mu = lane < BH_MLP_INPUTS ? n.mean[lane] : 0.0f, sc = lane < BH_MLP_INPUTS ? n.scale[lane] : 0.0f;
-    // lane i < 12 derives feature i: its argument in fp64 from the node rows,
-    // then one fp32 logarithm (order as in the features kernel)
+// Feature i of group (L, sub): its argument in fp64 from the node rows, then
+// one fp32 logarithm (order as in the features kernel).
+__device__ __forceinline__ float group_feature(const ThetaNetArgs &n, const LeafInfo &L, int sub, int i) {
     const int gnode = L.oct_first + sub;
-    if (lane < BH_MLP_INPUTS) {
-        float f = 6.0f;  // 0: log2(group cells)
-        if (lane == 1 || lane == 4 || lane == 11) {
-            const double Mg = n.mom[(int64_t)gnode * kMom + 3];
-            if (lane == 1) {
-                const double Mroot = n.mom[(int64_t)n.root * kMom + 3];
-                const double r = Mroot > 0.0 ? Mg / Mroot : 0.0;
-                f = logf((float)(r > 1e-30 ? r : 1e-30));
-            } else if (lane == 4) {
-                const double mmax = n.mom[(int64_t)gnode * kMom + 11];
-                f = Mg > 0.0 ? logf((float)(mmax / (Mg / 64.0))) : 0.0f;
-            } else {
-                const double Mb = n.mom[(int64_t)L.block_node * kMom + 3];
-                const double r = Mb > 0.0 ? 8.0 * Mg / Mb : 0.0;
-                f = Mb > 0.0 ? logf((float)(r > 1e-30 ? r : 1e-30)) : 0.0f;
-            }
-        } else if (lane == 2) {
-            f = logf((float)(4.0 * L.h / n.box));
-        } else if (lane == 3) {
-            f = rintf(log2f((float)(n.box / ((double)n.nbase * kNB * L.h))));
-        } else if (lane >= 5) {  // 5..10: (delta/l, |Q|/(M l^2)) of group node, block, block's parent
-            const int a = (lane - 5) >> 1;
-            const int pn = n.parent[L.block_node];
-            const int node = a == 0 ? gnode : (a == 1 ? L.block_node : (pn >= 0 ? pn : L.block_node));
-            const double *r = n.mom + (int64_t)node * kMom;
-            const double l = n.geom[4 * (int64_t)node + 3];
-            double arg;
-            if (((lane - 5) & 1) == 0) {
-                arg = r[10] / l + 1e-6;
-            } else {
-                const double M = r[3];
-                const double qf =
-                    sqrt(r[4] * r[4] + r[5] * r[5] + r[6] * r[6] + 2.0 * (r[7] * r[7] + r[8] * r[8] + r[9] * r[9]));
-                arg = (M > 0.0 ? qf / (M * l * l) : 0.0) + 1e-6;
-            }
-            f = logf((float)arg);
+    if (i == 0) return 6.0f;  // log2(group cells)
+    if (i == 1 || i == 4 || i == 11) {
+        const double Mg = n.mom[(int64_t)gnode * kMom + 3];
+        if (i == 1) {
+            const double Mroot = n.mom[(int64_t)n.root * kMom + 3];
+            const double r = Mroot > 0.0 ? Mg / Mroot : 0.0;
+            return logf((float)(r > 1e-30 ? r : 1e-30));
         }
-        xs[lane] = f;
-    }
-    wave_lds_sync();
-    if (lane < BH_MLP_INPUTS) xs[lane] = bf16_round((xs[lane] - mu) * sc);
-    wave_lds_sync();
-    float a1 = b1;
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-        const uint32_t wv[2] = {w1[q].x, w1[q].y};
-#pragma unroll
-        for (int p = 0; p < 2; p++) {
-            a1 = fmaf(__uint_as_float(wv[p] << 16), xs[4 * q + 2 * p], a1);
-            a1 = fmaf(__uint_as_float(wv[p] & 0xFFFF0000u), xs[4 * q + 2 * p + 1], a1);
+        if (i == 4) {
+            const double mmax = n.mom[(int64_t)gnode * kMom + 11];
+            return Mg > 0.0 ? logf((float)(mmax / (Mg / 64.0))) : 0.0f;
         }
+        const double Mb = n.mom[(int64_t)L.block_node * kMom + 3];
+        const double r = Mb > 0.0 ? 8.0 * Mg / Mb : 0.0;
+        return Mb > 0.0 ? logf((float)(r > 1e-30 ? r : 1e-30)) : 0.0f;
     }
-    hs[lane] = bf16_round(tanhf(a1));
-    wave_lds_sync();
-    float a2 = b2;
+    if (i == 2) return logf((float)(4.0 * L.h / n.box));
+    if (i == 3) return rintf(log2f((float)(n.box / ((double)n.nbase * kNB * L.h))));
+    // 5..10: (delta/l, |Q|/(M l^2)) of group node, block, block's parent
+    const int a = (i - 5) >> 1;
+    const int pn = n.parent[L.block_node];
+    const int node = a == 0 ? gnode : (a == 1 ? L.block_node : (pn >= 0 ? pn : L.block_node));
+    const double *r = n.mom + (int64_t)node * kMom;
+    const double l = n.geom[4 * (int64_t)node + 3];
+    double arg;
+    if (((i - 5) & 1) == 0) {
+        arg = r[10] / l + 1e-6;
+    } else {
+        const double M = r[3];
+        const double qf =
+            sqrt(r[4] * r[4] + r[5] * r[5] + r[6] * r[6] + 2.0 * (r[7] * r[7] + r[8] * r[8] + r[9] * r[9]));
+        arg = (M > 0.0 ? qf / (M * l * l) : 0.0) + 1e-6;
+    }
+    return logf((float)arg);
+}
+
+// theta of up to 16 groups g0 .. g0 + cnt - 1 on one wavefront, the network
+// as three small matrix products on the matrix cores
+// (v_mfma_f32_16x16x16_bf16: bf16 operands, fp32 accumulation).  Lane
+// l = c + 16 q (c = l & 15, q = l >> 4) takes part in every product as
+// column c and k-slot q (items 0..3 of its operand), and receives rows
+// 4q .. 4q + 3 of column c of the result.  The products are written
+// transposed, hidden unit x group, so that a layer's result is already in
+// the operand layout of the next one: no data moves between lanes.
+//   layer 1: H1 (64 x 16) = W1 (64 x 12) X^T (12 x 16) + b1, four row tiles,
+//            the 12 inputs packed as k = 3q + i (i < 3; item 3 is zero);
+//   layer 2: H2 = W2 (64 x 64) tanh(H1) + b2, k-step s = row tile s of H1;
+//   output:  z = w3 . tanh(H2) + b3, per lane over its 16 rows, then across
+//            the four lanes of a column in a fixed order.
+// The order of the k sum inside a product is the hardware's; results equal
+// the fused-multiply-add forward up to fp32 rounding.  Returns group c's
+// theta (snapped) in every lane of column c; columns c >= cnt are not valid.
+typedef short bh_bf16x4 __attribute__((ext_vector_type(4)));
+typedef float bh_f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(bf16_round(x)) >> 16); }
+
+__device__ inline float groups_theta16(const ThetaNetArgs &n, const LeafInfo *leaves, int64_t g0, int cnt, int lane) {
+    const int c = lane & 15, q = lane >> 4;
+    // inputs 3q .. 3q + 2 of group g0 + c, standardised and rounded to bf16
+    bh_bf16x4 x = {0, 0, 0, 0};
+    if (c < cnt) {
+        const int64_t g = g0 + c;
+        const LeafInfo L = leaves[g >> 3];
+        const int sub = (int)(g & 7);
+        const int f = 3 * q;
+        x[0] = bf16_bits((group_feature(n, L, sub, f) - n.mean[f]) * n.scale[f]);
+        x[1] = bf16_bits((group_feature(n, L, sub, f + 1) - n.mean[f + 1]) * n.scale[f + 1]);
+        x[2] = bf16_bits((group_feature(n, L, sub, f + 2) - n.mean[f + 2]) * n.scale[f + 2]);
+    }
+    const short *w = reinterpret_cast<const short *>(n.w);
+    // layer 1
+    bh_bf16x4 h1[4];
 #pragma unroll
-    for (int k8 = 0; k8 < BH_MLP_HIDDEN / 8; k8++) {
-        const uint32_t wv[4] = {w2[k8].x, w2[k8].y, w2[k8].z, w2[k8].w};
+    for (int t = 0; t < 4; t++) {
+        const short *r = w + OW1 + (16 * t + c) * BH_MLP_INPUTS + 3 * q;
+        const bh_bf16x4 a = {r[0], r[1], r[2], 0};
+        bh_f32x4 acc;
 #pragma unroll
-        for (int p = 0; p < 4; p++) {
-            a2 = fmaf(__uint_as_float(wv[p] << 16), hs[8 * k8 + 2 * p], a2);
-            a2 = fmaf(__uint_as_float(wv[p] & 0xFFFF0000u), hs[8 * k8 + 2 * p + 1], a2);
+        for (int i = 0; i < 4; i++) acc[i] = bf16_load(n.w, OB1 + 16 * t + 4 * q + i);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, x, acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; i++) h1[t][i] = bf16_bits(tanhf(acc[i]));
+    }
+    // layer 2 and the output's partial sum
+    float part = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        bh_f32x4 acc;
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc[i] = bf16_load(n.w, OB2 + 16 * t + 4 * q + i);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            // W2[16t + c][16k + 4q .. 16k + 4q + 3]: 8 bytes, 8-byte aligned
+            const bh_bf16x4 a = *reinterpret_cast<const bh_bf16x4 *>(w + OW2 + (16 * t + c) * BH_MLP_HIDDEN + 16 * k +
+                                                                     4 * q);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[k], acc, 0, 0, 0);
         }
+#pragma unroll
+        for (int i = 0; i < 4; i++) part = fmaf(bf16_load(n.w, OW3 + 16 * t + 4 * q + i), bf16_round(tanhf(acc[i])), part);
     }
-    const float z = wave_sum(w3 * bf16_round(tanhf(a2))) + b3;
-    wave_lds_sync();  // xs / hs may be reused by the caller
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    const float z = part + bf16_load(n.w, OB3);
     const float th = 0.2f + 0.8f / (1.0f + expf(-z)) - n.shift;
     // snapped up to the grid 0.20, 0.25, ..., 1.00 on which the labels and the
     // safety shift are defined (the shift is calibrated charging each
     // prediction the error of the next grid value up): the walk then uses a
     // value whose error was measured, and a network saturating just below 1
     // walks at 1
-    int k = (int)ceilf((th - 1e-6f - 0.2f) * 20.0f);
-    k = k < 0 ? 0 : (k > 16 ? 16 : k);
-    return (float)(0.2 + 0.05 * (double)k);
+    int kk = (int)ceilf((th - 1e-6f - 0.2f) * 20.0f);
+    kk = kk < 0 ? 0 : (kk > 16 ? 16 : kk);
+    return (float)(0.2 + 0.05 * (double)kk);
 }
 
 }  // namespace bh
