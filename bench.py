@@ -397,11 +397,10 @@ def main():
         step_learned()
         rms, mx = errors()
         th = theta_g.cpu().numpy()
-        learned = dict(rms_rel_err=rms, max_rel_err=mx, sampled_rms_1pct=LT.sampled_rms(bh, phi),
+        learned = dict(rms_rel_err=rms, max_rel_err=mx,
                        theta_mean=float(th.mean()), theta_min=float(th.min()), theta_max=float(th.max()),
                        network_target=float(net.meta.get("target", RMS_GATE)), theta_shift=net.shift)
-        log("learned theta: rms %.2e (1%% sample %.2e), theta mean %.3f" % (rms, learned["sampled_rms_1pct"],
-                                                                           th.mean()))
+        log("learned theta: rms %.2e, theta mean %.3f" % (rms, th.mean()))
 
     # ---- timed region: K whole learned-theta steps
     for _ in range(args.warmup):
@@ -435,6 +434,11 @@ def main():
     torch.cuda.synchronize()
     pot_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / nrep
     B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, B.BH_FP32, 1.0, phi, theta_g, counts)
+    if learned:
+        # the method's 1% sampled check of the learned step (an fp64 direct sum on the sample), taken after
+        # the timed regions: a long fp64 kernel lowers the clocks of the kernels that follow it for tens of ms
+        learned["sampled_rms_1pct"] = LT.sampled_rms(bh, phi)
+        log("learned theta: 1%% sampled rms %.2e" % learned["sampled_rms_1pct"])
     c = counts.cpu().numpy().astype(np.int64)
     flops, far_int, near_pairs = algorithmic_flops(c[:, 0], c[:, 1])
     achieved = flops / (pot_ms * 1e-3) / 1e12

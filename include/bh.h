@@ -433,16 +433,18 @@ int bh_mlp_get_params(bh_ctx *ctx, const bh_mlp *net, float *params);
 int bh_mlp_forward(bh_ctx *ctx, const bh_mlp *net, const float *feat_dev, int64_t n, int bf16, float theta_shift,
                    float *theta_dev);
 /* Per-group theta for a walk in one pass: the features of bh_group_features
- * fed to the bf16 network (as bh_mlp_forward with bf16 = 1) without storing
- * them.  theta_dev: fp32 [n_groups], canonical group order. */
+ * fed to the bf16 network without storing them, the network's products on
+ * the matrix cores (16 groups per wavefront).  The output equals
+ * bh_mlp_forward with bf16 = 1 up to the fp32 rounding of the sums, and is
+ * snapped up to the grid 0.20, 0.25, ..., 1.00 the labels are defined on.
+ * theta_dev: fp32 [n_groups], canonical group order. */
 int bh_theta_infer(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_mlp *net, float theta_shift,
                    float *theta_dev);
-/* The whole learned-theta walk in one launch: each group's theta from the
- * network (exactly the value bh_theta_infer gives), then the walk and sums of
- * bh_walk_potential with that theta -- the same bits as bh_theta_infer
- * followed by bh_walk_potential with theta_group_dev, without the
- * intermediate launch.  theta_dev: NULL, or fp32 [n_groups] receiving the
- * thetas used.  Other arguments and errors as bh_walk_potential. */
+/* The whole learned-theta walk in one call: bh_theta_infer, then the walk
+ * and sums of bh_walk_potential with those thetas (two launches on the
+ * context's stream; the same bits as the two calls).  theta_dev: NULL (the
+ * thetas go to a buffer of the moments handle), or fp32 [n_groups] receiving
+ * the thetas used.  Other arguments and errors as bh_walk_potential. */
 int bh_learned_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh_mlp *net,
                               float theta_shift, int precision, double G, double *phi_dev, float *theta_dev,
                               int32_t *counts_dev);

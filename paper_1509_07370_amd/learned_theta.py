@@ -146,8 +146,9 @@ class ThetaNet:
 
 def solve_learned(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi: torch.Tensor, feat: torch.Tensor,
                   theta: torch.Tensor, precision=B.BH_FP32, G=1.0):
-    """moments -> one kernel: per group, features + bf16 network, then the walk + sums with that theta
-    (the thetas used land in ``theta``).  ``feat`` is unused (kept for callers that stage features)."""
+    """moments, then bh_learned_walk_potential: per group features + bf16 network (one kernel), then the walk +
+    sums with those thetas (the thetas used land in ``theta``).  ``feat`` is unused (kept for callers that
+    stage features)."""
     bh.build_moments(rho)
     B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, precision, G, phi, theta)
     return phi
