@@ -276,7 +276,11 @@ int bh_direct_accel(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const
 
 /* Build the table for box side box_size on n_points^3 points (spacing
  * box_size / (2 (n_points - 1))) on the context's device and stream
- * (asynchronous; fp64 and fp32 copies, 160 + 80 bytes per point).  Errors:
+ * (asynchronous).  It holds the fp64 values (160 bytes per point, what
+ * bh_ewald_export returns) and the rows the walks read, dimensionless and
+ * compact: D L and the gradient L^2 at the walk's precision, the Hessian L^3
+ * and third derivatives L^4 at half of it (fp64 walks and the direct sum:
+ * 96 bytes per point; fp32 walks: 48).  Errors:
  * BH_EINVAL (box_size <= 0 or not finite, n_points outside
  * [3, BH_EWALD_MAX_POINTS]), BH_ENOMEM, BH_EDEVICE. */
 int bh_ewald_create(bh_ctx *ctx, double box_size, int n_points, bh_ewald **table);

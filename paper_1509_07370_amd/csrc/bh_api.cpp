@@ -564,9 +564,11 @@ int bh_ewald_create(bh_ctx *ctx, double box_size, int n_points, bh_ewald **out) 
     e->L = box_size;
     e->n = n_points;
     e->sp = 0.5 * box_size / (n_points - 1);
-    const size_t count = (size_t)n_points * n_points * n_points * bh::kEwaldValues;
+    const size_t points = (size_t)n_points * n_points * n_points;
     hipError_t err;
-    if ((err = dalloc(&e->d_t64, count)) != hipSuccess || (err = dalloc(&e->d_t32, count)) != hipSuccess) {
+    if ((err = dalloc(&e->d_t64, points * bh::kEwaldValues)) != hipSuccess ||
+        (err = dalloc(&e->d_t64c, points * bh::kEwaldCompactDoubles)) != hipSuccess ||
+        (err = dalloc(&e->d_t32, points * bh::kEwaldCompactFloats)) != hipSuccess) {
         bh_ewald_destroy(e);
         return hip_fail(ctx, err, "device allocation of the table");
     }
@@ -582,6 +584,7 @@ int bh_ewald_destroy(bh_ewald *e) {
     if (!e) return BH_OK;
     if (e->ctx && e->ctx->device >= 0) (void)hipSetDevice(e->ctx->device);
     hfree(e->d_t64);
+    hfree(e->d_t64c);
     hfree(e->d_t32);
     delete e;
     return BH_OK;

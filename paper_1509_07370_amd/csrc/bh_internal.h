@@ -127,6 +127,12 @@ struct bh_ctx {
 
 namespace bh {
 constexpr int kEwaldValues = 20;  // D, gradient (3), Hessian (6), third derivatives (10)
+// The walks' table points, dimensionless: D L and gradient L^2, then Hessian
+// L^3 and third derivatives L^4 at half the precision.  fp32 walks: 4 fp32 +
+// 16 fp16 = 48 bytes (three 16-byte loads); fp64 walks: 4 fp64 + 16 fp32 =
+// 96 bytes (six).
+constexpr int kEwaldCompactFloats = 12;
+constexpr int kEwaldCompactDoubles = 12;
 }
 
 struct bh_ewald {
@@ -134,8 +140,9 @@ struct bh_ewald {
     double L = 0.0;   // box side
     int n = 0;        // points per axis over [0, L/2]
     double sp = 0.0;  // spacing (L/2) / (n - 1)
-    double *d_t64 = nullptr;  // [n^3][20] D and its derivatives to third order
-    float *d_t32 = nullptr;
+    double *d_t64 = nullptr;   // [n^3][20] D and its derivatives to third order (export)
+    double *d_t64c = nullptr;  // [n^3][12] compact rows of the fp64 walks and direct sum
+    float *d_t32 = nullptr;    // [n^3][12] compact rows of the fp32 walks
 };
 
 struct bh_grid {

@@ -1090,6 +1090,7 @@ struct TilesPeriodic {
     double acc_far, acc_near;
     EwaldView<real> ew;
     real cg[3], box, box_inv, bg;
+    real dscale, qscale;  // table value -> D, and the Q:H sum -> Q:H / 6 (fp32 rows are scaled by powers of L)
 
     __device__ void setup(const WalkArgs &a, const LeafInfo &L, int sub) {
 #pragma clang fp contract(off)
@@ -1106,6 +1107,11 @@ struct TilesPeriodic {
         ew.sp = (real)a.ewald_sp;
         ew.inv_sp = (real)(1.0 / a.ewald_sp);
         ew.n = a.ewald_n;
+        ew.inv_box = box_inv;
+        ew.sp_box = (real)(a.ewald_sp / a.box);
+        // the table gives D L and H L^3; fp32 records hold Q/2 on the diagonal
+        dscale = box_inv;
+        qscale = (real)(1.0 / ((sizeof(real) == 4 ? 3.0 : 6.0) * a.box * a.box * a.box));
         node_s = a.node_s;
     }
     __device__ void init() { acc_far = acc_near = 0.0; }
@@ -1133,54 +1139,91 @@ struct TilesPeriodic {
         }
         wave_lds_sync();
     }
-    // M (1/|R| + D) + R^T Q R / (2 |R|^5) + Q:H / 6 + bg S of one staged node,
-    // R the nearest image of the cell from the node
-    __device__ real far_periodic(const V4 p, const V4 q, const V4 u) const {
-#pragma clang fp contract(off)
-        real dx = me.x - p.x, dy = me.y - p.y, dz = me.z - p.z;
-        dx -= box * rint(dx * box_inv);
-        dy -= box * rint(dy * box_inv);
-        dz -= box * rint(dz * box_inv);
+    // The cell's nearest image R of a staged position and its table point.
+    struct Pair {
+        real dx, dy, dz;
+        EwaldPoint<real> ep;
+    };
+    __device__ Pair pair_at(const V4 p) const {
+        Pair c;
+        c.dx = me.x - p.x;
+        c.dy = me.y - p.y;
+        c.dz = me.z - p.z;
+        c.dx -= box * rint(c.dx * box_inv);
+        c.dy -= box * rint(c.dy * box_inv);
+        c.dz -= box * rint(c.dz * box_inv);
+        c.ep = ewald_point(ew, c.dx, c.dy, c.dz);
+        return c;
+    }
+    // sum over j < n of eval(pair, table row, j), the table row of pair j + 1
+    // fetched before pair j is evaluated (two register buffers in turn)
+    template <typename At, typename Eval>
+    __device__ real pipelined(int n, At at, Eval eval) const {
+        real part = 0;
+        if (n <= 0) return part;
+        Pair ca = pair_at(at(0)), cb;
+        real va[kEwaldValues], vb[kEwaldValues];
+        ewald_fetch(ew, ca.ep.row, va);
+        for (int j = 0;; j += 2) {
+            const bool m1 = j + 1 < n;
+            if (m1) {
+                cb = pair_at(at(j + 1));
+                ewald_fetch(ew, cb.ep.row, vb);
+            }
+            part += eval(ca, va, j);
+            if (!m1) break;
+            const bool m2 = j + 2 < n;
+            if (m2) {
+                ca = pair_at(at(j + 2));
+                ewald_fetch(ew, ca.ep.row, va);
+            }
+            part += eval(cb, vb, j + 1);
+            if (!m2) break;
+        }
+        return part;
+    }
+    // M (1/|R| + D) + R^T Q R / (2 |R|^5) + Q:H / 6 + bg S of one staged node
+    __device__ real far_eval(const Pair &c, const real (&v)[kEwaldValues], const V4 p, const V4 q, const V4 u) const {
+        const real dx = c.dx, dy = c.dy, dz = c.dz;
         const real r2 = dx * dx + dy * dy + dz * dz;
         const real ri = rsq_any(r2);
         const real ri2 = ri * ri;
-        const EwaldPoint<real> ep = ewald_point(ew, dx, dy, dz);
-        const real D = ewald_value(ep);
         real H[6];
-        ewald_hessian(ep, H);
+        const real D = ewald_eval(c.ep, v, H);
         real quad, qh;
         if constexpr (sizeof(real) == 4) {  // q = (Qxx/2, Qyy/2, Qzz/2, Qxy), u = (Qxz, Qyz, S, -)
             quad = (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) + (q.w * dx * dy + u.x * dx * dz + u.y * dy * dz);
-            qh = ((q.x * H[0] + q.y * H[1] + q.z * H[2]) + (q.w * H[3] + u.x * H[4] + u.y * H[5])) * ((real)1 / (real)3);
+            qh = ((q.x * H[0] + q.y * H[1] + q.z * H[2]) + (q.w * H[3] + u.x * H[4] + u.y * H[5])) * qscale;
         } else {  // q = (Qxx, Qyy, Qzz, Qxy), u = (Qxz, Qyz, S, -)
             quad = (real)0.5 * (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) +
                    (q.w * dx * dy + u.x * dx * dz + u.y * dy * dz);
-            qh = ((q.x * H[0] + q.y * H[1] + q.z * H[2]) + (real)2 * (q.w * H[3] + u.x * H[4] + u.y * H[5])) *
-                 ((real)1 / (real)6);
+            qh = ((q.x * H[0] + q.y * H[1] + q.z * H[2]) + (real)2 * (q.w * H[3] + u.x * H[4] + u.y * H[5])) * qscale;
         }
-        return p.w * (ri + D) + quad * (ri2 * ri2 * ri) + qh + bg * u.z;
+        return p.w * (ri + D * dscale) + quad * (ri2 * ri2 * ri) + qh + bg * u.z;
     }
     __device__ void sum_far(int n) {
-        real part = 0;
-        for (int j = 0; j < n; j++) part += far_periodic(T[3 * j], T[3 * j + 1], T[3 * j + 2]);
+        const V4 *t = T;
+        const real part = pipelined(
+            n, [t](int j) { return t[3 * j]; },
+            [this, t](const Pair &c, const real(&v)[kEwaldValues], int j) {
+                return far_eval(c, v, t[3 * j], t[3 * j + 1], t[3 * j + 2]);
+            });
         acc_far += (double)part;
         wave_lds_sync();
     }
-    // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]
+    // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]; each cell
+    // m (1/|R| + D), the cell itself D(0) only
     __device__ void near_tile(int lane, int n, int id) {
         if (lane < 8 * n) T[lane] = cells[(int64_t)child[id] + (lane & 7)];
         wave_lds_sync();
-        real part = 0;
-        for (int j = 0; j < 8 * n; j++) {
-            const V4 s = T[j];
-            real dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-            dx -= box * rint(dx * box_inv);
-            dy -= box * rint(dy * box_inv);
-            dz -= box * rint(dz * box_inv);
-            const real r2 = dx * dx + dy * dy + dz * dz;
-            const real ri = r2 > (real)0 ? rsq_any(r2) : (real)0;  // the cell itself: D(0) only
-            part += s.w * (ri + ewald_value(ewald_point(ew, dx, dy, dz)));
-        }
+        const V4 *t = T;
+        const real part = pipelined(
+            8 * n, [t](int j) { return t[j]; },
+            [this, t](const Pair &c, const real(&v)[kEwaldValues], int j) {
+                const real r2 = c.dx * c.dx + c.dy * c.dy + c.dz * c.dz;
+                const real ri = r2 > (real)0 ? rsq_any(r2) : (real)0;
+                return t[j].w * (ri + ewald_eval<real>(c.ep, v, nullptr) * dscale);
+            });
         acc_near += (double)part;
         wave_lds_sync();
     }
@@ -1470,7 +1513,7 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
                                           int32_t *counts, hipStream_t s) {
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     a.box = g->topo.box;
-    a.ewald = precision == BH_FP64 ? (const void *)e->d_t64 : (const void *)e->d_t32;
+    a.ewald = precision == BH_FP64 ? (const void *)e->d_t64c : (const void *)e->d_t32;
     a.ewald_sp = e->sp;
     a.ewald_n = e->n;
     a.node_s = m->d_s;

@@ -144,7 +144,7 @@ __device__ void ewald_sums(double L, const double *u, EwaldAcc &acc) {
 }
 
 __global__ __launch_bounds__(128) void ewald_table_kernel(double L, int n, double sp, double *__restrict__ t64,
-                                                          float *__restrict__ t32) {
+                                                          double *__restrict__ t64c, float *__restrict__ t32) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)n * n * n;
     if (q >= total) return;
@@ -152,16 +152,33 @@ __global__ __launch_bounds__(128) void ewald_table_kernel(double L, int n, doubl
     const double u[3] = {i * sp, j * sp, k * sp};
     EwaldAcc acc;
     ewald_sums(L, u, acc);
-    for (int v = 0; v < kEwaldValues; v++) {
-        t64[q * kEwaldValues + v] = acc.v[v];
-        t32[q * kEwaldValues + v] = (float)acc.v[v];
+    for (int v = 0; v < kEwaldValues; v++) t64[q * kEwaldValues + v] = acc.v[v];
+    // compact rows, dimensionless: D L, g L^2, H L^3, T L^4 (magnitudes up to a
+    // few hundred, far inside the fp16 range)
+    const double L2 = L * L, L3 = L2 * L, L4 = L3 * L;
+    double s[kEwaldValues];
+    s[0] = acc.v[0] * L;
+    for (int v = 1; v < 4; v++) s[v] = acc.v[v] * L2;
+    for (int v = 4; v < 10; v++) s[v] = acc.v[v] * L3;
+    for (int v = 10; v < kEwaldValues; v++) s[v] = acc.v[v] * L4;
+    double *rd = t64c + q * kEwaldCompactDoubles;  // 4 fp64, then 16 fp32
+    float *rf = t32 + q * kEwaldCompactFloats;     // 4 fp32, then 16 fp16
+    float *rd_hi = reinterpret_cast<float *>(rd + 4);
+    _Float16 *rf_hi = reinterpret_cast<_Float16 *>(rf + 4);
+    for (int v = 0; v < 4; v++) {
+        rd[v] = s[v];
+        rf[v] = (float)s[v];
+    }
+    for (int v = 4; v < kEwaldValues; v++) {
+        rd_hi[v - 4] = (float)s[v];
+        rf_hi[v - 4] = (_Float16)(float)s[v];
     }
 }
 
 hipError_t launch_ewald_table(const bh_ewald *e, hipStream_t s) {
     const int64_t total = (int64_t)e->n * e->n * e->n;
     hipLaunchKernelGGL(ewald_table_kernel, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, e->L, e->n, e->sp,
-                       e->d_t64, e->d_t32);
+                       e->d_t64, e->d_t64c, e->d_t32);
     return hipGetLastError();
 }
 
@@ -204,7 +221,7 @@ __global__ __launch_bounds__(256) void direct_periodic_kernel(const int64_t *__r
             dz -= L * rint(dz * inv_L);
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (base + j != self) part += s.w / sqrt(r2);
-            part += s.w * ewald_value(ewald_point(ew, dx, dy, dz));
+            part += s.w * ewald_value_at(ew, dx, dy, dz);
         }
         acc += part;
     }
@@ -214,7 +231,7 @@ __global__ __launch_bounds__(256) void direct_periodic_kernel(const int64_t *__r
 hipError_t launch_direct_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, const int64_t *targets,
                                   int64_t n, double G, double *out, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    EwaldView<double> ew{e->d_t64, 1.0 / e->sp, e->sp, e->n};
+    EwaldView<double> ew{e->d_t64c, 1.0 / e->sp, e->sp, e->n, 1.0 / e->L, e->sp / e->L};
     hipLaunchKernelGGL(direct_periodic_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, targets, n,
                        m->d_cell64, g->n_cells, g->d_internal_of_canon, ew, e->L, G, out);
     return hipGetLastError();
