@@ -6,7 +6,10 @@
 * gradient within 1e-4 (relative to its largest entry) of the FP64 gradient;
 * Adam steps track the FP64 Adam; training lowers the loss;
 * the learned path (features -> bf16 network -> per-group walk) equals a walk
-  given the same theta array, and the fallback triggers on an impossible target.
+  given the same theta array, and the fallback triggers on an impossible target;
+* the one-pass inference (matrix-core network, 16 groups per wavefront) equals
+  features + bf16 forward, snapped, on every group of a grid whose last
+  wavefront holds 8 groups.
 """
 import numpy as np
 import pytest
@@ -180,10 +183,42 @@ def test_learned_path_equals_walk_with_same_thetas_and_fallback():
     bh.close()
 
 
+@pytest.mark.parametrize("seed,scale", [(7, 3.0), (11, 1.0)])
+def test_theta_infer_equals_features_and_forward_on_a_ragged_grid(seed, scale):
+    g = random_amr(23, nbase=2, max_level=3, p_refine=0.3, zero_fraction=0.1)
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    assert ng % 16 == 8  # the last wavefront of the inference kernel holds 8 groups
+    X = LT.group_features(bh, rho).cpu().numpy()
+    net = LT.ThetaNet.fresh(bh.ctx, X, (glorot_init(seed) * scale).astype(np.float32))
+    for shift in (0.0, 0.1):
+        th = torch.full((ng,), float("nan"), device="cuda")
+        feat = torch.empty((ng, 12), dtype=torch.float32, device="cuda")
+        cont = torch.empty(ng, dtype=torch.float32, device="cuda")
+        bh.build_moments(rho)
+        B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, th, shift)
+        B.bh_group_features(bh.ctx, bh.grid, bh.m, feat)
+        B.bh_mlp_forward(bh.ctx, net.h, feat, cont, True, shift)
+        bh.check()
+        t = th.cpu().numpy()
+        c = cont.cpu().numpy().astype(np.float64)
+        k = np.clip(np.ceil((c - 1e-6 - 0.2) * 20.0), 0, 16)
+        snapped = (0.2 + 0.05 * k).astype(np.float32)
+        # the two sides round their sums differently (matrix-core products vs fused multiply-adds, fp64-argument
+        # features vs fp32 logs): a prediction within 5e-3 of a grid boundary may snap to the neighbour
+        near_edge = np.abs((c - 0.2) * 20.0 - np.round((c - 0.2) * 20.0)) < 0.1
+        assert np.all(np.isfinite(t))
+        assert np.all((t == snapped) | near_edge)
+        assert np.mean(t == snapped) > 0.95 and np.unique(t).size > 3
+    net.close()
+    bh.close()
+
+
 @pytest.mark.parametrize("precision", [B.BH_FP32, B.BH_FP64])
 def test_one_launch_learned_walk_equals_two_launches(precision):
-    """bh_learned_walk_potential infers each group's theta inside the walk
-    kernel: the same thetas as bh_theta_infer and the same potentials as
+    """bh_learned_walk_potential (inference, then the walk with those thetas):
+    the same thetas as bh_theta_infer and the same potentials as
     bh_walk_potential given them, bit for bit."""
     g = random_amr(23, nbase=2, max_level=3, p_refine=0.3, zero_fraction=0.1)
     bh = BarnesHut(g)
