@@ -323,16 +323,25 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
     store_node(out, node, BM, BX, BY, BZ, BQ, BS, geom + 4 * (int64_t)node, child_arr[node], 0);
 }
 
-// Block-wide sum of one double per thread (256 threads), in a fixed order:
-// wavefront butterflies, then the four wavefront totals in order.  Every
-// thread gets the same value.
-__device__ __forceinline__ double block_sum256(double v, double *red) {
+// N block-wide sums of one double per thread (256 threads) at once, each in
+// a fixed order: wavefront butterflies, then the four wavefront totals in
+// order; one pair of barriers for all of them.  Every thread gets the same
+// values.  red: N x 4 doubles of LDS.
+template <int N>
+__device__ __forceinline__ void block_sums256(double (&v)[N], double (*red)[4]) {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int k = 0; k < N; k++) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < N; k++) red[k][threadIdx.x >> 6] = v[k];
+    }
     __syncthreads();
-    return ((red[0] + red[1]) + red[2]) + red[3];
+#pragma unroll
+    for (int k = 0; k < N; k++) v[k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
 }
 
 // Nodes above the leaf blocks (virtual and parent-block nodes), one
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
                                                             const int32_t *__restrict__ child_arr, MomOut out,
                                                             SchedArgs sa) {
 #pragma clang fp contract(off)
-    __shared__ double red[4];
+    __shared__ double red[7][4];
     if (sa.cost && (int)blockIdx.x < sa.parts) {  // a share of the dispatch schedule's placement
         __shared__ int start[256], wave_total[4];
         const int64_t n = sa.n_groups, p = blockIdx.x;
@@ -358,19 +367,21 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
     const int q = blockIdx.x - (sa.cost ? sa.parts : 0);
     const int id = nodes[q];
     const int f0 = range[2 * q], f1 = range[2 * q + 1];
-    double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    double p1[4] = {0.0, 0.0, 0.0, 0.0};  // m, m x, m y, m z
+#pragma unroll 4
     for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
         const double *r = out.mom + (int64_t)leaves[f].block_node * kMom;
         const double mb = r[3];
-        m += mb;
-        sx += mb * r[0];
-        sy += mb * r[1];
-        sz += mb * r[2];
+        p1[0] += mb;
+        p1[1] += mb * r[0];
+        p1[2] += mb * r[1];
+        p1[3] += mb * r[2];
     }
-    const double M = block_sum256(m, red);
-    const double SX = block_sum256(sx, red), SY = block_sum256(sy, red), SZ = block_sum256(sz, red);
-    const double X = M > 0.0 ? SX / M : 0.0, Y = M > 0.0 ? SY / M : 0.0, Z = M > 0.0 ? SZ / M : 0.0;
+    block_sums256(p1, red);
+    const double M = p1[0];
+    const double X = M > 0.0 ? p1[1] / M : 0.0, Y = M > 0.0 ? p1[2] / M : 0.0, Z = M > 0.0 ? p1[3] / M : 0.0;
     double qa[6] = {0, 0, 0, 0, 0, 0}, sa_ = 0.0;
+#pragma unroll 4
     for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
         const int bn = leaves[f].block_node;
         const double *r = out.mom + (int64_t)bn * kMom;
@@ -385,10 +396,9 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
         qa[4] += r[8] + mb * (3.0 * dx * dz);
         qa[5] += r[9] + mb * (3.0 * dy * dz);
     }
-    double Q[6];
-    for (int k = 0; k < 6; k++) Q[k] = block_sum256(qa[k], red);
-    const double S = block_sum256(sa_, red);
-    if (threadIdx.x == 0) store_node(out, id, M, X, Y, Z, Q, S, geom + 4 * (int64_t)id, child_arr[id], 0);
+    double p2[7] = {qa[0], qa[1], qa[2], qa[3], qa[4], qa[5], sa_};
+    block_sums256(p2, red);
+    if (threadIdx.x == 0) store_node(out, id, M, X, Y, Z, p2, p2[6], geom + 4 * (int64_t)id, child_arr[id], 0);
 }
 
 hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int fixed_epoch,
