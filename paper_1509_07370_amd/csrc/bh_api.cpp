@@ -231,6 +231,7 @@ int bh_moments_destroy(bh_moments *m) {
     if (m->grid && m->grid->ctx && m->grid->ctx->device >= 0) (void)hipSetDevice(m->grid->ctx->device);
     hfree(m->d_mom);
     hfree(m->d_s);
+    hfree(m->d_brow);
     hfree(m->d_w32);
     hfree(m->d_w64);
     hfree(m->d_f32);
@@ -259,6 +260,7 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
         const int64_t nn = g->topo.n_nodes, nc = g->n_cells;
         hipError_t e;
         if ((e = dalloc(&m->d_mom, (size_t)nn * bh::kMom)) != hipSuccess || (e = dalloc(&m->d_s, (size_t)nn)) != hipSuccess ||
+            (e = dalloc(&m->d_brow, g->topo.leaves.size() * bh::kBlockRow)) != hipSuccess ||
             (e = dalloc(&m->d_w32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_w64, (size_t)nn)) != hipSuccess ||
             (e = dalloc(&m->d_f32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_cell64, (size_t)nc)) != hipSuccess ||
             (e = dalloc(&m->d_cell32, (size_t)nc)) != hipSuccess || (e = dalloc(&m->d_flags, 2)) != hipSuccess ||

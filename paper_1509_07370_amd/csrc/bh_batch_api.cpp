@@ -180,6 +180,8 @@ int bh_batch_create(bh_ctx *ctx, bh_batch **out, int n, bh_grid *const *grids) {
         const int64_t nn = grids[k]->topo.n_nodes, nc = grids[k]->n_cells;
         if ((e = hipMalloc((void **)&m->d_mom, nn * bh::kMom * sizeof(double))) != hipSuccess ||
             (e = hipMalloc((void **)&m->d_s, nn * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void **)&m->d_brow, grids[k]->topo.leaves.size() * bh::kBlockRow * sizeof(double))) !=
+                hipSuccess ||
             (e = hipMalloc((void **)&m->d_w32, nn * sizeof(bh::WalkRec32))) != hipSuccess ||
             (e = hipMalloc((void **)&m->d_w64, nn * sizeof(bh::WalkRec64))) != hipSuccess ||
             (e = hipMalloc((void **)&m->d_f32, nn * sizeof(bh::FarRec32))) != hipSuccess ||

@@ -126,6 +126,7 @@ struct bh_ctx {
 };
 
 namespace bh {
+constexpr int kBlockRow = 12;  // leaf-ordered copy of a block node's row: X Y Z M Q[6] S, pad
 constexpr int kEwaldValues = 20;  // D, gradient (3), Hessian (6), third derivatives (10)
 // The walks' table points, dimensionless: D L and gradient L^2, then Hessian
 // L^3 and third derivatives L^4 at half the precision.  fp32 walks: 4 fp32 +
@@ -166,6 +167,7 @@ struct bh_moments {
     const bh_grid *grid = nullptr;
     double *d_mom = nullptr;              // [n_nodes][kMom]
     double *d_s = nullptr;                // [n_nodes] sum m |r - X|^2
+    double *d_brow = nullptr;             // [n_leaf][kBlockRow] each leaf block node's X Y Z M Q[6] S, leaf order
     bh::WalkRec32 *d_w32 = nullptr;
     bh::WalkRec64 *d_w64 = nullptr;
     bh::FarRec32 *d_f32 = nullptr;

@@ -29,12 +29,14 @@ struct MomOut {
     WalkRec32 *w32;
     WalkRec64 *w64;
     FarRec32 *f32;
-    double *s;  // [n] sum m |r - X|^2
+    double *s;     // [n] sum m |r - X|^2
+    double *brow;  // [n_leaf][kBlockRow] leaf-ordered copies of the block nodes' rows
 };
 
-// Write every derived record of node `id` from its fp64 moments.
+// Write every derived record of node `id` from its fp64 moments (and, for a
+// leaf block node, the copy of its row at leaf ordinal `leaf`).
 __device__ void store_node(const MomOut &o, int id, double M, double X, double Y, double Z, const double *Q, double S,
-                           const double *geom, int child, int sflags, double mmax = 0.0) {
+                           const double *geom, int child, int sflags, double mmax = 0.0, int leaf = -1) {
 #pragma clang fp contract(off)
     double cx = geom[0], cy = geom[1], cz = geom[2], l = geom[3];
     double q[6];
@@ -63,6 +65,16 @@ __device__ void store_node(const MomOut &o, int id, double M, double X, double Y
     for (int c = 0; c < 6; c++) mo[4 + c] = q[c];
     mo[10] = delta;
     mo[11] = mmax;
+    if (leaf >= 0) {
+        double *b = o.brow + (int64_t)leaf * kBlockRow;
+        b[0] = X;
+        b[1] = Y;
+        b[2] = Z;
+        b[3] = M;
+        for (int c = 0; c < 6; c++) b[4 + c] = q[c];
+        b[10] = S;
+        b[11] = 0.0;
+    }
     WalkRec32 w;
     w.x = (float)X;
     w.y = (float)Y;
@@ -320,7 +332,7 @@ __global__ __launch_bounds__(512) void moments_leaf_kernel(const double *__restr
                   __shfl(S * e, src, 64), BM, BX, BY, BZ, BQ, BS);
     if (t != 0) return;
     const int node = L.block_node;
-    store_node(out, node, BM, BX, BY, BZ, BQ, BS, geom + 4 * (int64_t)node, child_arr[node], 0);
+    store_node(out, node, BM, BX, BY, BZ, BQ, BS, geom + 4 * (int64_t)node, child_arr[node], 0, 0.0, f);
 }
 
 // N block-wide sums of one double per thread (256 threads) at once, each in
@@ -349,10 +361,10 @@ __device__ __forceinline__ void block_sums256(double (&v)[N], double (*red)[4]) 
 // the leaf blocks below it -- a contiguous range of leaf ordinals -- combined
 // directly (mass and centre of mass, then the quadrupole about it by the
 // parallel-axis rule), so no node waits for its children.  The leaf blocks'
-// rows come from moments_leaf_kernel.
+// rows are the leaf-ordered copies moments_leaf_kernel writes (one load per
+// row, no lookup of the block's node id).
 __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__restrict__ nodes,
                                                             const int32_t *__restrict__ range,
-                                                            const LeafInfo *__restrict__ leaves,
                                                             const double *__restrict__ geom,
                                                             const int32_t *__restrict__ child_arr, MomOut out,
                                                             SchedArgs sa) {
@@ -370,7 +382,7 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
     double p1[4] = {0.0, 0.0, 0.0, 0.0};  // m, m x, m y, m z
 #pragma unroll 4
     for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
-        const double *r = out.mom + (int64_t)leaves[f].block_node * kMom;
+        const double *r = out.brow + (int64_t)f * kBlockRow;
         const double mb = r[3];
         p1[0] += mb;
         p1[1] += mb * r[0];
@@ -383,12 +395,11 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
     double qa[6] = {0, 0, 0, 0, 0, 0}, sa_ = 0.0;
 #pragma unroll 4
     for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
-        const int bn = leaves[f].block_node;
-        const double *r = out.mom + (int64_t)bn * kMom;
+        const double *r = out.brow + (int64_t)f * kBlockRow;
         const double mb = r[3];
         const double dx = r[0] - X, dy = r[1] - Y, dz = r[2] - Z;
         const double r2 = dx * dx + dy * dy + dz * dz;
-        sa_ += out.s[bn] + mb * r2;
+        sa_ += r[10] + mb * r2;
         qa[0] += r[4] + mb * (3.0 * dx * dx - r2);
         qa[1] += r[5] + mb * (3.0 * dy * dy - r2);
         qa[2] += r[6] + mb * (3.0 * dz * dz - r2);
@@ -403,7 +414,7 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
 
 hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hipStream_t s, int fixed_epoch,
                           bool schedule) {
-    MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32, m->d_s};
+    MomOut o{m->d_mom, m->d_w32, m->d_w64, m->d_f32, m->d_s, m->d_brow};
     const int nleaf = (int)g->topo.leaves.size();
     const int epoch = fixed_epoch > 0 ? fixed_epoch : ++m->mom_epoch;
     SchedArgs sa{};
@@ -420,7 +431,7 @@ hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hi
     const int64_t blocks = (int64_t)g->topo.combine_nodes.size() + sa.parts;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(moments_upper_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g->d_combine,
-                       g->d_combine_range, g->d_leaves, g->d_geom, g->d_child, o, sa);
+                       g->d_combine_range, g->d_geom, g->d_child, o, sa);
     return hipGetLastError();
 }
 
