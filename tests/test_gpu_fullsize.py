@@ -125,11 +125,20 @@ def test_benchmark_mesh_in_bench_configuration():
     ref, oc = t.solve_groups(groups, theta=1.0, tau=TAU[B.BH_FP32])
     got = phi.reshape(-1).cpu().numpy()[_morton_cells(groups)]
     _check_groups(got, ref, oc, 1e-5)
-    # learned theta as bench.py runs it: RMS gate against the exact direct sum
+    # learned theta as bench.py runs it (bh_learned_walk_potential): sampled groups vs the oracle's walk and sums
+    # given the same per-group thetas, then the RMS gate against the exact direct sum
     net = LT.ThetaNet.load(bh.ctx, os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz"))
-    feat = torch.empty((ng, 12), dtype=torch.float32, device="cuda")
     theta = torch.empty(ng, dtype=torch.float32, device="cuda")
-    LT.solve_learned(bh, rho, net, phi, feat, theta)
+    counts.zero_()
+    bh.build_moments(rho)
+    B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, B.BH_FP32, 1.0, phi, theta, counts)
+    bh.check()
+    c = counts.cpu().numpy()
+    groups = _sample_groups(ng, c, seed=4)
+    ref, oc = t.solve_groups(groups, theta=theta.cpu().numpy().astype(np.float64), tau=TAU[B.BH_FP32])
+    clean = oc[:, 3] == 0
+    assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
+    _check_groups(phi.reshape(-1).cpu().numpy()[_morton_cells(groups)], ref, oc, 1e-5)
     direct = LT.direct_potential(bh, rho)
     rel = ((phi - direct) / direct).reshape(-1)
     assert float(torch.sqrt((rel * rel).mean())) <= 1e-3
