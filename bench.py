@@ -505,14 +505,27 @@ def main():
             ms64 = timed(lambda: bh.solve_periodic(rho, table, th_p, precision=B.BH_FP64, phi=phi),
                          max(args.steps, 10))
             iso = next(s for s in sweep if s["precision"] == "fp32" and abs(s["theta"] - th_p) < 1e-9)
+            # the fp32 periodic kernel alone (events around each launch inside whole steps) and its work
+            pevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+            for e0, e1 in pevs:
+                bh.build_moments(rho)
+                e0.record(stream)
+                B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, table, th_p, None, B.BH_FP32, 1.0, phi, None)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            pk_ms = sum(e0.elapsed_time(e1) for e0, e1 in pevs) / len(pevs)
+            B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, table, th_p, None, B.BH_FP32, 1.0, phi, counts)
+            pc = counts.cpu().numpy().astype(np.int64)
             periodic = dict(theta=th_p, norm_rms_err=e_p, norm_rms_err_fp64=e64, ms_per_step=ms32,
+                            kernel="walk_potential_periodic_kernel<float, 4>", kernel_ms=pk_ms,
+                            far_interactions=int(64 * pc[:, 0].sum()), near_pairs=int((512 * pc[:, 1]).sum()),
                             mcells_per_s=ncells / ms32 / 1e3, fp64_ms_per_step=ms64,
                             fp64_mcells_per_s=ncells / ms64 / 1e3, isolated_ms_per_step_same_theta=iso["ms_per_step"],
                             table_points=EWALD_POINTS,
                             error_metric="||phi - phi_ref|| / ||phi_ref|| on a 1% sample (periodic potentials have "
                                          "zero mean), phi_ref the periodic direct sum (bh_direct_periodic)")
-            log("periodic box: theta %.2f, normalised rms %.2e; %.3f ms/step (%.1f Mcells/s) fp32, %.3f ms fp64"
-                % (th_p, e_p, ms32, periodic["mcells_per_s"], ms64))
+            log("periodic box: theta %.2f, normalised rms %.2e; %.3f ms/step (%.1f Mcells/s, kernel %.3f ms) fp32, "
+                "%.3f ms fp64" % (th_p, e_p, ms32, periodic["mcells_per_s"], pk_ms, ms64))
         B.bh_ewald_destroy(table)
 
     cpu = None
