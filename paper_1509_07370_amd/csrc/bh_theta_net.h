@@ -46,44 +46,40 @@ struct ThetaNetArgs {
     double box;
 };
 
-// Feature i of group (L, sub): its argument in fp64 from the node rows, then
-// one fp32 logarithm (order as in the features kernel).
-__device__ __forceinline__ float group_feature(const ThetaNetArgs &n, const LeafInfo &L, int sub, int i) {
+// The 12 features of group (L, sub): each argument in fp64 from the node rows,
+// then one fp32 logarithm (order as in the features kernel).  No branch
+// depends on the feature index, so every lane of a wavefront issues the same
+// loads (the group's, block's and block parent's node rows) together.
+__device__ __forceinline__ void group_features12(const ThetaNetArgs &n, const LeafInfo &L, int sub, float *f) {
     const int gnode = L.oct_first + sub;
-    if (i == 0) return 6.0f;  // log2(group cells)
-    if (i == 1 || i == 4 || i == 11) {
-        const double Mg = n.mom[(int64_t)gnode * kMom + 3];
-        if (i == 1) {
-            const double Mroot = n.mom[(int64_t)n.root * kMom + 3];
-            const double r = Mroot > 0.0 ? Mg / Mroot : 0.0;
-            return logf((float)(r > 1e-30 ? r : 1e-30));
-        }
-        if (i == 4) {
-            const double mmax = n.mom[(int64_t)gnode * kMom + 11];
-            return Mg > 0.0 ? logf((float)(mmax / (Mg / 64.0))) : 0.0f;
-        }
-        const double Mb = n.mom[(int64_t)L.block_node * kMom + 3];
-        const double r = Mb > 0.0 ? 8.0 * Mg / Mb : 0.0;
-        return Mb > 0.0 ? logf((float)(r > 1e-30 ? r : 1e-30)) : 0.0f;
-    }
-    if (i == 2) return logf((float)(4.0 * L.h / n.box));
-    if (i == 3) return rintf(log2f((float)(n.box / ((double)n.nbase * kNB * L.h))));
-    // 5..10: (delta/l, |Q|/(M l^2)) of group node, block, block's parent
-    const int a = (i - 5) >> 1;
     const int pn = n.parent[L.block_node];
-    const int node = a == 0 ? gnode : (a == 1 ? L.block_node : (pn >= 0 ? pn : L.block_node));
-    const double *r = n.mom + (int64_t)node * kMom;
-    const double l = n.geom[4 * (int64_t)node + 3];
-    double arg;
-    if (((i - 5) & 1) == 0) {
-        arg = r[10] / l + 1e-6;
-    } else {
+    const int node[3] = {gnode, L.block_node, pn >= 0 ? pn : L.block_node};
+    const double Mg = n.mom[(int64_t)gnode * kMom + 3];
+    const double Mroot = n.mom[(int64_t)n.root * kMom + 3];
+    const double mmax = n.mom[(int64_t)gnode * kMom + 11];
+    const double Mb = n.mom[(int64_t)L.block_node * kMom + 3];
+    f[0] = 6.0f;  // log2(group cells)
+    {
+        const double r = Mroot > 0.0 ? Mg / Mroot : 0.0;
+        f[1] = logf((float)(r > 1e-30 ? r : 1e-30));
+    }
+    f[2] = logf((float)(4.0 * L.h / n.box));
+    f[3] = rintf(log2f((float)(n.box / ((double)n.nbase * kNB * L.h))));
+    f[4] = Mg > 0.0 ? logf((float)(mmax / (Mg / 64.0))) : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {  // (delta/l, |Q|/(M l^2)) of group node, block, block's parent
+        const double *r = n.mom + (int64_t)node[a] * kMom;
+        const double l = n.geom[4 * (int64_t)node[a] + 3];
+        f[5 + 2 * a] = logf((float)(r[10] / l + 1e-6));
         const double M = r[3];
         const double qf =
             sqrt(r[4] * r[4] + r[5] * r[5] + r[6] * r[6] + 2.0 * (r[7] * r[7] + r[8] * r[8] + r[9] * r[9]));
-        arg = (M > 0.0 ? qf / (M * l * l) : 0.0) + 1e-6;
+        f[6 + 2 * a] = logf((float)((M > 0.0 ? qf / (M * l * l) : 0.0) + 1e-6));
     }
-    return logf((float)arg);
+    {
+        const double r = Mb > 0.0 ? 8.0 * Mg / Mb : 0.0;
+        f[11] = Mb > 0.0 ? logf((float)(r > 1e-30 ? r : 1e-30)) : 0.0f;
+    }
 }
 
 // theta of up to 16 groups g0 .. g0 + cnt - 1 on one wavefront, the network
@@ -109,16 +105,21 @@ __device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_
 
 __device__ inline float groups_theta16(const ThetaNetArgs &n, const LeafInfo *leaves, int64_t g0, int cnt, int lane) {
     const int c = lane & 15, q = lane >> 4;
-    // inputs 3q .. 3q + 2 of group g0 + c, standardised and rounded to bf16
+    // inputs 3q .. 3q + 2 of group g0 + c, standardised and rounded to bf16 (every lane derives all 12 and
+    // keeps its three: no divergence between the lanes of a group)
     bh_bf16x4 x = {0, 0, 0, 0};
     if (c < cnt) {
         const int64_t g = g0 + c;
         const LeafInfo L = leaves[g >> 3];
-        const int sub = (int)(g & 7);
+        float fv[BH_MLP_INPUTS];
+        group_features12(n, L, (int)(g & 7), fv);
         const int f = 3 * q;
-        x[0] = bf16_bits((group_feature(n, L, sub, f) - n.mean[f]) * n.scale[f]);
-        x[1] = bf16_bits((group_feature(n, L, sub, f + 1) - n.mean[f + 1]) * n.scale[f + 1]);
-        x[2] = bf16_bits((group_feature(n, L, sub, f + 2) - n.mean[f + 2]) * n.scale[f + 2]);
+        const float a0 = q == 0 ? fv[0] : (q == 1 ? fv[3] : (q == 2 ? fv[6] : fv[9]));
+        const float a1 = q == 0 ? fv[1] : (q == 1 ? fv[4] : (q == 2 ? fv[7] : fv[10]));
+        const float a2 = q == 0 ? fv[2] : (q == 1 ? fv[5] : (q == 2 ? fv[8] : fv[11]));
+        x[0] = bf16_bits((a0 - n.mean[f]) * n.scale[f]);
+        x[1] = bf16_bits((a1 - n.mean[f + 1]) * n.scale[f + 1]);
+        x[2] = bf16_bits((a2 - n.mean[f + 2]) * n.scale[f + 2]);
     }
     const short *w = reinterpret_cast<const short *>(n.w);
     // layer 1
