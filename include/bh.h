@@ -21,7 +21,10 @@
  *  - Pointers named *_dev are device pointers on the context's GPU; every
  *    other pointer is host memory.  The caller owns all buffers it passes and
  *    the HIP stream; the library owns its opaque handles and their device
- *    workspaces, which bh_*_destroy releases.
+ *    workspaces, which bh_*_destroy releases.  Handles may be destroyed in
+ *    any order, also after the context or grid they were made with (each
+ *    frees on the device it was created on); no other call may use a handle
+ *    whose context or grid is gone.
  *  - Work is enqueued on the context's stream and is asynchronous unless the
  *    description says that the call synchronises.
  *  - Cell-field layout ("caller layout"): fp64 [n_leaf][8][8][8] indexed

@@ -131,6 +131,7 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
     bh_grid *g = new (std::nothrow) bh_grid();
     if (!g) return fail(ctx, BH_ENOMEM, "host allocation of the grid");
     g->ctx = ctx;
+    g->device = ctx->device;
     std::string why;
     try {
         why = bh::build_topology(g->topo, n_blocks, level, lo, parent, child, is_leaf, box_lo, box_size);
@@ -197,8 +198,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
 
 int bh_grid_destroy(bh_grid *g) {
     if (!g) return BH_OK;
-    if (g->ctx && g->ctx->device >= 0) {
-        (void)hipSetDevice(g->ctx->device);
+    if (g->device >= 0) {
+        (void)hipSetDevice(g->device);
         free_grid_device(g);
     }
     delete g;
@@ -228,7 +229,7 @@ int bh_grid_node_keys(const bh_grid *g, uint64_t *keys) {
 
 int bh_moments_destroy(bh_moments *m) {
     if (!m) return BH_OK;
-    if (m->grid && m->grid->ctx && m->grid->ctx->device >= 0) (void)hipSetDevice(m->grid->ctx->device);
+    if (m->device >= 0) (void)hipSetDevice(m->device);
     hfree(m->d_mom);
     hfree(m->d_s);
     hfree(m->d_brow);
@@ -257,6 +258,7 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
         m = new (std::nothrow) bh_moments();
         if (!m) return fail(ctx, BH_ENOMEM, "host allocation of the moments handle");
         m->grid = g;
+        m->device = g->device;
         const int64_t nn = g->topo.n_nodes, nc = g->n_cells;
         hipError_t e;
         if ((e = dalloc(&m->d_mom, (size_t)nn * bh::kMom)) != hipSuccess || (e = dalloc(&m->d_s, (size_t)nn)) != hipSuccess ||
@@ -326,7 +328,7 @@ int bh_moments_export(bh_ctx *ctx, const bh_moments *m, double *M, double *X, do
 
 int bh_lists_destroy(bh_lists *L) {
     if (!L) return BH_OK;
-    if (L->grid && L->grid->ctx && L->grid->ctx->device >= 0) (void)hipSetDevice(L->grid->ctx->device);
+    if (L->device >= 0) (void)hipSetDevice(L->device);
     hfree(L->d_far);
     hfree(L->d_near);
     hfree(L->d_far_off);
@@ -355,6 +357,7 @@ int bh_walk(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, double theta, co
         L = new (std::nothrow) bh_lists();
         if (!L) return fail(ctx, BH_ENOMEM, "host allocation of the lists handle");
         L->grid = g;
+        L->device = g->device;
         const int nblocks = (int)((ng + 1023) / 1024);
         hipError_t e;
         if ((e = dalloc(&L->d_far_off, (size_t)ng + 1)) != hipSuccess ||
@@ -563,6 +566,7 @@ int bh_ewald_create(bh_ctx *ctx, double box_size, int n_points, bh_ewald **out) 
     bh_ewald *e = new (std::nothrow) bh_ewald();
     if (!e) return fail(ctx, BH_ENOMEM, "host allocation of the table handle");
     e->ctx = ctx;
+    e->device = ctx->device;
     e->L = box_size;
     e->n = n_points;
     e->sp = 0.5 * box_size / (n_points - 1);
@@ -584,7 +588,7 @@ int bh_ewald_create(bh_ctx *ctx, double box_size, int n_points, bh_ewald **out) 
 
 int bh_ewald_destroy(bh_ewald *e) {
     if (!e) return BH_OK;
-    if (e->ctx && e->ctx->device >= 0) (void)hipSetDevice(e->ctx->device);
+    if (e->device >= 0) (void)hipSetDevice(e->device);
     hfree(e->d_t64);
     hfree(e->d_t64c);
     hfree(e->d_t32);

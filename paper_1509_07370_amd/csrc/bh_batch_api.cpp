@@ -13,6 +13,7 @@
 
 struct bh_batch {
     bh_ctx *ctx = nullptr;
+    int device = -1;  // for destroy, which does not touch the context
     std::vector<const bh_grid *> grids;
     std::vector<bh_moments *> moments;
     std::vector<int64_t> group_base;      // first queue slot of each grid, size n + 1
@@ -122,7 +123,7 @@ extern "C" {
 
 int bh_batch_destroy(bh_batch *b) {
     if (!b) return BH_OK;
-    if (b->ctx && b->ctx->device >= 0) (void)hipSetDevice(b->ctx->device);
+    if (b->device >= 0) (void)hipSetDevice(b->device);
     drop_graph(b);
     for (auto *m : b->moments) bh_moments_destroy(m);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
@@ -143,6 +144,7 @@ int bh_batch_create(bh_ctx *ctx, bh_batch **out, int n, bh_grid *const *grids) {
     bh_batch *b = new (std::nothrow) bh_batch();
     if (!b) return fail(ctx, BH_ENOMEM, "host allocation of the batch");
     b->ctx = ctx;
+    b->device = ctx->device;
     b->group_base.assign(1, 0);
     for (int k = 0; k < n; k++) {
         if (!grids[k] || grids[k]->ctx != ctx) {
@@ -176,6 +178,7 @@ int bh_batch_create(bh_ctx *ctx, bh_batch **out, int n, bh_grid *const *grids) {
             return fail(ctx, BH_ENOMEM, "host allocation of the moments");
         }
         m->grid = grids[k];
+        m->device = ctx->device;
         b->moments.push_back(m);
         const int64_t nn = grids[k]->topo.n_nodes, nc = grids[k]->n_cells;
         if ((e = hipMalloc((void **)&m->d_mom, nn * bh::kMom * sizeof(double))) != hipSuccess ||

@@ -136,8 +136,11 @@ constexpr int kEwaldCompactFloats = 12;
 constexpr int kEwaldCompactDoubles = 12;
 }
 
+// Every handle records the device it was created on: its destroy call frees
+// on that device without touching the context, which may already be gone.
 struct bh_ewald {
     bh_ctx *ctx = nullptr;
+    int device = -1;
     double L = 0.0;   // box side
     int n = 0;        // points per axis over [0, L/2]
     double sp = 0.0;  // spacing (L/2) / (n - 1)
@@ -148,6 +151,7 @@ struct bh_ewald {
 
 struct bh_grid {
     bh_ctx *ctx = nullptr;
+    int device = -1;
     bh::Topology topo;
     int group_cells = bh::kGroupCells;
     int64_t n_groups = 0;
@@ -165,6 +169,7 @@ struct bh_grid {
 
 struct bh_moments {
     const bh_grid *grid = nullptr;
+    int device = -1;
     double *d_mom = nullptr;              // [n_nodes][kMom]
     double *d_s = nullptr;                // [n_nodes] sum m |r - X|^2
     double *d_brow = nullptr;             // [n_leaf][kBlockRow] each leaf block node's X Y Z M Q[6] S, leaf order
@@ -192,6 +197,7 @@ struct bh_moments {
 
 struct bh_lists {
     const bh_grid *grid = nullptr;
+    int device = -1;
     int64_t cap_far = 0, cap_near = 0;
     int64_t n_far = 0, n_near = 0;
     int32_t *d_far = nullptr, *d_near = nullptr;         // node ids

@@ -21,6 +21,7 @@ hipError_t launch_group_rms(const bh_grid *g, const double *phi, const double *r
 
 struct bh_mlp {
     bh_ctx *ctx = nullptr;
+    int device = -1;  // for destroy, which does not touch the context
     float *d_params = nullptr;   // [kMlpParams]
     uint16_t *d_bf16 = nullptr;  // bf16 copy of the parameters
     float *d_mean = nullptr, *d_scale = nullptr;  // [kMlpIn]

@@ -61,7 +61,7 @@ int bh_group_rms_error(bh_ctx *ctx, const bh_grid *g, const double *phi, const d
 
 int bh_mlp_destroy(bh_mlp *net) {
     if (!net) return BH_OK;
-    if (net->ctx && net->ctx->device >= 0) (void)hipSetDevice(net->ctx->device);
+    if (net->device >= 0) (void)hipSetDevice(net->device);
     hfree(net->d_params);
     hfree(net->d_bf16);
     hfree(net->d_mean);
@@ -85,6 +85,7 @@ int bh_mlp_create(bh_ctx *ctx, bh_mlp **out, const float *params, const float *m
     bh_mlp *n = new (std::nothrow) bh_mlp();
     if (!n) return fail(ctx, BH_ENOMEM, "host allocation of the network");
     n->ctx = ctx;
+    n->device = ctx->device;
     const size_t P = bh::kMlpParams;
     hipError_t e;
     if ((e = hipMalloc((void **)&n->d_params, P * sizeof(float))) != hipSuccess ||
