@@ -1,0 +1,45 @@
+"""Derived error bounds of the periodic walk and sum against the oracle's
+exact Ewald sums (shared by the periodic GPU tests).  Box side 1, table of
+N_TABLE^3 points on [0, 1/2]^3 (spacing sp = 1/64).
+
+* Table: D by its third-order expansion, remainder |D^(4)| |delta|^4 / 24,
+  the Hessian by its first-order expansion, remainder |D^(4)| |delta|^2 / 2,
+  with |D^(4)| <= 24 / (L/2)^5 (the nearest image singularity is at least L/2
+  away; the smooth rest of D adds far less) and |delta| <= sqrt(3) sp / 2.
+* Storage: the walks read compact rows with H L^3 and T L^4 at half the
+  walk's precision (fp32 in the fp64 rows, fp16 in the fp32 rows; unit
+  roundoff eps).  With |u_a| <= sp / (2L) per axis and Hs, Ts the table's
+  largest |H| L^3 and |T| L^4, the rounding changes D by at most
+  eps (Hs (3u)^2 / 2 + Ts (3u)^3 / 6) / L per unit mass and the Hessian by at
+  most eps (Hs + 3u Ts) / L^3 per unit of sum_ab |Q_ab| / 6.
+"""
+import numpy as np
+
+N_TABLE = 33
+D4 = 24.0 * 2.0 ** 5
+DELTA = np.sqrt(3.0) / 64 / 2
+TABLE_ERR = D4 * DELTA ** 4 / 24   # per unit mass, about 1e-6
+HESS_ERR = D4 * DELTA ** 2 / 2     # per unit of sum_ab |Q_ab| / 6, about 0.07
+EPS_FP32_ROWS = 2.0 ** -11         # fp16 storage in the fp32 walks' rows
+EPS_FP64_ROWS = 2.0 ** -24         # fp32 storage in the fp64 rows
+
+
+def storage_terms(table_values, L, eps):
+    """(per unit mass, per unit of sum |Q| / 6) changes from the rows' storage;
+    table_values: the fp64 export [n, n, n, 20]."""
+    v = table_values.reshape(-1, 20)
+    Hs = np.max(np.abs(v[:, 4:10])) * L ** 3
+    Ts = np.max(np.abs(v[:, 10:20])) * L ** 4
+    u3 = 3 * (0.5 * L / (N_TABLE - 1)) / (2 * L)
+    return eps * (0.5 * Hs * u3 ** 2 + Ts * u3 ** 3 / 6) / L, eps * (Hs + u3 * Ts) / L ** 3
+
+
+def walk_tolerance(masses_sum, qsum, L, storage, fp32):
+    """Per-group bound: table (D and, weighted by the group's far-node sum |Q| / 6, the Hessian), storage, and in
+    fp32 the rounding of O(1) terms (relative 1e-6 of sum m / d over the box, about 3 sum m / L) that cancel to the
+    small periodic potential."""
+    ds, hs = storage
+    tol = TABLE_ERR * masses_sum / L + HESS_ERR * qsum + ds * masses_sum + hs * qsum
+    if fp32:
+        tol = tol + 3e-6 * 3 * masses_sum / L
+    return tol

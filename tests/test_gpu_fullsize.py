@@ -12,6 +12,7 @@ import pytest
 
 from amr_inputs import cloud_core, maclaurin_spheroid
 from oracle import OracleTree
+from periodic_bounds import EPS_FP32_ROWS, N_TABLE, storage_terms, walk_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -179,4 +180,38 @@ def test_benchmark_mesh_accelerations():
     rms = float(torch.sqrt((rel * rel).mean()))
     print("[accel] theta 1.0 fp32: rms relative acceleration error %.3e, max %.3e" % (rms, float(rel.max())))
     assert rms <= 1e-2
+    bh.close()
+
+
+def test_benchmark_mesh_periodic_in_bench_configuration():
+    """bh_walk_potential_periodic as bench.py times it (theta 1, fp32, 33^3 table) on the benchmark mesh: sampled
+    groups (random and the heaviest) against the oracle's O10 walk and sums, counts equal outside marginal groups,
+    potentials within the derived bound."""
+    g = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
+    assert g.box_size == 1.0
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    table = B.bh_ewald_create(bh.ctx, g.box_size, N_TABLE)
+    phi = torch.empty_like(rho)
+    counts = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, table, 1.0, None, B.BH_FP32, 1.0, phi, counts)
+    bh.check()
+    c = counts.cpu().numpy()
+    heavy = np.argsort(c[:, 0] * 35 + c[:, 1] * 88)[-2:]
+    groups = np.unique(np.concatenate([np.random.default_rng(5).choice(ng, 4, replace=False), heavy]))
+    t = OracleTree(g)
+    ref, oc, qs = t.solve_groups_periodic(groups, theta=1.0, tau=TAU[B.BH_FP32], with_qsum=True)
+    clean = oc[:, 3] == 0
+    assert clean.sum() >= 3
+    assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
+    got = phi.reshape(-1).cpu().numpy()[_morton_cells(groups)]
+    _, _, _, m = t.cells()
+    storage = storage_terms(B.bh_ewald_export(bh.ctx, table, N_TABLE), g.box_size, EPS_FP32_ROWS)
+    tol = walk_tolerance(m.sum(), qs[clean], g.box_size, storage, True)
+    ratio = np.max(np.abs(got[clean] - ref[clean]), axis=1) / tol
+    print("[periodic full size] %d groups, largest diff/tolerance %.2e" % (clean.sum(), ratio.max()))
+    assert np.all(ratio <= 1.0), ratio
+    B.bh_ewald_destroy(table)
     bh.close()

@@ -27,6 +27,7 @@ import pytest
 from amr_inputs import maclaurin_spheroid, random_amr
 from oracle import OracleTree
 from oracle.oracle import ewald_hessian
+from periodic_bounds import EPS_FP32_ROWS, EPS_FP64_ROWS, N_TABLE, TABLE_ERR, storage_terms, walk_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -37,33 +38,8 @@ if not torch.cuda.is_available():
 from paper_1509_07370_amd import binding as B  # noqa: E402
 from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
 
-N_TABLE = 33
-# Table errors, box 1, spacing sp = 1/64, lookup offset |delta| <= sqrt(3) sp / 2:
-# D by its third-order expansion, remainder |D^(4)| |delta|^4 / 24, and the
-# Hessian by its first-order expansion, remainder |D^(4)| |delta|^2 / 2, with
-# |D^(4)| <= 24 / (L/2)^5 (the nearest image singularity is at least L/2
-# away; the smooth rest of D adds far less).
-D4 = 24.0 * 2.0 ** 5
-DELTA = np.sqrt(3.0) / 64 / 2
-TABLE_ERR = D4 * DELTA ** 4 / 24   # per unit mass, about 1e-6
-HESS_ERR = D4 * DELTA ** 2 / 2     # per unit of sum_ab |Q_ab| / 6, about 0.07
 TAU = {B.BH_FP64: 1e-12, B.BH_FP32: 2e-6}
-# The walks and the GPU direct sum read compact table rows: H L^3 and T L^4
-# stored in fp32 for the fp64 path, fp16 for the fp32 path (unit roundoff
-# eps).  With |u_a| <= sp / (2L) per axis (offsets in units of L) and Hs, Ts
-# the table's largest |H| L^3 and |T| L^4, the rounding changes
-#   D by at most eps (Hs (3u)^2 / 2 + Ts (3u)^3 / 6) / L per unit mass,
-#   the Hessian by at most eps (Hs + 3u Ts) / L^3 per unit of sum_ab |Q_ab| / 6.
-STORE_EPS = {B.BH_FP64: 2.0 ** -24, B.BH_FP32: 2.0 ** -11}
-
-
-def storage_terms(ctx, table, L, precision):
-    v = B.bh_ewald_export(ctx, table, N_TABLE).reshape(-1, 20)
-    Hs = np.max(np.abs(v[:, 4:10])) * L ** 3
-    Ts = np.max(np.abs(v[:, 10:20])) * L ** 4
-    u3 = 3 * (0.5 * L / (N_TABLE - 1)) / (2 * L)
-    eps = STORE_EPS[precision]
-    return eps * (0.5 * Hs * u3 ** 2 + Ts * u3 ** 3 / 6) / L, eps * (Hs + u3 * Ts) / L ** 3
+STORE_EPS = {B.BH_FP64: EPS_FP64_ROWS, B.BH_FP32: EPS_FP32_ROWS}
 
 GRIDS = {
     "random_amr": lambda: random_amr(61, nbase=2, max_level=1, p_refine=0.3, zero_fraction=0.1),
@@ -146,7 +122,7 @@ def test_periodic_direct_equals_oracle(name):
     ref = t.direct_periodic(tg)
     out = bh.direct_periodic(table, torch.tensor(tg, device="cuda")).cpu().numpy()
     _, _, _, m = t.cells()
-    d32, _ = storage_terms(bh.ctx, table, g.box_size, B.BH_FP64)
+    d32, _ = storage_terms(B.bh_ewald_export(bh.ctx, table, N_TABLE), g.box_size, EPS_FP64_ROWS)
     assert np.max(np.abs(out - ref)) <= (TABLE_ERR / g.box_size + d32) * m.sum()
 
 
@@ -185,10 +161,8 @@ def test_periodic_walk_equals_oracle(name, precision, theta):
     # the table's errors (D per unit mass, the Hessian per unit of the group's far-node sum_ab |Q_ab| / 6),
     # and in fp32 the rounding of O(1) terms (relative 1e-6 of sum m / d over the box, about 3 m.sum() / L)
     # that cancel to the small periodic potential, and the storage of the table rows; per group
-    ds, hs = storage_terms(bh.ctx, table, g.box_size, precision)
-    tol_g = TABLE_ERR * m.sum() / g.box_size + HESS_ERR * qs[ok] + ds * m.sum() + hs * qs[ok]
-    if precision == B.BH_FP32:
-        tol_g = tol_g + 3e-6 * 3 * m.sum() / g.box_size
+    storage = storage_terms(B.bh_ewald_export(bh.ctx, table, N_TABLE), g.box_size, STORE_EPS[precision])
+    tol_g = walk_tolerance(m.sum(), qs[ok], g.box_size, storage, precision == B.BH_FP32)
     ratio = np.max(np.abs(p[ok] - ref[ok]), axis=1) / tol_g
     print("[periodic] %s precision %d theta %.1f: max diff %.2e, largest diff/tolerance %.2e (RMS potential %.2e)"
           % (name, precision, theta, np.max(np.abs(p[ok] - ref[ok])), ratio.max(), scale))
