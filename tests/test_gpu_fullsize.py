@@ -215,3 +215,40 @@ def test_benchmark_mesh_periodic_in_bench_configuration():
     assert np.all(ratio <= 1.0), ratio
     B.bh_ewald_destroy(table)
     bh.close()
+
+
+def test_batched_workload_in_bench_configuration():
+    """The 64-grid Plummer-mix batch as bench.py --workload batched runs it (theta 0.8, fp32, one persistent launch
+    replayed from a captured graph under a tuned configuration): sampled groups of the smallest and the largest grid
+    against the oracle's walk and sums, counts equal outside marginal groups."""
+    from amr_inputs import plummer_mix
+
+    grids = [plummer_mix(7370 + k) for k in range(64)]
+    ctx = B.bh_ctx_create(0)
+    handles = [B.bh_grid_create_from(ctx, g) for g in grids]
+    batch = B.bh_batch_create(ctx, handles)
+    rho = [torch.tensor(g.rho, device="cuda") for g in grids]
+    phi = [torch.full_like(r, float("nan")) for r in rho]
+    B.bh_batch_configure(ctx, batch, order=B.BH_ORDER_NATURAL, workgroups_per_cu=6, waves_per_simd=6, stack_limit=0)
+    B.bh_batch_capture(ctx, batch, rho, phi, 0.8, None, B.BH_FP32, 1.0)
+    for _ in range(2):
+        B.bh_batch_replay(ctx, batch)
+    B.bh_batch_check(ctx, batch)
+    counts = B.bh_batch_counts(ctx, batch)
+    sizes = [g.ncells for g in grids]
+    assert sum(sizes) > 80_000_000
+    base = np.concatenate([[0], np.cumsum([n // 64 for n in sizes])])
+    for k in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        ng = sizes[k] // 64
+        c = counts[base[k]:base[k + 1]]
+        heavy = np.argsort(c[:, 0] * 35 + c[:, 1] * 88)[-2:]
+        groups = np.unique(np.concatenate([np.random.default_rng(k).choice(ng, 4, replace=False), heavy]))
+        t = OracleTree(grids[k])
+        ref, oc = t.solve_groups(groups, theta=0.8, tau=TAU[B.BH_FP32])
+        clean = oc[:, 3] == 0
+        assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
+        _check_groups(phi[k].reshape(-1).cpu().numpy()[_morton_cells(groups)], ref, oc, TOL[B.BH_FP32])
+    B.bh_batch_destroy(batch)
+    for h in handles:
+        B.bh_grid_destroy(h)
+    B.bh_ctx_destroy(ctx)
