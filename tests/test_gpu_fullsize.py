@@ -1,4 +1,6 @@
-"""Full-size checks: the 12.4M-cell cloud core and the 1.4M-cell benchmark mesh.
+"""Full-size checks: the 12.4M-cell cloud core, the 1.4M-cell benchmark mesh
+(learned theta, accelerations, periodic box, the paper's opening test and far
+field, each in the configuration bench.py times) and the 64-grid batch.
 
 The oracle re-solves a seeded sample of groups one by one (its own walk and
 sums) and the exact direct sum at sampled cells; a group may differ from the
@@ -252,3 +254,28 @@ def test_batched_workload_in_bench_configuration():
     for h in handles:
         B.bh_grid_destroy(h)
     B.bh_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("mac,order", [(B.BH_MAC_GROUP_BOX, 0), (B.BH_MAC_CELLS, 0), (B.BH_MAC_GROUP_BOX, 2)])
+def test_benchmark_mesh_paper_opening_test_and_far_field(mac, order):
+    """The bench's ablation on the benchmark mesh (fp32, theta 0.55, the largest theta of the grid meeting the gate
+    for the monopole variants): the paper's group-cube opening test and/or monopole far field, sampled groups
+    against the oracle's walk and sums with the same options."""
+    g = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    phi = torch.empty_like(rho)
+    counts = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, 0.55, None, B.BH_FP32, 1.0, phi, counts, mac=mac, order=order)
+    bh.check()
+    c = counts.cpu().numpy()
+    heavy = np.argsort(c[:, 0] * 35 + c[:, 1] * 88)[-2:]
+    groups = np.unique(np.concatenate([np.random.default_rng(11).choice(ng, 6, replace=False), heavy]))
+    t = OracleTree(g)
+    ref, oc = t.solve_groups(groups, theta=0.55, tau=TAU[B.BH_FP32], order=order, mac=mac)
+    clean = oc[:, 3] == 0
+    assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
+    _check_groups(phi.reshape(-1).cpu().numpy()[_morton_cells(groups)], ref, oc, TOL[B.BH_FP32])
+    bh.close()
