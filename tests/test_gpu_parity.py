@@ -212,6 +212,33 @@ def test_zero_density_gives_zero_potential():
         assert float(phi.abs().max()) == 0.0
         nf, nn = B.bh_lists_info(bh.lists)
         assert nf == 0 and nn == 0
+    # the fused walk, the learned-theta step, accelerations and the periodic box: zero as well, no node visited
+    import os
+    from paper_1509_07370_amd import learned_theta as LT
+    ng = bh.info["n_groups"]
+    counts = torch.full((ng, 2), -1, dtype=torch.int32, device="cuda")
+    phi = torch.full_like(rho, float("nan"))
+    acc = torch.full(tuple(rho.shape) + (3,), float("nan"), dtype=torch.float64, device="cuda")
+    net = LT.ThetaNet.load(bh.ctx, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                                "paper_1509_07370_amd", "data", "theta_mlp_1e-3.npz"))
+    table = B.bh_ewald_create(bh.ctx, g.box_size, 9)
+    bh.build_moments(rho)
+    for prec in (B.BH_FP64, B.BH_FP32):
+        runs = [lambda: B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, None, prec, 1.0, phi, counts),
+                lambda: B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, prec, 1.0, phi, None,
+                                                    counts),
+                lambda: B.bh_walk_accel(bh.ctx, bh.grid, bh.m, 0.5, None, prec, 1.0, phi, acc, counts),
+                lambda: B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, table, 0.5, None, prec, 1.0, phi, counts)]
+        for run in runs:
+            phi.fill_(float("nan"))
+            counts.fill_(-1)
+            run()
+            bh.check()
+            assert float(phi.abs().max()) == 0.0
+            assert int(counts.abs().max()) == 0
+        assert float(acc.abs().max()) == 0.0
+    B.bh_ewald_destroy(table)
+    net.close()
     bh.close()
 
 
