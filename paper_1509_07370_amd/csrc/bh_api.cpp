@@ -59,7 +59,9 @@ void free_grid_device(bh_grid *g) {
     hfree(g->d_combine);
     hfree(g->d_combine_range);
     hfree(g->d_parent);
+    hfree(g->d_leaf_parent);
     g->d_parent = nullptr;
+    g->d_leaf_parent = nullptr;
     g->d_geom = nullptr;
     g->d_child = g->d_flags = g->d_internal_of_canon = g->d_combine = nullptr;
     g->d_combine_range = nullptr;
@@ -157,6 +159,11 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
             return rc;
         }
         const auto &t = g->topo;
+        std::vector<int32_t> leaf_parent(t.leaves.size());
+        for (size_t f = 0; f < t.leaves.size(); f++) {
+            const int b = t.leaves[f].block_node, p = t.parent[b];
+            leaf_parent[f] = p >= 0 ? p : b;
+        }
         hipError_t e;
         if ((e = dalloc(&g->d_geom, t.geom.size())) != hipSuccess ||
             (e = dalloc(&g->d_child, t.child.size())) != hipSuccess ||
@@ -165,7 +172,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
             (e = dalloc(&g->d_internal_of_canon, t.internal_of_canon.size())) != hipSuccess ||
             (e = dalloc(&g->d_combine, t.combine_nodes.size())) != hipSuccess ||
             (e = dalloc(&g->d_combine_range, t.combine_range.size())) != hipSuccess ||
-            (e = dalloc(&g->d_parent, t.parent.size())) != hipSuccess) {
+            (e = dalloc(&g->d_parent, t.parent.size())) != hipSuccess ||
+            (e = dalloc(&g->d_leaf_parent, leaf_parent.size())) != hipSuccess) {
             free_grid_device(g);
             delete g;
             return hip_fail(ctx, e, "device allocation of the grid topology");
@@ -181,7 +189,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
                   {g->d_internal_of_canon, t.internal_of_canon.data(), t.internal_of_canon.size() * sizeof(int32_t)},
                   {g->d_combine, t.combine_nodes.data(), t.combine_nodes.size() * sizeof(int32_t)},
                   {g->d_combine_range, t.combine_range.data(), t.combine_range.size() * sizeof(int32_t)},
-                  {g->d_parent, t.parent.data(), t.parent.size() * sizeof(int32_t)}};
+                  {g->d_parent, t.parent.data(), t.parent.size() * sizeof(int32_t)},
+                  {g->d_leaf_parent, leaf_parent.data(), leaf_parent.size() * sizeof(int32_t)}};
         for (auto &u : up) {
             if (u.n == 0) continue;
             e = hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice);

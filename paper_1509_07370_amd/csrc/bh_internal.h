@@ -165,6 +165,7 @@ struct bh_grid {
     int32_t *d_combine = nullptr;
     int32_t *d_combine_range = nullptr;
     int32_t *d_parent = nullptr;         // [n_nodes]
+    int32_t *d_leaf_parent = nullptr;    // [n_leaf] parent node of each leaf block's node (itself at the root)
 };
 
 struct bh_moments {

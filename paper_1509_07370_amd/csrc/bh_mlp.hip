@@ -248,7 +248,7 @@ ThetaNetArgs theta_net_args(const bh_grid *g, const bh_moments *m, const bh_mlp 
     a.shift = shift;
     a.mom = m->d_mom;
     a.geom = g->d_geom;
-    a.parent = g->d_parent;
+    a.leaf_parent = g->d_leaf_parent;
     a.root = g->topo.root;
     a.nbase = g->topo.nbase;
     a.box = g->topo.box;

@@ -40,7 +40,7 @@ struct ThetaNetArgs {
     float shift;
     const double *mom;
     const double *geom;
-    const int32_t *parent;
+    const int32_t *leaf_parent;  // [n_leaf] parent node of the leaf block's node (the node itself at the root)
     int root;
     int nbase;
     double box;
@@ -49,11 +49,12 @@ struct ThetaNetArgs {
 // The 12 features of group (L, sub): each argument in fp64 from the node rows,
 // then one fp32 logarithm (order as in the features kernel).  No branch
 // depends on the feature index, so every lane of a wavefront issues the same
-// loads (the group's, block's and block parent's node rows) together.
-__device__ __forceinline__ void group_features12(const ThetaNetArgs &n, const LeafInfo &L, int sub, float *f) {
+// loads (the group's, block's and block parent's node rows) together; the
+// parent's id comes from a leaf-indexed array, loaded beside the leaf record.
+__device__ __forceinline__ void group_features12(const ThetaNetArgs &n, const LeafInfo &L, int leaf, int sub,
+                                                 float *f) {
     const int gnode = L.oct_first + sub;
-    const int pn = n.parent[L.block_node];
-    const int node[3] = {gnode, L.block_node, pn >= 0 ? pn : L.block_node};
+    const int node[3] = {gnode, L.block_node, n.leaf_parent[leaf]};
     const double Mg = n.mom[(int64_t)gnode * kMom + 3];
     const double Mroot = n.mom[(int64_t)n.root * kMom + 3];
     const double mmax = n.mom[(int64_t)gnode * kMom + 11];
@@ -112,7 +113,7 @@ __device__ inline float groups_theta16(const ThetaNetArgs &n, const LeafInfo *le
         const int64_t g = g0 + c;
         const LeafInfo L = leaves[g >> 3];
         float fv[BH_MLP_INPUTS];
-        group_features12(n, L, (int)(g & 7), fv);
+        group_features12(n, L, (int)(g >> 3), (int)(g & 7), fv);
         const int f = 3 * q;
         const float a0 = q == 0 ? fv[0] : (q == 1 ? fv[3] : (q == 2 ? fv[6] : fv[9]));
         const float a1 = q == 0 ? fv[1] : (q == 1 ? fv[4] : (q == 2 ? fv[7] : fv[10]));
