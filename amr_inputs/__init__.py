@@ -13,6 +13,7 @@ from .grids import (  # noqa: F401
     maclaurin_spheroid,
     cloud_core,
     plummer_mix,
+    plummer_sphere,
     random_amr,
     single_block,
     maclaurin_axes,

@@ -483,3 +483,29 @@ def single_block(seed=0, sigma=0.5):
         return np.exp(sigma * rng.standard_normal((lo.shape[0], NB, NB, NB)))
 
     return build_grid("single_block", 1, lambda *a: False, 0, dens, meta=dict(seed=seed))
+
+
+def plummer_sphere(a=0.1, mass=1.0, r_trunc=0.45, nbase=4, max_level=0, centre=(0.5, 0.5, 0.5)):
+    """One Plummer sphere rho = (3M / 4 pi a^3)(1 + r^2/a^2)^(-5/2), zero beyond r_trunc.
+
+    Densities are sampled at the cell centres and weighted by the cell's
+    volume fraction inside r_trunc.  With ``max_level > 0`` the
+    blocks within 2a of the centre are refined.
+    """
+    c = np.asarray(centre, np.float64)
+
+    def refine(L, lo, e):
+        q = np.clip(c, lo, lo + e)
+        return float(np.sqrt(((q - c) ** 2).sum())) < 2 * a
+
+    def dens(lo, h):
+        off = np.arange(NB) + 0.5
+        x = lo[:, 0, None] + off[None, :] * h[:, None] - c[0]
+        y = lo[:, 1, None] + off[None, :] * h[:, None] - c[1]
+        z = lo[:, 2, None] + off[None, :] * h[:, None] - c[2]
+        r2 = x[:, None, None, :] ** 2 + y[:, None, :, None] ** 2 + z[:, :, None, None] ** 2
+        rho = 3.0 * mass / (4.0 * math.pi * a ** 3) * (1.0 + r2 / a ** 2) ** -2.5
+        return rho * ellipsoid_fraction(lo, h, c, np.array([r_trunc] * 3))
+
+    return build_grid("plummer_sphere", nbase, refine, max_level, dens,
+                      meta=dict(a=a, mass=mass, r_trunc=r_trunc, centre=c.tolist()))

@@ -13,10 +13,10 @@ import math
 import numpy as np
 import pytest
 
-from amr_inputs import maclaurin_spheroid, uniform_sphere
+from amr_inputs import maclaurin_spheroid, plummer_sphere, uniform_sphere
 from oracle import OracleTree
 from oracle.closed_forms import (ellipsoid_potential_integral, maclaurin_A, maclaurin_potential, prism_potential,
-                                 sphere_potential)
+                                 plummer_potential, sphere_potential)
 
 E, A1AX = 0.9, 0.25
 POINTS = [(0.0, 0.0, 0.0), (0.1, 0.05, 0.03), (0.2, -0.1, 0.02), (0.0, 0.0, 0.1), (0.3, 0.0, 0.0),
@@ -146,3 +146,34 @@ def test_direct_sum_converges_to_maclaurin():
         errs.append(float(np.max(np.abs((phi - exact) / exact))))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 1e-2
+
+
+def test_direct_sum_converges_to_plummer_potential():
+    """Plummer sphere truncated at R: inside R its potential is the closed form
+    -GM / sqrt(r^2 + a^2) plus the constant G M a^2 / (R^2 + a^2)^(3/2) of the
+    removed envelope (integrate 4 pi r rho from r to R: the envelope term is
+    (GM/a)[(1 + r^2/a^2)^(-3/2) - (1 + R^2/a^2)^(-3/2)]).  The direct sum leaves
+    out each target's own cell (no self term); its continuum share, the potential
+    of a homogeneous cube at its centre, is added back so that what remains is
+    the second-order error of point masses at the cell centres."""
+    a, M, R = 0.1, 1.0, 0.45
+    errs = []
+    for nbase in (2, 4, 8):
+        g = plummer_sphere(a=a, mass=M, r_trunc=R, nbase=nbase)
+        t = OracleTree(g)
+        x, y, z, m = t.cells()
+        c = np.array(g.meta["centre"])
+        r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+        inside = np.nonzero(r < 0.4)[0]
+        tg = inside[_sample_targets(len(inside), 400, seed=nbase)]
+        h = g.box_size / (8 * nbase)
+        own = np.array([prism_potential(x[i], y[i], z[i], (x[i] - h / 2, y[i] - h / 2, z[i] - h / 2),
+                                        (x[i] + h / 2, y[i] + h / 2, z[i] + h / 2), m[i] / h ** 3)
+                        for i in tg]).ravel()
+        phi = t.direct(tg) + own
+        exact = plummer_potential(r[tg], M, a) + M * a * a / (R * R + a * a) ** 1.5
+        errs.append(float(np.sqrt(np.mean(((phi - exact) / exact) ** 2))))
+    # smooth density sampled at cell centres: second order in h (two halvings: 16x)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] / errs[2] > 10.0
+    assert errs[2] < 5e-4

@@ -27,7 +27,7 @@ metric is ||phi - phi_ref|| / ||phi_ref|| over the sampled cells.
 import numpy as np
 import pytest
 
-from amr_inputs import random_amr, single_block
+from amr_inputs import random_amr, single_block, uniform_sphere
 from oracle import OracleTree
 from oracle.oracle import ewald, ewald_hessian, make_key, split_key
 
@@ -186,3 +186,23 @@ def test_half_box_translation_permutes_the_potential():
     assert ok.sum() >= 2
     assert np.array_equal(c1[ok, :3], c2[ok, :3])
     assert np.max(np.abs(p1[ok] - p2[ok])) <= 1e-12 * np.max(np.abs(p1))
+
+
+def test_accuracy_at_theta_half_on_a_sphere():
+    """Absolute accuracy pin: on the uniform sphere of the opening configuration
+    (16^3 cells, sixteen groups spread over the grid), the periodic walk and sum
+    at theta = 0.5 come within 5e-4 of the exact periodic direct sum in the
+    normalised norm.  That is a third of the maximum error the paper reports
+    for its isolated method at theta = 0.5 (1.4e-3, Fig. Errors), and the
+    quadrupole keeps this method's own isolated error at 5e-6 on the same
+    cells; the periodic error is larger because the expansion of D is cut at
+    second order near the half-box planes (measured 1.3e-4)."""
+    g = uniform_sphere(nbase=2)
+    t = OracleTree(g)
+    t.moments()
+    gs = np.unique(np.linspace(0, t.n_groups(64) - 1, 16).astype(int))
+    ref = t.direct_periodic(np.concatenate([_group_cells(q) for q in gs]))
+    phi, counts = t.solve_groups_periodic(gs, theta=0.5)
+    assert counts[:, 1].sum() > 0  # far nodes were accepted
+    err = np.linalg.norm(phi.ravel() - ref) / np.linalg.norm(ref)
+    assert err <= 5e-4, err
