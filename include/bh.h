@@ -201,6 +201,32 @@ int bh_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, const bh
 int bh_walk_potential(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, double theta,
                       const float *theta_group_dev, int precision, double G, double *phi_dev, int32_t *counts_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * bh_build_moments followed by bh_walk_potential in one call that allocates
+ * nothing.  The workspace a moments handle would own (node moments, walk and
+ * far records, cell records, per-group costs) lives instead in one static
+ * device array of BH_STATIC_SCRATCH_BYTES per GPU, held from the library's
+ * load on that GPU until the process ends.  Same kernels and tiles as the
+ * two-call path in the natural group order, hence the same potential bits.
+ * rho_dev, theta, theta_group_dev, precision, G, phi_dev, counts_dev: as for
+ * bh_build_moments and bh_walk_potential.
+ * status_dev: NULL or int32 [2], cleared by the call, then status_dev[0] != 0
+ * if some density was negative or not finite and status_dev[1] != 0 if the
+ * traversal stack overflowed (NULL: these conditions are not reported).
+ * Workspace of a grid: 232 B per node + 48 B per cell + 96 B per leaf block
+ * + 4 B per group, each part rounded up to 256 B (about 82 B per cell; the
+ * 1.4M-cell MacLaurin benchmark mesh needs about 115 MB).  A grid that needs
+ * more fails with BH_ECAPACITY before any work is enqueued.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (several streams or threads without
+ * ordering) race and give undefined results.  Errors: BH_EINVAL, BH_ESTATE
+ * (grid of another device), BH_ECAPACITY, BH_EDEVICE. */
+#define BH_STATIC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int bh_potential_static(bh_ctx *ctx, const bh_grid *grid, const double *rho_dev, double theta,
+                        const float *theta_group_dev, int precision, double G, double *phi_dev, int32_t *counts_dev,
+                        int32_t *status_dev);
+
 /* Accelerations g = -grad phi from the same walk and tiles as
  * bh_walk_potential: the gradient of the far term (monopole and quadrupole)
  * and of the near pair terms, taken term by term (an extension of the method,

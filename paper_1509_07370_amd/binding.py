@@ -68,6 +68,7 @@ _SIGS = {
     "bh_lists_destroy": (ctypes.c_int, [P]),
     "bh_potential": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
     "bh_walk_potential": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P]),
+    "bh_potential_static": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P, P]),
     "bh_walk_potential_ex": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P, P]),
     "bh_walk_accel": (ctypes.c_int, [P, P, P, f64, P, ctypes.c_int, f64, P, P, P]),
     "bh_direct_accel": (ctypes.c_int, [P, P, P, P, i64, f64, P]),
@@ -279,6 +280,15 @@ def bh_walk_potential(ctx, grid, m, theta, theta_group, precision, G, phi, count
     cn = _dev(counts, "int32") if counts is not None else None
     _check(_lib.bh_walk_potential(ctx, grid, m, float(theta), tg, int(precision), float(G), _dev(phi, "float64"), cn),
            ctx)
+    return phi
+
+
+def bh_potential_static(ctx, grid, rho, theta, theta_group, precision, G, phi, counts=None, status=None):
+    tg = _dev(theta_group, "float32") if theta_group is not None else None
+    cn = _dev(counts, "int32") if counts is not None else None
+    st = _dev(status, "int32") if status is not None else None
+    _check(_lib.bh_potential_static(ctx, grid, _dev(rho, "float64"), float(theta), tg, int(precision), float(G),
+                                    _dev(phi, "float64"), cn, st), ctx)
     return phi
 
 

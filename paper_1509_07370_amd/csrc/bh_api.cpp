@@ -93,6 +93,12 @@ int bh_ctx_create(bh_ctx **out, int device, void *stream) {
             g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
             return BH_EDEVICE;
         }
+        // the static scratch of bh_potential_static: its device address, once per device
+        e = bh::static_scratch_setup(device, nullptr);
+        if (e != hipSuccess) {
+            g_create_error = std::string("static scratch address: ") + hipGetErrorString(e);
+            return BH_EDEVICE;
+        }
     } else if (device != -1) {
         g_create_error = "device must be >= 0, or -1 for a host-only context";
         return BH_EINVAL;

@@ -254,4 +254,7 @@ hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_list
 hipError_t launch_direct(const bh_grid *g, const bh_moments *m, const int64_t *targets, int64_t n, double G,
                          double *out, bool accel, hipStream_t s);
 int walk_k8_threshold(int max_depth);
+// Device address of the static scratch of bh_potential_static on `device`
+// (looked up once per device; out may be NULL).
+hipError_t static_scratch_setup(int device, void **out);
 }  // namespace bh
