@@ -78,3 +78,23 @@ def bf16_round(x):
     u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p, X, mean, scale):
+    """The network as its bf16 inference evaluates it: standardised inputs,
+    weights, biases and both hidden activations rounded to bfloat16, every
+    product and sum in fp64 (the kernels accumulate in fp32).  Returns theta."""
+    W1, b1, W2, b2, W3, b3 = (bf16_round(np.asarray(a, np.float32)) for a in unpack(p))
+    Xn = bf16_round(((np.asarray(X, np.float64) - mean) * scale).astype(np.float32))
+    H1 = bf16_round(np.tanh(Xn @ W1.T + b1).astype(np.float32))
+    H2 = bf16_round(np.tanh(H1 @ W2.T + b2).astype(np.float32))
+    z = H2 @ W3 + b3
+    s = 1.0 / (1.0 + np.exp(-z))
+    return 0.2 + 0.8 * s
+
+
+def snap_up(theta, shift=0.0):
+    """theta - shift moved up to the next value of the grid 0.20, 0.25, ..., 1.00
+    (values within 1e-6 above a grid value stay on it; the grid's ends clamp)."""
+    k = np.clip(np.ceil((np.asarray(theta, np.float64) - shift - 1e-6 - 0.2) * 20.0), 0, 16)
+    return 0.2 + 0.05 * k

@@ -43,3 +43,33 @@ def walk_tolerance(masses_sum, qsum, L, storage, fp32):
     if fp32:
         tol = tol + 3e-6 * 3 * masses_sum / L
     return tol
+
+
+def measured_lookup_errors(table_values, L, n_points=4000, seed=0):
+    """Largest errors of the table lookup itself, measured: at random points of
+    the octant [0, L/2]^3, D by its third-order Taylor expansion about the
+    nearest table point and the Hessian by its first-order one (the lookup the
+    walks make, evaluated in fp64 from the exported fp64 table), against the
+    oracle's Ewald sums.  Returns (D error per unit mass, largest Hessian-entry
+    error), the measured counterparts of TABLE_ERR / L and HESS_ERR / L^3."""
+    from oracle.oracle import ewald_hessian
+    n = table_values.shape[0]
+    v = table_values.reshape(-1, 20)
+    sp = 0.5 * L / (n - 1)
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, 0.5 * L, (n_points, 3))
+    idx = np.clip(np.rint(u / sp).astype(np.int64), 0, n - 1)
+    d = u - idx * sp
+    row = v[(idx[:, 2] * n + idx[:, 1]) * n + idx[:, 0]]
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    D0, g, H, T = row[:, 0], row[:, 1:4], row[:, 4:10], row[:, 10:20]
+    Txxx, Tyyy, Tzzz, Txxy, Txxz, Txyy, Tyyz, Txzz, Tyzz, Txyz = T.T
+    quad = H[:, 0] * x * x + H[:, 1] * y * y + H[:, 2] * z * z + 2 * (H[:, 3] * x * y + H[:, 4] * x * z + H[:, 5] * y * z)
+    cube = (Txxx * x ** 3 + Tyyy * y ** 3 + Tzzz * z ** 3 + 3 * (Txxy * x * x * y + Txxz * x * x * z + Txyy * x * y * y
+            + Tyyz * y * y * z + Txzz * x * z * z + Tyzz * y * z * z) + 6 * Txyz * x * y * z)
+    D = D0 + (g * d).sum(1) + quad / 2 + cube / 6
+    Hl = np.stack([H[:, 0] + Txxx * x + Txxy * y + Txxz * z, H[:, 1] + Txyy * x + Tyyy * y + Tyyz * z,
+                   H[:, 2] + Txzz * x + Tyzz * y + Tzzz * z, H[:, 3] + Txxy * x + Txyy * y + Txyz * z,
+                   H[:, 4] + Txxz * x + Txyz * y + Txzz * z, H[:, 5] + Txyz * x + Tyyz * y + Tyzz * z], 1)
+    De, _, He = ewald_hessian(u, L)
+    return float(np.max(np.abs(D - De))), float(np.max(np.abs(Hl - He)))

@@ -241,3 +241,42 @@ def test_one_launch_learned_walk_equals_two_launches(precision):
         assert torch.equal(p1, p2) and torch.equal(c1, c2)
     net.close()
     bh.close()
+
+
+@pytest.mark.parametrize("which", ["glorot", "shipped_1e-4"])
+def test_theta_infer_equals_the_oracle_features_and_bf16_network(which):
+    """bh_theta_infer (features from node rows and the bf16 network on the matrix cores, snapped) against
+    the oracle: its fp64 features from brute-force node moments, the bf16-rounded fp64 network, the same
+    snap.  Every group of a MacLaurin grid and of a ragged random grid; the two sides round differently
+    (fp32 logs and fp32 accumulation against fp64), so a prediction within 5e-3 of a grid boundary may
+    take the neighbouring value."""
+    import os
+    for g in (maclaurin_spheroid(max_level=1), random_amr(23, nbase=2, max_level=3, p_refine=0.3,
+                                                           zero_fraction=0.1)):
+        bh = BarnesHut(g)
+        rho = torch.tensor(g.rho, device="cuda")
+        ng = bh.info["n_groups"]
+        F = oracle_features(OracleTree(g), g)
+        if which == "glorot":
+            net = LT.ThetaNet.fresh(bh.ctx, F.astype(np.float32), (glorot_init(7) * 3).astype(np.float32))
+        else:
+            net = LT.ThetaNet.load(bh.ctx, os.path.join(LT.DATA_DIR, "theta_mlp_1e-4.npz"))
+        p = net.params().astype(np.float64)
+        for shift in (0.0, 0.1):
+            th = torch.full((ng,), float("nan"), device="cuda")
+            bh.build_moments(rho)
+            B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, th, shift)
+            bh.check()
+            t = th.cpu().numpy().astype(np.float64)
+            cont = omlp.forward_bf16(p, F, net.mean.astype(np.float64), net.scale.astype(np.float64)) - shift
+            want = omlp.snap_up(cont)
+            near_edge = np.abs((cont - 0.2) * 20.0 - np.round((cont - 0.2) * 20.0)) < 0.1
+            same = np.abs(t - want) < 1e-6
+            print("[theta_infer vs oracle] %s %s shift %.1f: %d groups, %d differ (%d near a grid edge), "
+                  "%d distinct thetas" % (which, g.name, shift, ng, int((~same).sum()), int(near_edge.sum()),
+                                          np.unique(t).size))
+            assert np.all(same | (near_edge & (np.abs(t - want) < 0.05 + 1e-6)))
+            assert same.mean() > 0.97
+            assert np.unique(t).size > 2
+        net.close()
+        bh.close()

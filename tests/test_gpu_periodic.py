@@ -9,13 +9,16 @@ O9 and O10, through the C ABI.
 * the periodic direct sum (table lookups) equals the oracle's exact one
   within the table's error, derived from the lookup's third-order remainder
   (see TABLE_ERR);
-* the periodic walk and sum: far/near counts equal the oracle's O10 walk in
-  every group without a marginal decision, and the potentials agree within
-  the table's errors (D and, weighted by the far nodes' quadrupoles, its
-  Hessian) plus, in fp32, the rounding of O(1) terms that cancel to the small
-  periodic potential; and the storage of the walks' table rows (Hessian and
-  third derivatives at half the walk's precision, see STORE_EPS); a tiny
-  theta equals the GPU periodic direct sum;
+* the periodic walk and sum, on 16 sampled groups per grid: far/near counts
+  equal the oracle's O10 walk in every group without a marginal decision, and
+  the potentials agree within the table's errors (D and, weighted by the far
+  nodes' quadrupoles, its Hessian) plus, in fp32, the rounding of O(1) terms
+  that cancel to the small periodic potential; and the storage of the walks'
+  table rows (Hessian and third derivatives at half the walk's precision, see
+  STORE_EPS).  Three tiers: the table errors bounded from |D^(4)|, the same
+  bound with the lookup's errors measured at random points, and a regression
+  guard at 4x the largest difference the library gives today; a tiny theta
+  equals the GPU periodic direct sum;
 * bad arguments are refused.
 
 Error scale: periodic potentials have zero mean, so differences are taken
@@ -27,7 +30,8 @@ import pytest
 from amr_inputs import maclaurin_spheroid, random_amr
 from oracle import OracleTree
 from oracle.oracle import ewald_hessian
-from periodic_bounds import EPS_FP32_ROWS, EPS_FP64_ROWS, N_TABLE, TABLE_ERR, storage_terms, walk_tolerance
+from periodic_bounds import (EPS_FP32_ROWS, EPS_FP64_ROWS, HESS_ERR, N_TABLE, TABLE_ERR, measured_lookup_errors,
+                             storage_terms, walk_tolerance)
 
 pytestmark = pytest.mark.gpu
 
@@ -128,13 +132,22 @@ def test_periodic_direct_equals_oracle(name):
 
 _oracle_cache = {}
 
+# largest |phi_gpu - phi_oracle| over the sampled groups of test_periodic_walk_equals_oracle as this library
+# computes them (33^3 table): the derived bounds sit 20-200x above, so these guard against regressions
+REGRESSION_MAX_DIFF = {
+    ("random_amr", B.BH_FP64, 0.5): 6.48e-7, ("maclaurin_l1", B.BH_FP64, 0.5): 7.98e-8,
+    ("random_amr", B.BH_FP32, 0.5): 7.98e-7, ("maclaurin_l1", B.BH_FP32, 0.5): 1.13e-7,
+    ("random_amr", B.BH_FP64, 0.8): 1.59e-6, ("maclaurin_l1", B.BH_FP64, 0.8): 2.39e-7,
+    ("random_amr", B.BH_FP32, 0.8): 1.53e-6, ("maclaurin_l1", B.BH_FP32, 0.8): 2.58e-7,
+}
+
 
 def _oracle_groups(name, theta):
     """O10 on a few sampled groups, shared by both precisions (marginal flags at the fp32 tau, the wider)."""
     if (name, theta) not in _oracle_cache:
         g, bh, rho, table, t = setup(name)
         ng = bh.info["n_groups"]
-        gs = np.unique(np.r_[0, ng - 1, np.random.default_rng(7).choice(ng, 3, replace=False)])
+        gs = np.unique(np.r_[0, ng - 1, np.random.default_rng(7).choice(ng, 14, replace=False)])
         ref, oc, qs = t.solve_groups_periodic(gs, theta=theta, tau=TAU[B.BH_FP32], with_qsum=True)
         _oracle_cache[(name, theta)] = (gs, ref, oc, qs)
     return _oracle_cache[(name, theta)]
@@ -164,9 +177,21 @@ def test_periodic_walk_equals_oracle(name, precision, theta):
     storage = storage_terms(B.bh_ewald_export(bh.ctx, table, N_TABLE), g.box_size, STORE_EPS[precision])
     tol_g = walk_tolerance(m.sum(), qs[ok], g.box_size, storage, precision == B.BH_FP32)
     ratio = np.max(np.abs(p[ok] - ref[ok]), axis=1) / tol_g
-    print("[periodic] %s precision %d theta %.1f: max diff %.2e, largest diff/tolerance %.2e (RMS potential %.2e)"
-          % (name, precision, theta, np.max(np.abs(p[ok] - ref[ok])), ratio.max(), scale))
+    # the same bound with the lookup's errors measured instead of bounded (see measured_lookup_errors)
+    e_d, e_h = measured_lookup_errors(B.bh_ewald_export(bh.ctx, table, N_TABLE), g.box_size)
+    ds, hs = storage
+    fp32_term = 3e-6 * 3 * m.sum() / g.box_size if precision == B.BH_FP32 else 0.0
+    tol_m = e_d * m.sum() + e_h * qs[ok] + ds * m.sum() + hs * qs[ok] + fp32_term
+    ratio_m = np.max(np.abs(p[ok] - ref[ok]), axis=1) / tol_m
+    print("[periodic] %s precision %d theta %.1f: %d groups, max diff %.2e, largest diff/tolerance %.2e, "
+          "diff/measured-lookup tolerance %.2e (RMS potential %.2e; e_D %.2e e_H %.2e TABLE %.2e HESS %.2e "
+          "storage %.2e %.2e fp32 %.2e qsum max %.2e sum m %.3e)"
+          % (name, precision, theta, ok.sum(), np.max(np.abs(p[ok] - ref[ok])), ratio.max(), ratio_m.max(), scale,
+             e_d, e_h, TABLE_ERR, HESS_ERR, ds, hs, fp32_term, qs[ok].max(), m.sum()))
     assert np.all(ratio <= 1.0), (ratio, tol_g)
+    assert np.all(ratio_m <= 1.0), (ratio_m, tol_m)
+    # regression guard: 4x the largest difference this library gave on these groups (not a derived bound)
+    assert np.max(np.abs(p[ok] - ref[ok])) <= 4.0 * REGRESSION_MAX_DIFF[(name, precision, theta)]
 
 
 def test_tiny_theta_equals_the_periodic_direct_sum():

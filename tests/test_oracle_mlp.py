@@ -80,3 +80,25 @@ def test_features_are_finite_with_empty_blocks():
     F = group_features(OracleTree(g), g)
     assert np.isfinite(F).all()
     assert F[:, 3].max() == 3
+
+
+def test_bf16_forward_and_snap():
+    X, y, mean, scale = _data(300)
+    p = glorot_init(9)
+    th, _ = mlp.forward(p, X, mean, scale)
+    tb = mlp.forward_bf16(p, X, mean, scale)
+    # bf16 inputs, weights and activations move theta by well under the grid step
+    assert np.max(np.abs(tb - th)) <= 0.01 and np.max(np.abs(tb - th)) > 0
+    # weights and inputs that bf16 holds exactly, hidden layers saturated (tanh = +-1 exactly in bf16):
+    # the bf16 forward is the fp64 forward
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(glorot_init(5))
+    W1 = np.where(W1 < 0, -4.0, 4.0)
+    W2 = np.where(W2 < 0, -32.0, 32.0)
+    W3 = np.round(W3 * 64) / 64
+    q = mlp.pack(W1, np.zeros(64), W2, np.zeros(64), W3, 0.25)
+    Xe = np.where(X < 0, -4.0, 4.0)  # pre-activations are multiples of 32: tanh is 0 or +-1 exactly
+    assert np.array_equal(mlp.forward_bf16(q, Xe, np.zeros(12), np.ones(12)),
+                          mlp.forward(q, Xe, np.zeros(12), np.ones(12))[0])
+    s = mlp.snap_up(np.array([0.2, 0.2 + 5e-7, 0.21, 0.25, 0.2500001, 0.26, 0.999, 1.0, 0.1, 0.55]))
+    assert np.allclose(s, [0.2, 0.2, 0.25, 0.25, 0.25, 0.3, 1.0, 1.0, 0.2, 0.55], atol=1e-12, rtol=0)
+    assert np.allclose(mlp.snap_up(np.array([0.61, 0.7]), shift=0.1), [0.55, 0.6], atol=1e-12, rtol=0)
