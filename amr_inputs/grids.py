@@ -366,20 +366,22 @@ def cloud_core(r0=0.02, rho0=1.0, r_trunc=0.5, contrast_out=1e-4, sigma=0.1, see
                                 seed=seed, jeans_cs=jeans_cs, cells_per_jeans=cells_per_jeans))
 
 
-def plummer_mix(seed, n_target_blocks=None, nbase=4):
+def plummer_mix(seed, n_target_blocks=None, nbase=4, max_level=None):
     """Seeded mix of 1-4 Plummer spheres rho = (3M / 4 pi a^3)(1 + r^2/a^2)^(-5/2).
 
     Scale a log-uniform in [0.02, 0.1], mass ratios uniform in [0.1, 1], centres
-    uniform in [0.3, 0.7]^3, max level uniform in {3..6}; blocks are refined in
-    order of decreasing peak density until the leaf-block target (log-uniform in
-    [100, 8000] unless given) would be exceeded.
+    uniform in [0.3, 0.7]^3, max level uniform in {3..6} unless given; blocks
+    are refined in order of decreasing peak density until the leaf-block target
+    (log-uniform in [100, 8000] unless given) would be exceeded.  The random
+    draws do not depend on the arguments given.
     """
     rng = np.random.default_rng(seed)
     k = int(rng.integers(1, 5))
     a = np.exp(rng.uniform(math.log(0.02), math.log(0.1), size=k))
     mass = rng.uniform(0.1, 1.0, size=k)
     ctr = rng.uniform(0.3, 0.7, size=(k, 3))
-    max_level = int(rng.integers(3, 7))
+    drawn_level = int(rng.integers(3, 7))
+    max_level = drawn_level if max_level is None else int(max_level)
     if n_target_blocks is None:
         n_target_blocks = int(round(math.exp(rng.uniform(math.log(100), math.log(8000)))))
 

@@ -39,7 +39,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector datasheet figure
-F_FAR = 35                  # flop per (cell, far node): monopole + quadrupole
+F_FAR = 28                  # flop per (cell, far node): monopole + quadrupole, as the fp32 kernel computes it
+F_FAR_NAIVE = 35            # the same term written out without reusing the squares (reported beside it)
 F_NEAR = 11                 # flop per (cell, near cell) pair
 F_FAR_ACC = 55              # flop per (cell, far node) pair with potential + acceleration
 F_NEAR_ACC = 19             # flop per (cell, near cell) pair with potential + acceleration
@@ -82,7 +83,11 @@ def profiled_traffic():
 
 
 def algorithmic_flops(n_far, n_near):
-    """35 per cell-node far interaction + 11 per near cell pair (self excluded);
+    """28 per cell-node far interaction + 11 per near cell pair (self excluded);
+    FMA = 2, add/mul/rsqrt = 1.  Far: 3 differences, 3 squares and 2 adds for
+    d^2, 1 rsqrt, R^T (Q/2) R with the squares reused (1 mul + 5 FMA + 2 mul),
+    then (M + qd/d^4)/d and the accumulation (2 mul + 2 FMA).  Near: 3
+    differences, d^2 (1 mul + 2 FMA), 1 rsqrt, 1 FMA.
     n_far / n_near: far nodes and near bottom nodes per 64-cell group."""
     n_far = np.asarray(n_far, np.int64)
     n_near = np.asarray(n_near, np.int64)
@@ -571,8 +576,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
                      "kernel": "walk_potential_theta_kernel<float, 8>", "kernel_ms": pot_ms,
-                     "flop_per_launch": flops,
-                     "far_interactions": far_int, "near_pairs": near_pairs},
+                     "flop_per_launch": flops, "flop_per_far_interaction": F_FAR, "flop_per_near_pair": F_NEAR,
+                     "far_interactions": far_int, "near_pairs": near_pairs,
+                     "achieved_naive_far_count": (flops + (F_FAR_NAIVE - F_FAR) * far_int) / (pot_ms * 1e-3) / 1e12},
         "cpu_baseline": cpu,
         "topology_ms": topo_ms,
         "sweep": sweep,

@@ -98,8 +98,13 @@ const char *bh_create_error(void);
  * nbase^3 lattice with nbase a power of two; log2(nbase) virtual levels join
  * them under one root.  nb must be 8 (cells per block edge).  group_cells is
  * the number of neighbouring cells sharing one opening vote and one
- * interaction list; this build supports 64 (a 4x4x4 Morton sub-cube, one
- * wavefront).  Errors: BH_EINVAL with the first inconsistency found
+ * interaction list (the all() vote of section 3.3, whose group is a 32-thread
+ * warp): 32, 64, 128, 256 or 512, an aligned Morton run of the block's cells
+ * (4x4x2, 4x4x4, 8x4x4, 8x8x4 or the whole 8x8x8 block).  A group of 64 or
+ * more cells spans group_cells/64 wavefronts that walk alike; two 32-cell
+ * groups share one wavefront.  The learned-theta calls (features, network
+ * inference, per-group errors) and batches need 64-cell groups.
+ * Errors: BH_EINVAL with the first inconsistency found
  * (parent/child mismatch, level, position off the lattice, missing base block,
  * duplicate block, tree deeper than 18 levels), BH_ENOMEM, BH_EDEVICE. */
 int bh_grid_create(bh_ctx *ctx, bh_grid **grid, int n_blocks, int nb, const int32_t *level, const double *lo,
@@ -342,7 +347,8 @@ int bh_direct_periodic(bh_ctx *ctx, const bh_grid *grid, const bh_moments *m, co
  * persistent launch of the fused walk + sums in which each wavefront takes the
  * next (grid, group) work item from an atomic queue until all are done.  The
  * method per group is exactly bh_walk_potential's (same tiles, same order, the
- * same bits).  A batch owns its own moments; all grids must belong to ctx. */
+ * same bits).  A batch owns its own moments; all grids must belong to ctx and
+ * have 64-cell groups (BH_EINVAL otherwise). */
 #define BH_ORDER_NATURAL 0 /* grid by grid, groups in Morton order */
 #define BH_ORDER_COST 1    /* most expensive groups first (counts of the last solve) */
 

@@ -133,7 +133,8 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
     if (!out) return fail(ctx, BH_EINVAL, "grid output pointer is NULL");
     *out = nullptr;
     if (nb != bh::kNB) return fail(ctx, BH_EINVAL, "nb must be 8 (cells per block edge)");
-    if (group_cells != bh::kGroupCells) return fail(ctx, BH_EINVAL, "group_cells must be 64 in this build");
+    if (group_cells != 32 && group_cells != 64 && group_cells != 128 && group_cells != 256 && group_cells != 512)
+        return fail(ctx, BH_EINVAL, "group_cells must be 32, 64, 128, 256 or 512");
     if (!level || !lo || !parent || !child || !is_leaf || !box_lo)
         return fail(ctx, BH_EINVAL, "a grid array pointer is NULL");
     bh_grid *g = new (std::nothrow) bh_grid();
@@ -158,6 +159,7 @@ int bh_grid_create(bh_ctx *ctx, bh_grid **out, int n_blocks, int nb, const int32
     g->group_cells = group_cells;
     g->n_cells = (int64_t)g->topo.leaves.size() * bh::kCellsPerBlock;
     g->n_groups = g->n_cells / group_cells;
+    g->n_units = (int64_t)g->topo.leaves.size() * 8;
     if (ctx->device >= 0) {
         int rc = require_gpu(ctx);
         if (rc) {
@@ -282,9 +284,9 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
             (e = dalloc(&m->d_f32, (size_t)nn)) != hipSuccess || (e = dalloc(&m->d_cell64, (size_t)nc)) != hipSuccess ||
             (e = dalloc(&m->d_cell32, (size_t)nc)) != hipSuccess || (e = dalloc(&m->d_flags, 2)) != hipSuccess ||
             (e = hipMemset(m->d_flags, 0, 2 * sizeof(int))) != hipSuccess ||
-            (e = dalloc(&m->d_cost, (size_t)g->n_groups)) != hipSuccess ||
+            (e = dalloc(&m->d_cost, (size_t)g->n_units)) != hipSuccess ||
             (e = dalloc(&m->d_theta, (size_t)g->n_groups)) != hipSuccess ||
-            (e = dalloc(&m->d_order, (size_t)g->n_groups)) != hipSuccess ||
+            (e = dalloc(&m->d_order, (size_t)g->n_units)) != hipSuccess ||
             (e = dalloc(&m->d_sched, 2 * 256 + 1)) != hipSuccess ||
             (e = hipMemset(m->d_sched, 0, (2 * 256 + 1) * sizeof(int))) != hipSuccess) {
             bh_moments_destroy(m);
@@ -294,7 +296,7 @@ int bh_build_moments(bh_ctx *ctx, const bh_grid *g, const double *rho, bh_moment
     }
     // once a fused walk has recorded its costs, the upward pass also sorts the
     // groups by them, for the dispatch order of the next fused walks
-    const bool schedule = m->cost_valid && g->n_groups > 1;
+    const bool schedule = m->cost_valid && g->n_units > 1;
     HIPX(ctx, bh::launch_moments(g, m, rho, ctx->stream, 0, schedule), "moments kernels");
     if (schedule) m->order_valid = true;
     return BH_OK;

@@ -151,6 +151,10 @@ int bh_batch_create(bh_ctx *ctx, bh_batch **out, int n, bh_grid *const *grids) {
             bh_batch_destroy(b);
             return fail(ctx, BH_EINVAL, "a grid is NULL or belongs to another context");
         }
+        if (grids[k]->group_cells != bh::kGroupCells) {
+            bh_batch_destroy(b);
+            return fail(ctx, BH_EINVAL, "batched grids must have 64-cell groups");
+        }
         b->grids.push_back(grids[k]);
         b->group_base.push_back(b->group_base.back() + grids[k]->n_groups);
     }

@@ -65,7 +65,9 @@ struct WalkArgs {
     const LeafInfo *leaves;
     const float *theta_group;
     double theta;
-    int64_t n_groups;
+    int64_t n_groups;  // groups of gcells cells
+    int gcells;        // cells per group: 32, 64, 128, 256 or 512
+    int64_t n_units;   // 64-cell octants (8 per leaf block): the fused kernels' wavefronts
     int root;
     int k8_threshold;
     int epoch;
@@ -155,6 +157,7 @@ struct bh_grid {
     bh::Topology topo;
     int group_cells = bh::kGroupCells;
     int64_t n_groups = 0;
+    int64_t n_units = 0;  // 64-cell octants, 8 per leaf block (dispatch units of the fused walks)
     int64_t n_cells = 0;
     // device copies of the static topology
     double *d_geom = nullptr;            // [n_nodes][4]
@@ -189,8 +192,8 @@ struct bh_moments {
     // walk records the cost of every group; the next upward pass sorts the
     // groups by it into the order that the following fused walks dispatch
     float *d_theta = nullptr;     // [n_groups] canonical order: the learned step's thetas
-    uint32_t *d_cost = nullptr;   // [n_groups], internal group order
-    int32_t *d_order = nullptr;   // [n_groups]
+    uint32_t *d_cost = nullptr;   // [n_units], internal octant order
+    int32_t *d_order = nullptr;   // [n_units]
     int *d_sched = nullptr;       // bin histogram [256], placement cursors [256], finished count: zero between passes
     mutable bool cost_valid = false;  // d_cost holds a walk's costs
     bool order_valid = false;         // d_order holds a permutation

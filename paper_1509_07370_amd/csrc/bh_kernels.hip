@@ -166,12 +166,12 @@ __device__ __forceinline__ void combine_lanes(double m, double x, double y, doub
 // the atomics; it decides which wavefront computes a group, not what it
 // computes.
 struct SchedArgs {
-    const uint32_t *cost;  // [n_groups] from the last fused walk; NULL: no schedule in this pass
+    const uint32_t *cost;  // [n_units] from the last fused walk; NULL: no schedule in this pass
     int *hist;             // [256] bin counts (zero between passes)
     int *cursor;           // [256] placement cursors (zero between passes)
     int *done;             // workgroups of the placement that have finished (zero between passes)
-    int32_t *order;        // [n_groups] dispatch order
-    int64_t n_groups;
+    int32_t *order;        // [n_units] dispatch order of the 64-cell octants
+    int64_t n_units;
     int parts;             // workgroups of the placement, the first ones of the upper-node launch
 };
 
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) void moments_upper_kernel(const int32_t *__res
     __shared__ double red[7][4];
     if (sa.cost && (int)blockIdx.x < sa.parts) {  // a share of the dispatch schedule's placement
         __shared__ int start[256], wave_total[4];
-        const int64_t n = sa.n_groups, p = blockIdx.x;
+        const int64_t n = sa.n_units, p = blockIdx.x;
         sched_place(sa, n * p / sa.parts, n * (p + 1) / sa.parts, start, wave_total);
         return;
     }
@@ -419,10 +419,10 @@ hipError_t launch_moments(const bh_grid *g, bh_moments *m, const double *rho, hi
     const int epoch = fixed_epoch > 0 ? fixed_epoch : ++m->mom_epoch;
     SchedArgs sa{};
     if (schedule) {
-        if (g->n_groups != 8 * (int64_t)nleaf) return hipErrorInvalidValue;
-        // one placement workgroup per 256 groups, launched beside the node workgroups
-        sa = SchedArgs{m->d_cost, m->d_sched, m->d_sched + 256, m->d_sched + 512, m->d_order, g->n_groups,
-                       (int)((g->n_groups + 255) / 256)};
+        if (g->n_units != 8 * (int64_t)nleaf) return hipErrorInvalidValue;
+        // one placement workgroup per 256 octants, launched beside the node workgroups
+        sa = SchedArgs{m->d_cost, m->d_sched, m->d_sched + 256, m->d_sched + 512, m->d_order, g->n_units,
+                       (int)((g->n_units + 255) / 256)};
     }
     hipLaunchKernelGGL(moments_leaf_kernel, dim3(nleaf), dim3(512), 0, s, rho, g->d_leaves, g->d_geom, g->d_child, o,
                        m->d_cell64, m->d_cell32, m->d_flags, epoch, sa);
@@ -480,132 +480,180 @@ __device__ __forceinline__ real cube_gap(real lo, real hi, real X) {
     return below > (real)0 ? below : (above > (real)0 ? above : (real)0);
 }
 
+// The cell-centre lattice of one group: the first centre per axis and the
+// number of centres per axis.  Groups are aligned Morton runs of gcells
+// cells inside a block (Morton bit 0 = x): 32 -> 4x4x2, 64 -> 4x4x4,
+// 128 -> 8x4x4, 256 -> 8x8x4, 512 -> 8x8x8 cells.
+template <typename real>
+struct GroupBox {
+    real x0[3];
+    int n[3];
+};
+
+template <typename real>
+__device__ __forceinline__ GroupBox<real> group_box(const LeafInfo &L, int gcells, int run) {
+    int i0, j0, k0;
+    demorton9(run * gcells, i0, j0, k0);
+    GroupBox<real> b;
+    b.n[0] = gcells >= 128 ? 8 : 4;
+    b.n[1] = gcells >= 256 ? 8 : 4;
+    b.n[2] = gcells >= 512 ? 8 : (gcells >= 64 ? 4 : 2);
+    b.x0[0] = (real)(L.lo[0] + (i0 + 0.5) * L.h);
+    b.x0[1] = (real)(L.lo[1] + (j0 + 0.5) * L.h);
+    b.x0[2] = (real)(L.lo[2] + (k0 + 0.5) * L.h);
+    return b;
+}
+
+// Groups per leaf block and the group (within the block) of octant `sub`.
+__device__ __forceinline__ int groups_per_leaf(int gcells) { return kCellsPerBlock / gcells; }
+
+__device__ __forceinline__ float group_theta(const WalkArgs &a, int64_t canon_group) {
+    float th = a.theta_group[canon_group];
+    if (!(th == th)) th = 1e-3f;
+    return th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
+}
+
 // Group walk state of one wavefront.  The group vote of the potential kernel
-// (all lanes accept) needs, per node, the minimum over the group's cells of
-// d^2.  The group is an axis-aligned 4x4x4 lattice of cell centres, so that
-// minimum separates per axis: the cell whose per-axis gaps are each minimal
-// has the smallest rounded d^2 too (rounding is monotone).  One lane therefore
-// decides one node exactly as 64 per-cell tests would, and a step tests the 64
-// children of up to 8 opened nodes.  The LDS stack holds the first-child ids
-// of opened nodes; it pops 8 entries while it is short and 1 entry (plain
-// depth-first order, growth <= 7 per level) once it passes k8_threshold, so it
-// never exceeds k8_threshold + 56 + 7 (max_depth + 1) + 1 < kWalkStackCap.
+// (all cells of the group accept) needs, per node, the minimum over the
+// group's cells of d^2.  The group is an axis-aligned lattice of cell
+// centres, so that minimum separates per axis: the cell whose per-axis gaps
+// are each minimal has the smallest rounded d^2 too (rounding is monotone).
+// One lane therefore decides one node exactly as per-cell tests would, and a
+// step tests the 64 children of up to 8 opened nodes.  The LDS stack holds
+// the first-child ids of opened nodes; it pops 8 entries while it is short
+// and 1 entry (plain depth-first order, growth <= 7 per level) once it passes
+// k8_threshold, so it never exceeds k8_threshold + 56 + 7 (max_depth + 1) + 1
+// < kWalkStackCap.
+// GM = 1: one group (any size); its cells may span several wavefronts, each
+// of which walks the same tree with the same decisions.
+// GM = 2: two 32-cell groups on one wavefront (the halves z < 2 and z >= 2 of
+// a 4x4x4 octant; lanes 0-31 and 32-63).  Each stack entry carries a 2-bit
+// mask of the groups that still need its sibling set (entry = child * 4 +
+// mask); a node is tested for each group in its mask, and its outcome per
+// group goes to `acc` / `nr` as masks (bit 0: lanes 0-31's group).
 // MAC 0: the exact vote of every cell of the group (O(1) per node, above);
 // MAC 1: the paper's test between a node and a region -- the smallest
-// distance from the node's centre of mass to the group's cube (cell faces).
-template <typename real, int MAC = 0>
+// distance from the node's centre of mass to the group's cube (cell faces);
+// MAC 2: the periodic box's nearest-image distances.
+template <typename real, int MAC = 0, int GM = 1>
 struct Walker {
     using Rec = typename Prec<real>::Rec;
     const Rec *nodes;
     int *stk;
     int size;
     int k8;
-    real x0, y0, z0, h, hinv, inv;
-    real blo[3], bhi[3];  // MAC 1 only
-    real cg[3], box, box_inv;  // MAC 2 (periodic) only
+    real h, hinv;
+    GroupBox<real> box;
+    real z0b;          // GM 2: first z centre of the second group
+    real inv, invb;    // 1/theta of the group(s)
+    real box_l, box_inv;  // MAC 2 only
     bool overflow;
 
-    // min over the group's 4 cell centres x0 + k h on one axis of the
+    // MAC 2: min over the group's n centres x0 + k h on one axis of the
     // nearest-image distance to X
-    __device__ real periodic_gap(real x0_, real X, real c) const {
+    __device__ real periodic_gap(real x0_, int n, real X) const {
 #pragma clang fp contract(off)
-        const real Xn = X - box * rint((X - c) * box_inv);  // image nearest the centre
-        const real Xo = Xn < c ? Xn + box : Xn - box;         // the next one on the other side
-        const real g1 = nearest_gap<real>(x0_, h, hinv, Xn, 4), g2 = nearest_gap<real>(x0_, h, hinv, Xo, 4);
+        const real c = x0_ + (real)0.5 * (real)(n - 1) * h;
+        const real Xn = X - box_l * rint((X - c) * box_inv);  // image nearest the centre
+        const real Xo = Xn < c ? Xn + box_l : Xn - box_l;       // the next one on the other side
+        const real g1 = nearest_gap<real>(x0_, h, hinv, Xn, n), g2 = nearest_gap<real>(x0_, h, hinv, Xo, n);
         return g1 < g2 ? g1 : g2;
     }
+    __device__ real axis_gap(real x0_, int n, real X) const {
+#pragma clang fp contract(off)
+        if constexpr (MAC == 1) {  // cube [first centre - h/2, last centre + h/2]
+            const real half = (real)0.5 * h;
+            return cube_gap<real>(x0_ - half, (x0_ + (real)(n - 1) * h) + half, X);
+        } else if constexpr (MAC == 2) {
+            return periodic_gap(x0_, n, X);
+        } else {
+            return nearest_gap<real>(x0_, h, hinv, X, n);
+        }
+    }
 
-    __device__ void init(const WalkArgs &a, const LeafInfo &L, int sub, int *stack, int lane) {
+    // g0: canonical index of the (first) group, for the per-group theta
+    __device__ void init(const WalkArgs &a, const LeafInfo &L, const GroupBox<real> &b, int64_t g0, int *stack,
+                         int lane) {
         nodes = (const Rec *)a.nodes;
         stk = stack;
         k8 = a.k8_threshold;
         overflow = false;
-        const int i0 = (sub & 1) * 4, j0 = ((sub >> 1) & 1) * 4, k0 = ((sub >> 2) & 1) * 4;
         h = (real)L.h;
         hinv = (real)1 / h;
-        x0 = (real)(L.lo[0] + (i0 + 0.5) * L.h);
-        y0 = (real)(L.lo[1] + (j0 + 0.5) * L.h);
-        z0 = (real)(L.lo[2] + (k0 + 0.5) * L.h);
-        if constexpr (MAC == 1) {  // cube [first centre - h/2, last centre + h/2] per axis
-#pragma clang fp contract(off)
-            const real half = (real)0.5 * h;
-            blo[0] = x0 - half;
-            blo[1] = y0 - half;
-            blo[2] = z0 - half;
-            bhi[0] = (x0 + (real)3 * h) + half;
-            bhi[1] = (y0 + (real)3 * h) + half;
-            bhi[2] = (z0 + (real)3 * h) + half;
-        }
-        if constexpr (MAC == 2) {  // group centre, box
-#pragma clang fp contract(off)
-            cg[0] = x0 + (real)1.5 * h;
-            cg[1] = y0 + (real)1.5 * h;
-            cg[2] = z0 + (real)1.5 * h;
-            box = (real)a.box;
+        box = b;
+        if constexpr (GM == 2) z0b = b.x0[2] + (real)2 * h;
+        if constexpr (MAC == 2) {
+            box_l = (real)a.box;
             box_inv = (real)(1.0 / a.box);
         }
         if (a.theta_group) {
-            float th = a.theta_group[(int64_t)L.canon * 8 + sub];
-            if (!(th == th)) th = 1e-3f;
-            th = th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
-            inv = (real)1 / (real)th;
-        } else if (sizeof(real) == 4) {
-            inv = (real)(1.0f / (float)a.theta);
+            inv = (real)1 / (real)group_theta(a, g0);
+            if constexpr (GM == 2) invb = (real)1 / (real)group_theta(a, g0 + 1);
         } else {
-            inv = (real)(1.0 / a.theta);
+            if (sizeof(real) == 4)
+                inv = (real)(1.0f / (float)a.theta);
+            else
+                inv = (real)(1.0 / a.theta);
+            invb = inv;
         }
         size = 0;
         const Rec root = nodes[a.root];
         if (!(root.flags & FLAG_EMPTY)) {
-            if (lane == 0) stk[0] = root.child;
+            if (lane == 0) stk[0] = GM == 2 ? root.child * 4 + 3 : root.child;
             size = 1;
         }
         wave_lds_sync();
     }
 
     // One step.  Per lane: id of the tested node, and whether it was accepted
-    // (far) or is a rejected bottom node (near).  Opened nodes are pushed.
-    __device__ void step(int lane, int &id, bool &acc, bool &nr) {
+    // (far) or is a rejected bottom node (near) -- for GM 2 as masks of the
+    // two groups.  Opened nodes are pushed.
+    __device__ void step(int lane, int &id, int &acc, int &nr) {
         const int k = size <= k8 ? (size < 8 ? size : 8) : 1;
         const int slot = lane >> 3;
         const bool active = slot < k;
+        int mask = 1;
         id = 0;
-        if (active) id = stk[size - 1 - slot] + (lane & 7);
+        if (active) {
+            const int e = stk[size - 1 - slot];
+            if constexpr (GM == 2) {
+                id = (e >> 2) + (lane & 7);
+                mask = e & 3;
+            } else {
+                id = e + (lane & 7);
+            }
+        }
         size -= k;
         wave_lds_sync();
-        acc = false;
-        nr = false;
+        acc = 0;
+        nr = 0;
         bool op = false;
         int ch = 0;
         if (active) {
             const Rec r = nodes[id];
             if (!(r.flags & FLAG_EMPTY)) {
 #pragma clang fp contract(off)
-                real dx, dy, dz;
-                if constexpr (MAC == 1) {
-                    dx = cube_gap<real>(blo[0], bhi[0], r.x);
-                    dy = cube_gap<real>(blo[1], bhi[1], r.y);
-                    dz = cube_gap<real>(blo[2], bhi[2], r.z);
-                } else if constexpr (MAC == 2) {
-                    // nearest-image distance from every cell: per axis the smaller gap of
-                    // the image nearest the group centre and the next one towards the group
-                    dx = periodic_gap(x0, r.x, cg[0]);
-                    dy = periodic_gap(y0, r.y, cg[1]);
-                    dz = periodic_gap(z0, r.z, cg[2]);
-                } else {
-                    dx = nearest_gap<real>(x0, h, hinv, r.x, 4);
-                    dy = nearest_gap<real>(y0, h, hinv, r.y, 4);
-                    dz = nearest_gap<real>(z0, h, hinv, r.z, 4);
+                const real dx = axis_gap(box.x0[0], box.n[0], r.x);
+                const real dy = axis_gap(box.x0[1], box.n[1], r.y);
+                const real dz = axis_gap(box.x0[2], box.n[2], r.z);
+                const real dxy = dx * dx + dy * dy;
+                const real d2 = dxy + dz * dz;
+                const real s = r.l * inv + r.delta;
+                int fm = (mask & 1) && d2 > s * s ? 1 : 0;
+                if constexpr (GM == 2) {
+                    const real dzb = axis_gap(z0b, box.n[2], r.z);
+                    const real d2b = dxy + dzb * dzb;
+                    const real sb = r.l * invb + r.delta;
+                    fm |= (mask & 2) && d2b > sb * sb ? 2 : 0;
                 }
-                real d2 = dx * dx + dy * dy + dz * dz;
-                real s = r.l * inv + r.delta;
-                acc = d2 > s * s;
-                if (!acc) {
+                acc = fm;
+                const int om = mask & ~fm;
+                if (om) {
                     if (r.flags & FLAG_BOTTOM)
-                        nr = true;
+                        nr = om;
                     else {
                         op = true;
-                        ch = r.child;
+                        ch = GM == 2 ? r.child * 4 + om : r.child;
                     }
                 }
             }
@@ -631,6 +679,8 @@ struct Walker {
     }
 };
 
+// One wavefront per group (internal group order: leaf in internal order, then
+// the group's Morton run in the block), whatever the group size.
 template <typename real, bool FILL>
 __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
     __shared__ int stack[4][kWalkStackCap];
@@ -638,10 +688,11 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t g = (int64_t)blockIdx.x * 4 + w;
     if (g >= a.n_groups) return;
-    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const int gpl = groups_per_leaf(a.gcells);
+    const int f = (int)(g / gpl), run = (int)(g % gpl);
     const LeafInfo L = a.leaves[f];
     Walker<real> W;
-    W.init(a, L, sub, stack[w], lane);
+    W.init(a, L, group_box<real>(L, a.gcells, run), (int64_t)L.canon * gpl + run, stack[w], lane);
     int64_t fbase = 0, nbase = 0;
     if (FILL) {
         fbase = a.far_off[g];
@@ -649,8 +700,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
     }
     int nf = 0, nn = 0;
     while (W.size > 0) {
-        int id;
-        bool acc, nr;
+        int id, acc, nr;
         W.step(lane, id, acc, nr);
         const uint64_t mf = __ballot(acc);
         const uint64_t mn = __ballot(nr);
@@ -678,6 +728,8 @@ static WalkArgs walk_args(const bh_grid *g, const bh_moments *m, double theta, c
     a.theta_group = theta_group;
     a.theta = theta;
     a.n_groups = g->n_groups;
+    a.gcells = g->group_cells;
+    a.n_units = g->n_units;
     a.root = g->topo.root;
     a.k8_threshold = walk_k8_threshold(g->topo.max_depth);
     a.epoch = epoch;
@@ -989,17 +1041,20 @@ struct Tiles {
         if (lane < n) put(lane, rec[3 * (int64_t)id + 0], rec[3 * (int64_t)id + 1], rec[3 * (int64_t)id + 2]);
         wave_lds_sync();
     }
-    __device__ void sum_far(int n) {
+    // keep: whether this lane's cell takes the tile (two 32-cell groups on one
+    // wavefront: a tile of one group's list is computed by all lanes and kept
+    // by that group's lanes)
+    __device__ void sum_far(int n, bool keep = true) {
         real part = 0;
         if (ORDER == 0)
             for (int j = 0; j < n; j++) part = far_monopole(me.x, me.y, me.z, T[3 * j], part);
         else
             for (int j = 0; j < n; j++) part = far_term(me.x, me.y, me.z, T[3 * j], T[3 * j + 1], T[3 * j + 2], part);
-        acc_far += (double)part;
+        if (keep) acc_far += (double)part;
         wave_lds_sync();
     }
     // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]
-    __device__ void near_tile(int lane, int n, int id) {
+    __device__ void near_tile(int lane, int n, int id, bool keep = true) {
         bool own = false;
         if (lane < 8 * n) {
             own = (unsigned)(id - own_lo) < 8u;
@@ -1012,7 +1067,7 @@ struct Tiles {
             for (int j = 0; j < 8 * n; j++) part = near_pair(me.x, me.y, me.z, T[j], part);
         else
             for (int j = 0; j < 8 * n; j++) part = near_pair_self(me.x, me.y, me.z, T[j], part);
-        acc_near += (double)part;
+        if (keep) acc_near += (double)part;
         wave_lds_sync();
     }
     __device__ void finish(const WalkArgs &a, int64_t cell) const { a.phi[cell] = -a.G * (acc_far + acc_near); }
@@ -1053,16 +1108,18 @@ struct TilesAcc {
         if (lane < n) put(lane, rec[3 * (int64_t)id + 0], rec[3 * (int64_t)id + 1], rec[3 * (int64_t)id + 2]);
         wave_lds_sync();
     }
-    __device__ void sum_far(int n) {
+    __device__ void sum_far(int n, bool keep = true) {
         real p = 0, x = 0, y = 0, z = 0;
         for (int j = 0; j < n; j++) far_term_acc<real>(me.x, me.y, me.z, T[3 * j], T[3 * j + 1], T[3 * j + 2], p, x, y, z);
-        phi += (double)p;
-        gx += (double)x;
-        gy += (double)y;
-        gz += (double)z;
+        if (keep) {
+            phi += (double)p;
+            gx += (double)x;
+            gy += (double)y;
+            gz += (double)z;
+        }
         wave_lds_sync();
     }
-    __device__ void near_tile(int lane, int n, int id) {
+    __device__ void near_tile(int lane, int n, int id, bool keep = true) {
         bool own = false;
         if (lane < 8 * n) {
             own = (unsigned)(id - own_lo) < 8u;
@@ -1075,10 +1132,12 @@ struct TilesAcc {
             for (int j = 0; j < 8 * n; j++) near_pair_acc<real, false>(me.x, me.y, me.z, T[j], p, x, y, z);
         else
             for (int j = 0; j < 8 * n; j++) near_pair_acc<real, true>(me.x, me.y, me.z, T[j], p, x, y, z);
-        phi += (double)p;
-        gx += (double)x;
-        gy += (double)y;
-        gz += (double)z;
+        if (keep) {
+            phi += (double)p;
+            gx += (double)x;
+            gy += (double)y;
+            gz += (double)z;
+        }
         wave_lds_sync();
     }
     __device__ void finish(const WalkArgs &a, int64_t cell) const {
@@ -1222,19 +1281,19 @@ struct TilesPeriodic {
         }
         return p.w * (ri + D * dscale) + quad * (ri2 * ri2 * ri) + qh + bg * u.z;
     }
-    __device__ void sum_far(int n) {
+    __device__ void sum_far(int n, bool keep = true) {
         const V4 *t = T;
         const real part = pipelined(
             n, [t](int j) { return t[3 * j]; },
             [this, t](const Pair &c, const real(&v)[kEwaldValues], int j) {
                 return far_eval(c, v, t[3 * j], t[3 * j + 1], t[3 * j + 2]);
             });
-        acc_far += (double)part;
+        if (keep) acc_far += (double)part;
         wave_lds_sync();
     }
     // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]; each cell
     // m (1/|R| + D), the cell itself D(0) only
-    __device__ void near_tile(int lane, int n, int id) {
+    __device__ void near_tile(int lane, int n, int id, bool keep = true) {
         if (lane < 8 * n) T[lane] = cells[(int64_t)child[id] + (lane & 7)];
         wave_lds_sync();
         const V4 *t = T;
@@ -1245,7 +1304,7 @@ struct TilesPeriodic {
                 const real ri = r2 > (real)0 ? rsq_any(r2) : (real)0;
                 return t[j].w * (ri + ewald_eval<real>(c.ep, v, nullptr) * dscale);
             });
-        acc_near += (double)part;
+        if (keep) acc_near += (double)part;
         wave_lds_sync();
     }
     __device__ void finish(const WalkArgs &a, int64_t cell) const { a.phi[cell] = -a.G * (acc_far + acc_near); }
@@ -1258,7 +1317,8 @@ struct PotArgs {
     const int32_t *child;        // node -> first internal cell (bottom nodes)
     const void *cells;           // float4 / double4, internal order
     const LeafInfo *leaves;
-    int64_t n_groups;
+    int64_t n_items;             // wavefronts: 64-cell octants, or 32-cell groups
+    int gcells;
     double G;
     double *phi;
 };
@@ -1269,15 +1329,30 @@ __device__ __forceinline__ int64_t phi_index(const LeafInfo &L, int sub, int lan
     return (int64_t)L.canon * kCellsPerBlock + k * 64 + j * 8 + i;
 }
 
+// One wavefront per 64-cell octant of a group of 64 or more cells (the
+// octants of one group read the same lists), or per 32-cell group (lanes
+// 32-63 idle).  Lane = cell in Morton order.
 template <typename real>
 __global__ __launch_bounds__(256) void potential_kernel(PotArgs a) {
     using V4 = typename Prec<real>::V4;
     __shared__ V4 tile[4][64 * 3];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + w;
-    if (g >= a.n_groups) return;
-    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const int64_t q = (int64_t)blockIdx.x * 4 + w;
+    if (q >= a.n_items) return;
+    int f, sub, cell;
+    int64_t g;
+    if (a.gcells == 32) {
+        g = q;
+        f = (int)(q >> 4);
+        sub = (int)((q & 15) >> 1);
+        cell = (int)(q & 15) * 32 + (lane & 31);
+    } else {
+        f = (int)(q >> 3);
+        sub = (int)(q & 7);
+        g = q / (a.gcells >> 6);
+        cell = sub * 64 + lane;
+    }
     const LeafInfo L = a.leaves[f];
     Tiles<real> S;
     S.T = tile[w];
@@ -1285,9 +1360,8 @@ __global__ __launch_bounds__(256) void potential_kernel(PotArgs a) {
     S.cells = (const V4 *)a.cells;
     S.child = a.child;
     S.own_lo = L.bot_first + sub * 8;
-    S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
-    S.acc_far = 0.0;
-    S.acc_near = 0.0;
+    S.me = S.cells[(int64_t)f * kCellsPerBlock + cell];
+    S.init();
     const int64_t fb = a.far_off[g], fe = a.far_off[g + 1];
     for (int64_t b = fb; b < fe; b += 64) {
         const int n = (int)(fe - b < 64 ? fe - b : 64);
@@ -1299,7 +1373,10 @@ __global__ __launch_bounds__(256) void potential_kernel(PotArgs a) {
         const int n = (int)(ne - b < 8 ? ne - b : 8);
         S.near_tile(lane, n, lane < 8 * n ? a.near_idx[b + (lane >> 3)] : 0);
     }
-    a.phi[phi_index(L, sub, lane)] = -a.G * (S.acc_far + S.acc_near);
+    if (a.gcells == 32 && lane >= 32) return;
+    int i, j, k;
+    demorton9(cell, i, j, k);
+    a.phi[(int64_t)L.canon * kCellsPerBlock + k * 64 + j * 8 + i] = -a.G * (S.acc_far + S.acc_near);
 }
 
 hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_lists *L, double G, int precision,
@@ -1311,10 +1388,11 @@ hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_list
     a.near_idx = L->d_near;
     a.child = g->d_child;
     a.leaves = g->d_leaves;
-    a.n_groups = g->n_groups;
+    a.gcells = g->group_cells;
+    a.n_items = g->group_cells == 32 ? g->n_groups : g->n_units;
     a.G = G;
     a.phi = phi;
-    const int blocks = (int)((g->n_groups + 3) / 4);
+    const int blocks = (int)((a.n_items + 3) / 4);
     if (precision == BH_FP64) {
         a.far_rec = m->d_mom;
         a.cells = m->d_cell64;
@@ -1345,38 +1423,58 @@ hipError_t launch_potential(const bh_grid *g, const bh_moments *m, const bh_list
 constexpr int kFusedDefaultWaves32 = 8;
 constexpr int kFusedDefaultWaves64 = 4;
 
-template <typename real>
+// LDS of one 4-wavefront workgroup.  GM 2 (two 32-cell groups per
+// wavefront) keeps three far and three near buffers per wavefront: entries of
+// both groups, of the first only, of the second only.
+template <typename real, int GM = 1>
 struct FusedSmem {
     using V4 = typename Prec<real>::V4;
     int stack[4][kWalkStackCap];
-    int fbuf[4][128];
-    int nbuf[4][72];
+    int fbuf[4][GM == 2 ? 3 : 1][128];
+    int nbuf[4][GM == 2 ? 3 : 1][72];
     V4 tile[4][64 * 3];
 };
 
-// The wavefront's group: slot q of the dispatch order (groups by decreasing
-// cost of the previous walk, so that the longest start first and the end of
-// the launch is filled with short ones), or q itself; -1 past the end.
-__device__ __forceinline__ int64_t dispatch_group(const WalkArgs &a, int64_t q) {
-    if (q >= a.n_groups) return -1;
+// The wavefront's unit (a 64-cell octant, leaf-major): slot q of the dispatch
+// order (units by decreasing cost of the previous walk, so that the longest
+// start first and the end of the launch is filled with short ones), or q
+// itself; -1 past the end.
+__device__ __forceinline__ int64_t dispatch_unit(const WalkArgs &a, int64_t q) {
+    if (q >= a.n_units) return -1;
     return a.order ? (int64_t)a.order[q] : q;
 }
 
-// algorithmic cost of a group from its counts: 35 flop x 64 cells per far node,
-// 11 flop x 512 pairs per near bottom node
+// algorithmic cost of a wavefront's work from its tile entries: 28 flop x 64
+// cells per far node, 11 flop x 512 pairs per near bottom node
 __device__ __forceinline__ uint32_t group_cost(int nfar, int nnear) {
-    return 35u * 64u * (uint32_t)nfar + 11u * 512u * (uint32_t)nnear;
+    return 28u * 64u * (uint32_t)nfar + 11u * 512u * (uint32_t)nnear;
 }
 
-// one group g of the grid described by a, on wavefront w of the workgroup;
-// TL: the tile evaluator (potential, potential and acceleration, periodic)
-template <typename real, typename TL = Tiles<real>, int MAC = 0>
-__device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w, int lane, FusedSmem<real> &sm) {
+// Moves the entries past the first `used` of a wavefront's buffer to its front.
+__device__ __forceinline__ void buffer_shift(int *B, int used, int &cnt, int lane) {
+    const int rest = cnt - used;
+    const int v = lane < rest ? B[used + lane] : 0;
+    wave_lds_sync();
+    if (lane < rest) B[lane] = v;
+    cnt = rest;
+    wave_lds_sync();
+}
+
+// Octant u of the grid described by a, on wavefront w of the workgroup: walk
+// and sums of the group containing it (GM 1, groups of 64 or more cells) or
+// of the two 32-cell groups it holds (GM 2).  TL: the tile evaluator
+// (potential, potential and acceleration, periodic).
+template <typename real, typename TL = Tiles<real>, int MAC = 0, int GM = 1>
+__device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t u, int w, int lane, FusedSmem<real, GM> &sm) {
     using V4 = typename Prec<real>::V4;
-    const int f = (int)(g >> 3), sub = (int)(g & 7);
+    const int f = (int)(u >> 3), sub = (int)(u & 7);
     const LeafInfo L = a.leaves[f];
-    Walker<real, MAC> W;
-    W.init(a, L, sub, sm.stack[w], lane);
+    const int gpl = groups_per_leaf(a.gcells);
+    const int wpg = GM == 2 ? 1 : (a.gcells >> 6);  // wavefronts per group
+    const int run = GM == 2 ? 2 * sub : sub / wpg;   // (first) group of the octant within the block
+    const int64_t cg0 = (int64_t)L.canon * gpl + run;
+    Walker<real, MAC, GM> W;
+    W.init(a, L, group_box<real>(L, a.gcells, run), cg0, sm.stack[w], lane);
     TL S;
     S.T = sm.tile[w];
     S.rec = (const V4 *)a.far_rec;
@@ -1386,78 +1484,120 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t g, int w,
     S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
     if constexpr (MAC == 2) S.setup(a, L, sub);
     S.init();
-    int *FB = sm.fbuf[w];
-    int *NB = sm.nbuf[w];
-    int fcnt = 0, ncnt = 0, ftot = 0, ntot = 0;
-    bool pending = false;  // a full far tile waits in p0..p2
-    V4 p0, p1, p2;
-    while (W.size > 0) {
-        int id;
-        bool acc, nr;
-        W.step(lane, id, acc, nr);
-        if (pending) {  // loaded before the step: sum it now
+    if constexpr (GM == 1) {
+        int *FB = sm.fbuf[w][0];
+        int *NB = sm.nbuf[w][0];
+        int fcnt = 0, ncnt = 0, ftot = 0, ntot = 0;
+        bool pending = false;  // a full far tile waits in p0..p2
+        V4 p0, p1, p2;
+        while (W.size > 0) {
+            int id, acc, nr;
+            W.step(lane, id, acc, nr);
+            if (pending) {  // loaded before the step: sum it now
+                S.put(lane, p0, p1, p2);
+                wave_lds_sync();
+                S.sum_far(64);
+                pending = false;
+            }
+            const uint64_t mf = __ballot(acc);
+            const uint64_t mn = __ballot(nr);
+            if (acc) FB[fcnt + lane_prefix(mf)] = id;
+            if (nr) NB[ncnt + lane_prefix(mn)] = id;
+            fcnt += __popcll(mf);
+            ncnt += __popcll(mn);
+            ftot += __popcll(mf);
+            ntot += __popcll(mn);
+            wave_lds_sync();
+            if (fcnt >= 64) {  // issue the loads of the next full tile; summed after the next step
+                S.load(FB[lane], p0, p1, p2);
+                pending = true;
+                buffer_shift(FB, 64, fcnt, lane);
+            }
+            while (ncnt >= 8) {
+                S.near_tile(lane, 8, NB[lane >> 3]);
+                buffer_shift(NB, 8, ncnt, lane);
+            }
+        }
+        W.finish(a, lane);
+        if (pending) {
             S.put(lane, p0, p1, p2);
             wave_lds_sync();
             S.sum_far(64);
-            pending = false;
         }
-        const uint64_t mf = __ballot(acc);
-        const uint64_t mn = __ballot(nr);
-        if (acc) FB[fcnt + lane_prefix(mf)] = id;
-        if (nr) NB[ncnt + lane_prefix(mn)] = id;
-        fcnt += __popcll(mf);
-        ncnt += __popcll(mn);
-        ftot += __popcll(mf);
-        ntot += __popcll(mn);
-        wave_lds_sync();
-        if (fcnt >= 64) {  // issue the loads of the next full tile; summed after the next step
-            S.load(FB[lane], p0, p1, p2);
-            pending = true;
-            const int rest = fcnt - 64;
-            int v = lane < rest ? FB[64 + lane] : 0;
-            wave_lds_sync();
-            if (lane < rest) FB[lane] = v;
-            fcnt = rest;
-            wave_lds_sync();
+        if (fcnt >= 64) {  // at most one more full tile can remain
+            S.stage_far(lane, 64, FB[lane]);
+            S.sum_far(64);
+            buffer_shift(FB, 64, fcnt, lane);
         }
-        while (ncnt >= 8) {
-            S.near_tile(lane, 8, NB[lane >> 3]);
-            const int rest = ncnt - 8;
-            int v = lane < rest ? NB[8 + lane] : 0;
-            wave_lds_sync();
-            if (lane < rest) NB[lane] = v;
-            ncnt = rest;
-            wave_lds_sync();
+        if (fcnt > 0) {
+            S.stage_far(lane, fcnt, lane < fcnt ? FB[lane] : 0);
+            S.sum_far(fcnt);
         }
+        if (ncnt > 0) S.near_tile(lane, ncnt, lane < 8 * ncnt ? NB[lane >> 3] : 0);
+        S.finish(a, phi_index(L, sub, lane));
+        if (a.counts && lane == 0 && sub % wpg == 0) {  // one wavefront per group reports its counts
+            a.counts[2 * cg0 + 0] = ftot;
+            a.counts[2 * cg0 + 1] = ntot;
+        }
+        if (a.cost_out && lane == 0) a.cost_out[u] = group_cost(ftot, ntot);
+    } else {
+        // category c: 0 = both groups, 1 = lanes 0-31's group only, 2 = lanes 32-63's only
+        int fcnt[3] = {0, 0, 0}, ncnt[3] = {0, 0, 0}, ftot[3] = {0, 0, 0}, ntot[3] = {0, 0, 0};
+        const bool low = lane < 32;
+        while (W.size > 0) {
+            int id, acc, nr;
+            W.step(lane, id, acc, nr);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const int code = c == 0 ? 3 : c;
+                const uint64_t mf = __ballot(acc == code);
+                const uint64_t mn = __ballot(nr == code);
+                if (acc == code) sm.fbuf[w][c][fcnt[c] + lane_prefix(mf)] = id;
+                if (nr == code) sm.nbuf[w][c][ncnt[c] + lane_prefix(mn)] = id;
+                fcnt[c] += __popcll(mf);
+                ncnt[c] += __popcll(mn);
+                ftot[c] += __popcll(mf);
+                ntot[c] += __popcll(mn);
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const bool keep = c == 0 || (c == 1) == low;
+                int *FB = sm.fbuf[w][c];
+                int *NB = sm.nbuf[w][c];
+                if (fcnt[c] >= 64) {
+                    S.stage_far(lane, 64, FB[lane]);
+                    S.sum_far(64, keep);
+                    buffer_shift(FB, 64, fcnt[c], lane);
+                }
+                while (ncnt[c] >= 8) {
+                    S.near_tile(lane, 8, NB[lane >> 3], keep);
+                    buffer_shift(NB, 8, ncnt[c], lane);
+                }
+            }
+        }
+        W.finish(a, lane);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const bool keep = c == 0 || (c == 1) == low;
+            int *FB = sm.fbuf[w][c];
+            int *NB = sm.nbuf[w][c];
+            if (fcnt[c] > 0) {
+                S.stage_far(lane, fcnt[c], lane < fcnt[c] ? FB[lane] : 0);
+                S.sum_far(fcnt[c], keep);
+            }
+            if (ncnt[c] > 0) S.near_tile(lane, ncnt[c], lane < 8 * ncnt[c] ? NB[lane >> 3] : 0, keep);
+        }
+        S.finish(a, phi_index(L, sub, lane));
+        if (a.counts && lane == 0) {
+            a.counts[2 * cg0 + 0] = ftot[0] + ftot[1];
+            a.counts[2 * cg0 + 1] = ntot[0] + ntot[1];
+            a.counts[2 * cg0 + 2] = ftot[0] + ftot[2];
+            a.counts[2 * cg0 + 3] = ntot[0] + ntot[2];
+        }
+        if (a.cost_out && lane == 0)
+            a.cost_out[u] = group_cost(ftot[0] + ftot[1] + ftot[2], ntot[0] + ntot[1] + ntot[2]);
     }
-    W.finish(a, lane);
-    if (pending) {
-        S.put(lane, p0, p1, p2);
-        wave_lds_sync();
-        S.sum_far(64);
-    }
-    if (fcnt >= 64) {  // at most one more full tile can remain
-        S.stage_far(lane, 64, FB[lane]);
-        S.sum_far(64);
-        const int rest = fcnt - 64;
-        int v = lane < rest ? FB[64 + lane] : 0;
-        wave_lds_sync();
-        if (lane < rest) FB[lane] = v;
-        fcnt = rest;
-        wave_lds_sync();
-    }
-    if (fcnt > 0) {
-        S.stage_far(lane, fcnt, lane < fcnt ? FB[lane] : 0);
-        S.sum_far(fcnt);
-    }
-    if (ncnt > 0) S.near_tile(lane, ncnt, lane < 8 * ncnt ? NB[lane >> 3] : 0);
-    S.finish(a, phi_index(L, sub, lane));
-    if (a.counts && lane == 0) {
-        const int64_t cg = (int64_t)L.canon * 8 + sub;
-        a.counts[2 * cg + 0] = ftot;
-        a.counts[2 * cg + 1] = ntot;
-    }
-    if (a.cost_out && lane == 0) a.cost_out[g] = group_cost(ftot, ntot);
 }
 
 // Attach the schedule to a single-grid fused walk: dispatch in the order that
@@ -1470,26 +1610,31 @@ static hipError_t attach_schedule(const bh_grid *, const bh_moments *m, WalkArgs
     return hipSuccess;
 }
 
-template <typename real, int WAVES>
+// Wavefronts of a single-grid fused launch: one per 64-cell octant, four per
+// workgroup; GM 2 for 32-cell groups (two per wavefront).
+static dim3 fused_blocks(const bh_grid *g) { return dim3((unsigned)((g->n_units + 3) / 4)); }
+static int fused_gm(const bh_grid *g) { return g->group_cells == 32 ? 2 : 1; }
+
+template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_kernel(WalkArgs a) {
-    __shared__ FusedSmem<real> sm;
+    __shared__ FusedSmem<real, GM> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
-    if (g < 0) return;
-    fused_group<real>(a, g, w, lane, sm);
+    const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
+    if (u < 0) return;
+    fused_group<real, Tiles<real>, 0, GM>(a, u, w, lane, sm);
 }
 
 // The fused walk with another opening test and/or far-field order (the
 // paper's own choices, for comparison); otherwise as walk_potential_kernel.
-template <typename real, int WAVES, int MAC, int ORDER>
+template <typename real, int WAVES, int MAC, int ORDER, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_opts_kernel(WalkArgs a) {
-    __shared__ FusedSmem<real> sm;
+    __shared__ FusedSmem<real, GM> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
-    if (g < 0) return;
-    fused_group<real, Tiles<real, ORDER>, MAC>(a, g, w, lane, sm);
+    const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
+    if (u < 0) return;
+    fused_group<real, Tiles<real, ORDER>, MAC, GM>(a, u, w, lane, sm);
 }
 
 hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
@@ -1500,8 +1645,14 @@ hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, dou
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;
-    const dim3 grid((unsigned)((g->n_groups + 3) / 4)), block(256);
-#define BH_OPTS(T, W, M, O) hipLaunchKernelGGL((walk_potential_opts_kernel<T, W, M, O>), grid, block, 0, s, a)
+    const dim3 grid = fused_blocks(g), block(256);
+#define BH_OPTS(T, W, M, O)                                                                          \
+    do {                                                                                             \
+        if (fused_gm(g) == 2)                                                                        \
+            hipLaunchKernelGGL((walk_potential_opts_kernel<T, W, M, O, 2>), grid, block, 0, s, a); \
+        else                                                                                         \
+            hipLaunchKernelGGL((walk_potential_opts_kernel<T, W, M, O, 1>), grid, block, 0, s, a); \
+    } while (0)
     if (precision == BH_FP64) {
         if (mac == BH_MAC_GROUP_BOX && order == 2) BH_OPTS(double, kFusedDefaultWaves64, 1, 2);
         else if (mac == BH_MAC_GROUP_BOX) BH_OPTS(double, kFusedDefaultWaves64, 1, 0);
@@ -1519,14 +1670,14 @@ hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, dou
 // (MAC mode 2), the sums through the periodic Green's function table
 // (TilesPeriodic).
 constexpr int kPeriodicWaves32 = 4, kPeriodicWaves64 = 2;
-template <typename real, int WAVES>
+template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_periodic_kernel(WalkArgs a) {
-    __shared__ FusedSmem<real> sm;
+    __shared__ FusedSmem<real, GM> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
-    if (g < 0) return;
-    fused_group<real, TilesPeriodic<real>, 2>(a, g, w, lane, sm);
+    const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
+    if (u < 0) return;
+    fused_group<real, TilesPeriodic<real>, 2, GM>(a, u, w, lane, sm);
 }
 
 hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
@@ -1540,25 +1691,32 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     a.node_s = m->d_s;
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;
-    const dim3 grid((unsigned)((g->n_groups + 3) / 4)), block(256);
-    if (precision == BH_FP64)
-        hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32>), grid, block, 0, s, a);
+    const dim3 grid = fused_blocks(g), block(256);
+    if (precision == BH_FP64) {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64, 1>), grid, block, 0, s, a);
+    } else {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 1>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
 // walk_potential_kernel with each group's theta read from an array (the
 // learned-theta step's walk, after the inference kernel): a kernel of its own
 // name, so that profiles tell per-group-theta walks from fixed-theta ones.
-template <typename real, int WAVES>
+template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_theta_kernel(WalkArgs a) {
-    __shared__ FusedSmem<real> sm;
+    __shared__ FusedSmem<real, GM> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
-    if (g < 0) return;
-    fused_group<real>(a, g, w, lane, sm);
+    const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
+    if (u < 0) return;
+    fused_group<real, Tiles<real>, 0, GM>(a, u, w, lane, sm);
 }
 
 hipError_t launch_walk_potential_theta(const bh_grid *g, const bh_moments *m, const float *theta_group,
@@ -1566,13 +1724,18 @@ hipError_t launch_walk_potential_theta(const bh_grid *g, const bh_moments *m, co
     WalkArgs a = fused_args(g, m, 1.0, theta_group, precision, G, phi, counts, m->walk_epoch);
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;
-    const int blocks = (int)((g->n_groups + 3) / 4);
-    if (precision == BH_FP64)
-        hipLaunchKernelGGL((walk_potential_theta_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0,
-                           s, a);
-    else
-        hipLaunchKernelGGL((walk_potential_theta_kernel<float, kFusedDefaultWaves32>), dim3(blocks), dim3(256), 0,
-                           s, a);
+    const dim3 grid = fused_blocks(g), block(256);
+    if (precision == BH_FP64) {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_potential_theta_kernel<double, kFusedDefaultWaves64, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_potential_theta_kernel<double, kFusedDefaultWaves64, 1>), grid, block, 0, s, a);
+    } else {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_potential_theta_kernel<float, kFusedDefaultWaves32, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_potential_theta_kernel<float, kFusedDefaultWaves32, 1>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -1580,14 +1743,14 @@ hipError_t launch_walk_potential_theta(const bh_grid *g, const bh_moments *m, co
 // the potential kernel, hence a smaller register budget per wave.
 constexpr int kAccelWaves32 = 6;
 constexpr int kAccelWaves64 = 4;
-template <typename real, int WAVES>
+template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_accel_kernel(WalkArgs a) {
-    __shared__ FusedSmem<real> sm;
+    __shared__ FusedSmem<real, GM> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t g = dispatch_group(a, (int64_t)blockIdx.x * 4 + w);
-    if (g < 0) return;
-    fused_group<real, TilesAcc<real>>(a, g, w, lane, sm);
+    const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
+    if (u < 0) return;
+    fused_group<real, TilesAcc<real>, 0, GM>(a, u, w, lane, sm);
 }
 
 hipError_t launch_walk_accel(const bh_grid *g, const bh_moments *m, double theta, const float *theta_group,
@@ -1596,11 +1759,18 @@ hipError_t launch_walk_accel(const bh_grid *g, const bh_moments *m, double theta
     a.acc = acc;
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;
-    const int blocks = (int)((g->n_groups + 3) / 4);
-    if (precision == BH_FP64)
-        hipLaunchKernelGGL((walk_accel_kernel<double, kAccelWaves64>), dim3(blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((walk_accel_kernel<float, kAccelWaves32>), dim3(blocks), dim3(256), 0, s, a);
+    const dim3 grid = fused_blocks(g), block(256);
+    if (precision == BH_FP64) {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_accel_kernel<double, kAccelWaves64, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_accel_kernel<double, kAccelWaves64, 1>), grid, block, 0, s, a);
+    } else {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_accel_kernel<float, kAccelWaves32, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_accel_kernel<float, kAccelWaves32, 1>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -1613,7 +1783,7 @@ template <typename real, int WAVES>
 __global__ __launch_bounds__(256, WAVES) void batch_walk_potential_kernel(
     const WalkArgs *__restrict__ grids, const int2 *__restrict__ order, int64_t total,
     unsigned long long *__restrict__ counter) {
-    __shared__ FusedSmem<real> sm;
+    __shared__ FusedSmem<real, 1> sm;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     while (true) {
@@ -1626,7 +1796,7 @@ __global__ __launch_bounds__(256, WAVES) void batch_walk_potential_kernel(
         q = ((unsigned long long)qhi << 32) | qlo;
         if (q >= (unsigned long long)total) break;
         const int2 item = order[q];
-        fused_group<real>(grids[item.x], item.y, w, lane, sm);
+        fused_group<real, Tiles<real>, 0, 1>(grids[item.x], item.y, w, lane, sm);
     }
 }
 
@@ -1647,11 +1817,18 @@ hipError_t launch_walk_potential(const bh_grid *g, const bh_moments *m, double t
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;
-    const int blocks = (int)((g->n_groups + 3) / 4);
-    if (precision == BH_FP64)
-        hipLaunchKernelGGL((walk_potential_kernel<double, kFusedDefaultWaves64>), dim3(blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((walk_potential_kernel<float, kFusedDefaultWaves32>), dim3(blocks), dim3(256), 0, s, a);
+    const dim3 grid = fused_blocks(g), block(256);
+    if (precision == BH_FP64) {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_potential_kernel<double, kFusedDefaultWaves64, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_potential_kernel<double, kFusedDefaultWaves64, 1>), grid, block, 0, s, a);
+    } else {
+        if (fused_gm(g) == 2)
+            hipLaunchKernelGGL((walk_potential_kernel<float, kFusedDefaultWaves32, 2>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((walk_potential_kernel<float, kFusedDefaultWaves32, 1>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

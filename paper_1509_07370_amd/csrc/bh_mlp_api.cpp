@@ -47,6 +47,7 @@ int bh_group_features(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, float 
     if (rc) return rc;
     if (!g || !m || !feat) return fail(ctx, BH_EINVAL, "grid, moments or feat_dev is NULL");
     if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (g->group_cells != bh::kGroupCells) return fail(ctx, BH_EINVAL, "the network's features need 64-cell groups");
     HIPX(ctx, bh::launch_features(g, m, feat, ctx->stream), "features kernel");
     return BH_OK;
 }
@@ -55,6 +56,7 @@ int bh_group_rms_error(bh_ctx *ctx, const bh_grid *g, const double *phi, const d
     int rc = require_gpu(ctx);
     if (rc) return rc;
     if (!g || !phi || !ref || !rms) return fail(ctx, BH_EINVAL, "grid, phi_dev, ref_dev or rms_dev is NULL");
+    if (g->group_cells != bh::kGroupCells) return fail(ctx, BH_EINVAL, "per-group errors need 64-cell groups");
     HIPX(ctx, bh::launch_group_rms(g, phi, ref, rms, ctx->stream), "group error kernel");
     return BH_OK;
 }
@@ -148,6 +150,7 @@ int bh_learned_walk_potential(bh_ctx *ctx, const bh_grid *g, const bh_moments *m
     if (rc) return rc;
     if (!g || !m || !net || !phi) return fail(ctx, BH_EINVAL, "grid, moments, network or phi_dev is NULL");
     if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (g->group_cells != bh::kGroupCells) return fail(ctx, BH_EINVAL, "the network's features need 64-cell groups");
     if (precision != BH_FP64 && precision != BH_FP32) return fail(ctx, BH_EINVAL, "precision must be BH_FP64 or BH_FP32");
     if (!std::isfinite(shift)) return fail(ctx, BH_EINVAL, "theta_shift must be finite");
     if (!std::isfinite(G)) return fail(ctx, BH_EINVAL, "G must be finite");
@@ -165,6 +168,7 @@ int bh_theta_infer(bh_ctx *ctx, const bh_grid *g, const bh_moments *m, const bh_
     if (rc) return rc;
     if (!g || !m || !net || !theta) return fail(ctx, BH_EINVAL, "grid, moments, network or theta_dev is NULL");
     if (m->grid != g) return fail(ctx, BH_ESTATE, "moments were built for another grid");
+    if (g->group_cells != bh::kGroupCells) return fail(ctx, BH_EINVAL, "the network's features need 64-cell groups");
     if (!std::isfinite(shift)) return fail(ctx, BH_EINVAL, "theta_shift must be finite");
     HIPX(ctx, bh::launch_theta_infer(g, m, net, shift, theta, ctx->stream), "theta inference kernel");
     return BH_OK;

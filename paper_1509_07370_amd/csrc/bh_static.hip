@@ -45,7 +45,7 @@ struct StaticLayout {
 
 StaticLayout static_layout(const bh_grid *g) {
     const size_t nn = (size_t)g->topo.n_nodes, nc = (size_t)g->n_cells, nl = g->topo.leaves.size();
-    const size_t ng = (size_t)g->n_groups;
+    const size_t nu = (size_t)g->n_units;
     StaticLayout L{};
     size_t o = 0;
     L.mom = o;
@@ -65,7 +65,7 @@ StaticLayout static_layout(const bh_grid *g) {
     L.cell32 = o;
     o = align256(o + nc * sizeof(float4));
     L.cost = o;
-    o = align256(o + ng * sizeof(uint32_t));
+    o = align256(o + nu * sizeof(uint32_t));
     L.flags = o;
     o = align256(o + 2 * sizeof(int));
     L.total = o;

@@ -1,6 +1,7 @@
 """bench.py's contract on the host: more than one GPU is refused before any
 GPU is touched, and the algorithmic work behind `roofline.achieved` follows
-the per-pair count (35 flop per cell and far node, 11 per near cell pair,
+the per-pair count (28 flop per cell and far node, as the fp32 far term
+computes it, 11 per near cell pair,
 the group's own 64 self pairs excluded)."""
 import os
 import subprocess
@@ -24,4 +25,4 @@ def test_algorithmic_work_count():
     # group 1: two far nodes
     flops, far, near = bench.algorithmic_flops([1, 2], [1, 0])
     assert far == 64 * 3 and near == 512 - 64
-    assert flops == 35 * 192 + 11 * 448
+    assert flops == 28 * 192 + 11 * 448

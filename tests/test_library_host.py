@@ -83,7 +83,8 @@ def test_malformed_grids_are_rejected(hctx):
     a = dict(level=g.level.copy(), lo=g.lo.copy(), parent=g.parent.copy(), child=g.child.copy(),
              is_leaf=g.is_leaf.copy())
     _expect_einval(hctx, **a, nb=16, match="nb must be 8")
-    _expect_einval(hctx, **a, gc=32, match="group_cells")
+    _expect_einval(hctx, **a, gc=48, match="group_cells")
+    _expect_einval(hctx, **a, gc=1024, match="group_cells")
     b = {k: v.copy() for k, v in a.items()}
     b["lo"][3, 0] += 1e-3
     _expect_einval(hctx, **b, match="lattice")
