@@ -272,12 +272,207 @@ def run_batched(args, dev):
     B.bh_ctx_destroy(ctx)
 
 
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / reps
+
+
+def _sample(n, frac, seed, dev, minimum=1000):
+    import torch
+    rng = np.random.default_rng(seed)
+    return torch.tensor(np.sort(rng.choice(n, min(n, max(minimum, int(frac * n))), replace=False)),
+                        dtype=torch.int64, device=dev)
+
+
+def cpu_oracle(grid, theta_groups, frac_all=1.0, frac_one=0.125, reps=3, seed=0, group_cells=64):
+    """The oracle (fp64, same per-group theta, same groups) on the host: the upward
+    pass (moments) plus the walk and sums, the topology excluded as on the GPU.
+    Median of `reps` runs on the OpenMP runtime's default thread count (all
+    cores given to the process) over a seeded fraction `frac_all` of the groups,
+    and on one thread over a fraction `frac_one`; the walk and sums of a
+    sample are scaled to the whole grid."""
+    from oracle import OracleTree
+    from oracle.oracle import get_threads, set_threads
+    t = OracleTree(grid)
+    t.set_density()
+    ng = grid.ncells // group_cells
+    th = np.broadcast_to(np.asarray(theta_groups, np.float64), (ng,)).copy()
+    out = {}
+    default = get_threads()
+    rng = np.random.default_rng(seed)
+    for label, threads, frac in (("all_cores", default, frac_all), ("one_core", 1, frac_one)):
+        used = set_threads(threads)
+        gs = np.arange(ng) if frac >= 1.0 else np.sort(rng.choice(ng, max(1, int(frac * ng)), replace=False))
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            t.lib.ot_moments(t.h)
+            t1 = time.perf_counter()
+            t.solve_groups(gs, group_cells=group_cells, theta=th)
+            t2 = time.perf_counter()
+            times.append((t1 - t0) + (t2 - t1) * ng / len(gs))
+        sec = float(np.median(times))
+        out[label] = dict(value=grid.ncells / sec / 1e6, seconds=sec, cores=used, groups_sampled=int(len(gs)),
+                          runs=[float(x) for x in times])
+    set_threads(default)
+    return out
+
+
+def config_lines(dev, log, cpu=True):
+    """Throughput of the opening (uniform sphere) and cloud-core configurations at
+    theta 0.5, fixed, beside the oracle, with their errors against the direct sum."""
+    import torch
+    from amr_inputs import cloud_core, uniform_sphere
+    from paper_1509_07370_amd import binding as B
+    from paper_1509_07370_amd.solver import BarnesHut
+    out = {}
+    for name, make, full in (("uniform_sphere", lambda: uniform_sphere(), True),
+                             ("cloud_core", lambda: cloud_core(), False)):
+        t0 = time.time()
+        g = make()
+        bh = BarnesHut(g, device=0)
+        rho = torch.tensor(g.rho, device=dev)
+        phi = torch.empty_like(rho)
+        n = g.ncells
+        tg = torch.arange(n, device=dev, dtype=torch.int64) if full else _sample(n, 0.01, 17, dev)
+        bh.build_moments(rho)
+        d = bh.direct(tg)
+        rec = dict(cells=n, leaf_blocks=g.nleaf, theta=0.5,
+                   error_sample="all cells" if full else "1%% of cells (%d)" % tg.numel())
+        for prec, key in ((B.BH_FP32, "fp32"), (B.BH_FP64, "fp64")):
+            def step(prec=prec):
+                bh.build_moments(rho)
+                B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, None, prec, 1.0, phi, None)
+            step()
+            rel = (phi.reshape(-1).index_select(0, tg) - d) / d
+            ms = _timed(step, 20 if n < 1e6 else 5)
+            rec[key] = dict(ms_per_step=ms, mcells_per_s=n / ms / 1e3, rms_rel_err=float(torch.sqrt((rel * rel).mean())),
+                            max_rel_err=float(rel.abs().max()))
+        if cpu:  # the whole cloud core takes minutes on the host: 1% of its groups on all cores, 0.1% on one
+            rec["cpu_oracle"] = cpu_oracle(g, 0.5, frac_all=1.0 if full else 0.01, frac_one=1.0 if full else 0.001)
+        log("%s: %d cells, fp32 %.1f Mcells/s (rms %.2e), fp64 %.1f Mcells/s; %.1f s" % (
+            name, n, rec["fp32"]["mcells_per_s"], rec["fp32"]["rms_rel_err"], rec["fp64"]["mcells_per_s"],
+            time.time() - t0))
+        out[name] = rec
+        bh.close()
+        del rho, phi, d
+    return out
+
+
+SMALL_GRIDS = 128
+SMALL_SEED = 9000
+
+
+def small_grids():
+    """Many small uneven grids: seeded Plummer mixes on 2^3 base blocks refined up
+    to 3 levels, leaf-block targets log-uniform in [100, 500] (the low end of the
+    batched configuration, where one grid alone fills a fraction of the chip)."""
+    import math
+    from amr_inputs import plummer_mix
+    rng = np.random.default_rng(SMALL_SEED)
+    targets = np.exp(rng.uniform(math.log(100), math.log(500), SMALL_GRIDS)).round().astype(int)
+    return [plummer_mix(SMALL_SEED + k, n_target_blocks=int(targets[k]), nbase=2, max_level=3)
+            for k in range(SMALL_GRIDS)]
+
+
+def batched_small(dev, log, steps=50):
+    """One persistent launch (replayed from a captured graph) against separate
+    single-grid solves, on SMALL_GRIDS small grids at the largest theta whose
+    1%-sampled RMS error meets the gate on every grid."""
+    import torch
+    from paper_1509_07370_amd import binding as B
+    from paper_1509_07370_amd import learned_theta as LT
+    t0 = time.time()
+    grids = small_grids()
+    cells = np.array([g.ncells for g in grids], np.int64)
+    ctx = B.bh_ctx_create(0)
+    handles = [B.bh_grid_create_from(ctx, g) for g in grids]
+    batch = B.bh_batch_create(ctx, handles)
+    rho = [torch.tensor(g.rho, device=dev) for g in grids]
+    phi = [torch.empty_like(r) for r in rho]
+    nblk = [g.nleaf for g in grids]
+    del grids
+    samples, direct = [], []
+    for k, (h, r) in enumerate(zip(handles, rho)):
+        m = B.bh_build_moments(ctx, h, r)
+        tg = _sample(int(cells[k]), 0.01, k, dev, minimum=200)
+        d = torch.empty(tg.numel(), dtype=torch.float64, device=dev)
+        B.bh_direct(ctx, h, m, tg, 1.0, d)
+        torch.cuda.synchronize()
+        B.bh_moments_destroy(m)
+        samples.append(tg)
+        direct.append(d)
+
+    def worst():
+        w = 0.0
+        for p_, tg, d in zip(phi, samples, direct):
+            rel = (p_.reshape(-1).index_select(0, tg) - d) / d
+            w = max(w, float(torch.sqrt((rel * rel).mean())))
+        return w
+
+    theta = LT.FALLBACK_THETA
+    for th in LT.THETA_GRID[::-1]:
+        B.bh_batch_solve(ctx, batch, rho, phi, float(th), None, B.BH_FP32, 1.0)
+        if worst() <= RMS_GATE:
+            theta = float(th)
+            break
+    ms_list = [B.bh_build_moments(ctx, h, r) for h, r in zip(handles, rho)]
+
+    def separate():
+        for h, r, p_, m in zip(handles, rho, phi, ms_list):
+            B.bh_build_moments(ctx, h, r, m)
+            B.bh_walk_potential(ctx, h, m, theta, None, B.BH_FP32, 1.0, p_, None)
+    ms_sep = _timed(separate, 10)
+    for m in ms_list:
+        B.bh_moments_destroy(m)
+    ms_eager = _timed(lambda: B.bh_batch_solve(ctx, batch, rho, phi, theta, None, B.BH_FP32, 1.0), 10)
+    best, best_ms, table = B.bh_batch_autotune(ctx, batch, rho, phi, theta, None, B.BH_FP32, 1.0, reps=3)
+    B.bh_batch_capture(ctx, batch, rho, phi, theta, None, B.BH_FP32, 1.0)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        B.bh_batch_replay(ctx, batch)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        B.bh_batch_replay(ctx, batch)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = ev0.elapsed_time(ev1) / steps
+    B.bh_batch_check(ctx, batch)
+    w = worst()
+    n = int(cells.sum())
+    out = dict(grids=SMALL_GRIDS, cells=n, leaf_blocks_min=int(min(nblk)), leaf_blocks_max=int(max(nblk)),
+               leaf_blocks_median=int(np.median(nblk)), theta=theta, worst_grid_sampled_rms=w,
+               ms_separate_solves=ms_sep, ms_batched_eager=ms_eager, ms_batched_graph_tuned=ms_graph,
+               mcells_per_s_separate=n / ms_sep / 1e3, mcells_per_s_batched=n / ms_graph / 1e3,
+               speedup_batched_vs_separate=ms_sep / ms_graph, autotune_best=best,
+               workload="%d Plummer-mix grids (seeds %d..%d, 2^3 base blocks, <= 3 levels, %d..%d leaf blocks), "
+                        "fp32 walk, fixed theta" % (SMALL_GRIDS, SMALL_SEED, SMALL_SEED + SMALL_GRIDS - 1,
+                                                    min(nblk), max(nblk)))
+    log("batched small grids: %d grids, %d cells, theta %.2f: separate %.3f ms, batched graph %.3f ms (%.2fx), "
+        "eager %.3f ms; %.1f s" % (SMALL_GRIDS, n, theta, ms_sep, ms_graph, ms_sep / ms_graph, ms_eager,
+                                   time.time() - t0))
+    B.bh_batch_destroy(batch)
+    for h in handles:
+        B.bh_grid_destroy(h)
+    B.bh_ctx_destroy(ctx)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (sphere, cloud core, small batched grids)")
     ap.add_argument("--profile-only", action="store_true",
                     help="time the headline step only (for profiler runs)")
     ap.add_argument("--workload", choices=("maclaurin", "batched"), default="maclaurin")
@@ -533,21 +728,47 @@ def main():
                 "%.3f ms fp64" % (th_p, e_p, ms32, periodic["mcells_per_s"], pk_ms, ms64))
         B.bh_ewald_destroy(table)
 
+    # ---- group size and theta chosen together by the autotuner under the gate (1% sampled direct sums)
+    group_size = None
+    if not args.profile_only:
+        from paper_1509_07370_amd.tune import tune_group_size
+        tg = _sample(ncells, 0.01, 21, dev)
+        bh.build_moments(rho)
+        best_g, table_g = tune_group_size(grid, rho, RMS_GATE, sample=tg, direct=bh.direct(tg), log=log)
+        group_size = dict(best=best_g, table=[dict(r, mcells_per_s=(ncells / r["ms"] / 1e3) if r["ms"] else None)
+                                              for r in table_g],
+                          note="largest theta of the grid meeting the gate on a 1% sample, per group size; "
+                               "moments + fused walk and sums, fp32")
+
+    configs = None
+    batched = None
+    if not args.profile_only and not args.no_configs:
+        configs = config_lines(dev, log, cpu=not args.no_cpu_baseline)
+        batched = batched_small(dev, log)
+
     cpu = None
     if not args.no_cpu_baseline and not args.profile_only:
-        from oracle import OracleTree
         th = theta_g.cpu().numpy().astype(np.float64)
-        t0 = time.perf_counter()
-        ot = OracleTree(grid)
-        ot.moments()
-        ot.walk(64, th)
-        ot.potential()
-        cpu_s = time.perf_counter() - t0
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = dict(value=ncells / cpu_s / 1e6, unit="Mcells/s", cores=threads, kind="oracle",
-                   sample="whole workload (%d cells): fp64 oracle tree + moments + walk + sum with the same "
-                          "per-group theta, %.2f s" % (ncells, cpu_s))
-        log("cpu oracle %.2f s on %d threads" % (cpu_s, threads))
+        c = cpu_oracle(grid, th, frac_all=1.0, frac_one=0.125)
+        a, o = c["all_cores"], c["one_core"]
+        cpu = dict(value=a["value"], unit="Mcells/s", cores=a["cores"], kind="oracle",
+                   sample="whole workload (%d cells): fp64 oracle upward pass + walk + sum with the same per-group "
+                          "theta and groups (topology excluded, as on the GPU), median of 3 on the OpenMP runtime's "
+                          "%d threads; one thread: 1/8 of the groups (seeded), scaled, median of 3" % (
+                              ncells, a["cores"]),
+                   seconds=a["seconds"], one_core=dict(value=o["value"], cores=o["cores"], seconds=o["seconds"]))
+        log("cpu oracle: %.2f Mcells/s on %d threads, %.3f Mcells/s on one" % (a["value"], a["cores"], o["value"]))
+
+    # ---- the GPU direct sum (the error reference of every gate) against the oracle's on 1000 targets
+    direct_check = None
+    if not args.no_cpu_baseline and not args.profile_only:
+        from oracle import OracleTree
+        tg = _sample(ncells, 0.0, 23, dev, minimum=1000)
+        bh.build_moments(rho)
+        gd = bh.direct(tg).cpu().numpy()
+        od = OracleTree(grid).direct(tg.cpu().numpy())
+        direct_check = dict(targets=int(tg.numel()), max_rel_diff=float(np.max(np.abs(gd - od) / np.abs(od))))
+        log("direct sum vs oracle on %d targets: max rel diff %.2e" % (tg.numel(), direct_check["max_rel_diff"]))
 
     out = {
         "metric": "Mcells/s potential eval at RMS rel err <=1e-3 vs direct sum; learned-theta vs fixed-theta",
@@ -580,6 +801,10 @@ def main():
                      "far_interactions": far_int, "near_pairs": near_pairs,
                      "achieved_naive_far_count": (flops + (F_FAR_NAIVE - F_FAR) * far_int) / (pot_ms * 1e-3) / 1e12},
         "cpu_baseline": cpu,
+        "group_size": group_size,
+        "configs": configs,
+        "batched_small_grids": batched,
+        "direct_crosscheck": direct_check,
         "topology_ms": topo_ms,
         "sweep": sweep,
     }

@@ -54,6 +54,7 @@
  * in units of its own edge.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1210,3 +1211,8 @@ void ot_node_far_periodic(const otree *t, int n, const double *p, double *out) {
     out[2] = qh / 6.0;
     out[3] = 2.0 * pi / (3.0 * L * L * L) * a->S;
 }
+
+/* Threads of the OpenMP parallel regions (for timing the oracle on a given
+ * number of host cores): set, and read back what the runtime will use. */
+void ot_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int ot_get_threads(void) { return omp_get_max_threads(); }

@@ -77,6 +77,8 @@ def _load():
         lib.ot_potential_lists.restype = ctypes.c_int
         lib.ot_potential_lists.argtypes = [P, ctypes.c_int, P, P, P, P, ctypes.c_double, ctypes.c_int, P]
         lib.ot_direct.argtypes = [P, P, i64, ctypes.c_double, P]
+        lib.ot_set_threads.argtypes = [ctypes.c_int]
+        lib.ot_get_threads.restype = ctypes.c_int
         lib.ot_solve_groups.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                         P, P]
         lib.ot_cells.argtypes = [P, P, P, P, P]
@@ -99,6 +101,17 @@ def _load():
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP regions; returns what the runtime reports it will use."""
+    lib = _load()
+    lib.ot_set_threads(int(n))
+    return int(lib.ot_get_threads())
+
+
+def get_threads():
+    return int(_load().ot_get_threads())
 
 
 def make_key(depth, ix, iy, iz):
