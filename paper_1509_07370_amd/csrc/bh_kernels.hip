@@ -608,7 +608,7 @@ struct Walker {
     // One step.  Per lane: id of the tested node, and whether it was accepted
     // (far) or is a rejected bottom node (near) -- for GM 2 as masks of the
     // two groups.  Opened nodes are pushed.
-    __device__ void step(int lane, int &id, int &acc, int &nr) {
+    __device__ void step(int lane, int &id, int &acc, int &nr, int &cid) {
         const int k = size <= k8 ? (size < 8 ? size : 8) : 1;
         const int slot = lane >> 3;
         const bool active = slot < k;
@@ -627,6 +627,7 @@ struct Walker {
         wave_lds_sync();
         acc = 0;
         nr = 0;
+        cid = 0;
         bool op = false;
         int ch = 0;
         if (active) {
@@ -649,9 +650,10 @@ struct Walker {
                 acc = fm;
                 const int om = mask & ~fm;
                 if (om) {
-                    if (r.flags & FLAG_BOTTOM)
+                    if (r.flags & FLAG_BOTTOM) {
                         nr = om;
-                    else {
+                        cid = r.child;  // a bottom node's first cell (internal order)
+                    } else {
                         op = true;
                         ch = GM == 2 ? r.child * 4 + om : r.child;
                     }
@@ -700,8 +702,8 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a) {
     }
     int nf = 0, nn = 0;
     while (W.size > 0) {
-        int id, acc, nr;
-        W.step(lane, id, acc, nr);
+        int id, acc, nr, cid;
+        W.step(lane, id, acc, nr, cid);
         const uint64_t mf = __ballot(acc);
         const uint64_t mn = __ballot(nr);
         if (FILL) {
@@ -1053,15 +1055,37 @@ struct Tiles {
         if (keep) acc_far += (double)part;
         wave_lds_sync();
     }
-    // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]
-    __device__ void near_tile(int lane, int n, int id, bool keep = true) {
+    // A full near tile staged by direct-to-LDS loads (fp32 records: 16 bytes
+    // per lane, global_load_lds_dwordx4): lane l's cell lands in T[l] without
+    // passing through registers, so the loads stay in flight during the next
+    // walk step.  near_issue starts them and returns whether the tile holds one
+    // of the wavefront's own cells; near_finish waits for them and sums.
+    static constexpr bool kNearAsync = sizeof(real) == 4;
+    __device__ bool near_issue(int lane, int cid) {
+        const bool own = (unsigned)(cid - own_lo) < 64u;
+        __builtin_amdgcn_global_load_lds((const void *)(cells + (int64_t)cid + (lane & 7)),
+                                         (__attribute__((address_space(3))) void *)T, 16, 0, 0);
+        return __ballot(own) != 0;
+    }
+    __device__ void near_finish(bool any_own) {
+        __builtin_amdgcn_s_waitcnt(0);
+        wave_lds_sync();
+        near_sum(8, any_own, true);
+    }
+    // up to 8 bottom nodes given by their first cell (internal order); lane l
+    // holds that of node l >> 3.  own_lo: the wavefront's first cell, so a tile
+    // holding one of its 64 cells takes the self-pair select.
+    __device__ void near_tile(int lane, int n, int cid, bool keep = true) {
         bool own = false;
         if (lane < 8 * n) {
-            own = (unsigned)(id - own_lo) < 8u;
-            T[lane] = cells[(int64_t)child[id] + (lane & 7)];
+            own = (unsigned)(cid - own_lo) < 64u;
+            T[lane] = cells[(int64_t)cid + (lane & 7)];
         }
         const bool any_own = __ballot(own) != 0;
         wave_lds_sync();
+        near_sum(n, any_own, keep);
+    }
+    __device__ void near_sum(int n, bool any_own, bool keep) {
         real part = 0;
         if (!any_own)
             for (int j = 0; j < 8 * n; j++) part = near_pair(me.x, me.y, me.z, T[j], part);
@@ -1079,6 +1103,7 @@ struct Tiles {
 template <typename real>
 struct TilesAcc {
     using V4 = typename Prec<real>::V4;
+    static constexpr bool kNearAsync = false;
     V4 *T;
     const V4 *rec;
     const V4 *cells;
@@ -1119,11 +1144,11 @@ struct TilesAcc {
         }
         wave_lds_sync();
     }
-    __device__ void near_tile(int lane, int n, int id, bool keep = true) {
+    __device__ void near_tile(int lane, int n, int cid, bool keep = true) {
         bool own = false;
         if (lane < 8 * n) {
-            own = (unsigned)(id - own_lo) < 8u;
-            T[lane] = cells[(int64_t)child[id] + (lane & 7)];
+            own = (unsigned)(cid - own_lo) < 64u;
+            T[lane] = cells[(int64_t)cid + (lane & 7)];
         }
         const bool any_own = __ballot(own) != 0;
         wave_lds_sync();
@@ -1160,6 +1185,7 @@ struct TilesAcc {
 template <typename real>
 struct TilesPeriodic {
     using V4 = typename Prec<real>::V4;
+    static constexpr bool kNearAsync = false;
     V4 *T;
     const V4 *rec;
     const V4 *cells;
@@ -1291,10 +1317,10 @@ struct TilesPeriodic {
         if (keep) acc_far += (double)part;
         wave_lds_sync();
     }
-    // nodes: up to 8 bottom-node ids, lane l holds node ids[l >> 3]; each cell
-    // m (1/|R| + D), the cell itself D(0) only
-    __device__ void near_tile(int lane, int n, int id, bool keep = true) {
-        if (lane < 8 * n) T[lane] = cells[(int64_t)child[id] + (lane & 7)];
+    // up to 8 bottom nodes given by their first cell, lane l holds that of
+    // node l >> 3; each cell m (1/|R| + D), the cell itself D(0) only
+    __device__ void near_tile(int lane, int n, int cid, bool keep = true) {
+        if (lane < 8 * n) T[lane] = cells[(int64_t)cid + (lane & 7)];
         wave_lds_sync();
         const V4 *t = T;
         const real part = pipelined(
@@ -1359,7 +1385,7 @@ __global__ __launch_bounds__(256) void potential_kernel(PotArgs a) {
     S.rec = (const V4 *)a.far_rec;
     S.cells = (const V4 *)a.cells;
     S.child = a.child;
-    S.own_lo = L.bot_first + sub * 8;
+    S.own_lo = f * kCellsPerBlock + sub * 64;
     S.me = S.cells[(int64_t)f * kCellsPerBlock + cell];
     S.init();
     const int64_t fb = a.far_off[g], fe = a.far_off[g + 1];
@@ -1371,7 +1397,7 @@ __global__ __launch_bounds__(256) void potential_kernel(PotArgs a) {
     const int64_t nb = a.near_off[g], ne = a.near_off[g + 1];
     for (int64_t b = nb; b < ne; b += 8) {
         const int n = (int)(ne - b < 8 ? ne - b : 8);
-        S.near_tile(lane, n, lane < 8 * n ? a.near_idx[b + (lane >> 3)] : 0);
+        S.near_tile(lane, n, lane < 8 * n ? a.child[a.near_idx[b + (lane >> 3)]] : 0);
     }
     if (a.gcells == 32 && lane >= 32) return;
     int i, j, k;
@@ -1441,8 +1467,14 @@ struct FusedSmem {
 // itself; -1 past the end.
 __device__ __forceinline__ int64_t dispatch_unit(const WalkArgs &a, int64_t q) {
     if (q >= a.n_units) return -1;
-    return a.order ? (int64_t)a.order[q] : q;
+    const int64_t u = a.order ? (int64_t)a.order[q] : q;
+    // the same for every lane: kept in scalar registers, as is all that derives from it
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)u));
 }
+
+// Wavefront of the workgroup, known to the compiler as the same for every lane.
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 // algorithmic cost of a wavefront's work from its tile entries: 28 flop x 64
 // cells per far node, 11 flop x 512 pairs per near bottom node
@@ -1480,7 +1512,7 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t u, int w,
     S.rec = (const V4 *)a.far_rec;
     S.cells = (const V4 *)a.cells;
     S.child = a.child;
-    S.own_lo = L.bot_first + sub * 8;
+    S.own_lo = f * kCellsPerBlock + sub * 64;
     S.me = S.cells[(int64_t)f * kCellsPerBlock + sub * 64 + lane];
     if constexpr (MAC == 2) S.setup(a, L, sub);
     S.init();
@@ -1489,10 +1521,17 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t u, int w,
         int *NB = sm.nbuf[w][0];
         int fcnt = 0, ncnt = 0, ftot = 0, ntot = 0;
         bool pending = false;  // a full far tile waits in p0..p2
+        bool npending = false, nown = false;  // a full near tile is on its way into the LDS tile
         V4 p0, p1, p2;
         while (W.size > 0) {
-            int id, acc, nr;
-            W.step(lane, id, acc, nr);
+            int id, acc, nr, cid;
+            W.step(lane, id, acc, nr, cid);
+            if constexpr (TL::kNearAsync) {
+                if (npending) {  // staged during the step (it uses the tile before the far records do)
+                    S.near_finish(nown);
+                    npending = false;
+                }
+            }
             if (pending) {  // loaded before the step: sum it now
                 S.put(lane, p0, p1, p2);
                 wave_lds_sync();
@@ -1502,7 +1541,7 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t u, int w,
             const uint64_t mf = __ballot(acc);
             const uint64_t mn = __ballot(nr);
             if (acc) FB[fcnt + lane_prefix(mf)] = id;
-            if (nr) NB[ncnt + lane_prefix(mn)] = id;
+            if (nr) NB[ncnt + lane_prefix(mn)] = cid;
             fcnt += __popcll(mf);
             ncnt += __popcll(mn);
             ftot += __popcll(mf);
@@ -1513,12 +1552,27 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t u, int w,
                 pending = true;
                 buffer_shift(FB, 64, fcnt, lane);
             }
-            while (ncnt >= 8) {
+            // near tiles in buffer order: all but the newest full one now, that one staged during the next step
+            while (ncnt >= (TL::kNearAsync ? 16 : 8)) {
                 S.near_tile(lane, 8, NB[lane >> 3]);
                 buffer_shift(NB, 8, ncnt, lane);
             }
+            if constexpr (TL::kNearAsync) {
+                if (ncnt >= 8 && W.size > 0) {
+                    nown = S.near_issue(lane, NB[lane >> 3]);
+                    npending = true;
+                    buffer_shift(NB, 8, ncnt, lane);
+                }
+            }
         }
         W.finish(a, lane);
+        if constexpr (TL::kNearAsync) {
+            if (npending) S.near_finish(nown);
+        }
+        while (ncnt >= 8) {  // the last full tiles (the walk has ended)
+            S.near_tile(lane, 8, NB[lane >> 3]);
+            buffer_shift(NB, 8, ncnt, lane);
+        }
         if (pending) {
             S.put(lane, p0, p1, p2);
             wave_lds_sync();
@@ -1545,15 +1599,15 @@ __device__ __forceinline__ void fused_group(const WalkArgs &a, int64_t u, int w,
         int fcnt[3] = {0, 0, 0}, ncnt[3] = {0, 0, 0}, ftot[3] = {0, 0, 0}, ntot[3] = {0, 0, 0};
         const bool low = lane < 32;
         while (W.size > 0) {
-            int id, acc, nr;
-            W.step(lane, id, acc, nr);
+            int id, acc, nr, cid;
+            W.step(lane, id, acc, nr, cid);
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 const int code = c == 0 ? 3 : c;
                 const uint64_t mf = __ballot(acc == code);
                 const uint64_t mn = __ballot(nr == code);
                 if (acc == code) sm.fbuf[w][c][fcnt[c] + lane_prefix(mf)] = id;
-                if (nr == code) sm.nbuf[w][c][ncnt[c] + lane_prefix(mn)] = id;
+                if (nr == code) sm.nbuf[w][c][ncnt[c] + lane_prefix(mn)] = cid;
                 fcnt[c] += __popcll(mf);
                 ncnt[c] += __popcll(mn);
                 ftot[c] += __popcll(mf);
@@ -1618,7 +1672,7 @@ static int fused_gm(const bh_grid *g) { return g->group_cells == 32 ? 2 : 1; }
 template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_kernel(WalkArgs a) {
     __shared__ FusedSmem<real, GM> sm;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
     if (u < 0) return;
@@ -1630,7 +1684,7 @@ __global__ __launch_bounds__(256, WAVES) void walk_potential_kernel(WalkArgs a) 
 template <typename real, int WAVES, int MAC, int ORDER, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_opts_kernel(WalkArgs a) {
     __shared__ FusedSmem<real, GM> sm;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
     if (u < 0) return;
@@ -1673,7 +1727,7 @@ constexpr int kPeriodicWaves32 = 4, kPeriodicWaves64 = 2;
 template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_periodic_kernel(WalkArgs a) {
     __shared__ FusedSmem<real, GM> sm;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
     if (u < 0) return;
@@ -1712,7 +1766,7 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
 template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_theta_kernel(WalkArgs a) {
     __shared__ FusedSmem<real, GM> sm;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
     if (u < 0) return;
@@ -1746,7 +1800,7 @@ constexpr int kAccelWaves64 = 4;
 template <typename real, int WAVES, int GM>
 __global__ __launch_bounds__(256, WAVES) void walk_accel_kernel(WalkArgs a) {
     __shared__ FusedSmem<real, GM> sm;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
     if (u < 0) return;
@@ -1784,7 +1838,7 @@ __global__ __launch_bounds__(256, WAVES) void batch_walk_potential_kernel(
     const WalkArgs *__restrict__ grids, const int2 *__restrict__ order, int64_t total,
     unsigned long long *__restrict__ counter) {
     __shared__ FusedSmem<real, 1> sm;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_index();
     const int lane = threadIdx.x & 63;
     while (true) {
         unsigned long long q = 0;
