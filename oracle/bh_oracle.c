@@ -101,6 +101,10 @@ typedef struct otree {
     int64_t ngroups;
     ivec *far, *near;
     int64_t *counts; /* [g][4] visited, far, near, marginal */
+    /* marginal band of the next walks: |d^2 - s^2| <= tau s^2 + tau_lin s
+     * (the linear term bounds rounding that scales with the coordinates, not
+     * with s; 0 unless set) */
+    double tau_lin;
 } otree;
 
 static void ivec_push(ivec *a, int x) {
@@ -435,7 +439,7 @@ typedef struct {
     const int64_t *cells;
     int G;
     double inv_theta;
-    double tau;
+    double tau, tau_lin;
     ivec *far, *near;
     int64_t visited, marginal;
     int mac;            /* 0: every cell of the group (O5); 1: the group's cube (O5b) */
@@ -488,7 +492,7 @@ static void walk_node(walkctx *w, int n) {
             if (d2 < dmin2) dmin2 = d2;
         }
     }
-    if (fabs(dmin2 - s2) <= w->tau * s2) w->marginal++;
+    if (fabs(dmin2 - s2) <= w->tau * s2 + w->tau_lin * s) w->marginal++;
     if (accept) {
         ivec_push(w->far, n);
     } else if (a->bottom) {
@@ -518,6 +522,7 @@ int64_t ot_walk_mac(otree *t, int group_cells, const double *theta_group, double
             w.t = t; w.cells = cells; w.G = G;
             w.inv_theta = 1.0 / theta_group[g];
             w.tau = tau;
+            w.tau_lin = t->tau_lin;
             w.far = &t->far[g]; w.near = &t->near[g];
             w.visited = 0; w.marginal = 0;
             w.mac = mac;
@@ -676,6 +681,7 @@ void ot_solve_groups_mac(const otree *t, int group_cells, const double *theta_gr
             w.t = t; w.cells = cells; w.G = G;
             w.inv_theta = 1.0 / theta_group[g];
             w.tau = tau;
+            w.tau_lin = t->tau_lin;
             w.far = &far; w.near = &near;
             w.visited = 0; w.marginal = 0;
             w.mac = mac;
@@ -812,6 +818,7 @@ void ot_solve_groups_accel(const otree *t, int group_cells, const double *theta_
             w.t = t; w.cells = cells; w.G = G;
             w.inv_theta = 1.0 / theta_group[g];
             w.tau = tau;
+            w.tau_lin = t->tau_lin;
             w.far = &far; w.near = &near;
             w.visited = 0; w.marginal = 0;
             w.mac = 0;
@@ -1063,7 +1070,7 @@ typedef struct {
     const otree *t;
     const int64_t *cells;
     int G;
-    double inv_theta, tau, L;
+    double inv_theta, tau, tau_lin, L;
     ivec *far, *near;
     int64_t visited, marginal;
 } pwalkctx;
@@ -1093,7 +1100,7 @@ static void pwalk_node(pwalkctx *w, int n) {
         if (!(d2 > s2)) accept = 0;
         if (d2 < dmin2) dmin2 = d2;
     }
-    if (fabs(dmin2 - s2) <= w->tau * s2) w->marginal++;
+    if (fabs(dmin2 - s2) <= w->tau * s2 + w->tau_lin * s) w->marginal++;
     if (accept) {
         ivec_push(w->far, n);
     } else if (a->bottom) {
@@ -1168,6 +1175,7 @@ void ot_solve_groups_periodic(const otree *t, int group_cells, const double *the
             w.t = t; w.cells = cells; w.G = G;
             w.inv_theta = 1.0 / theta_group[g];
             w.tau = tau;
+            w.tau_lin = t->tau_lin;
             w.L = t->box;
             w.far = &far; w.near = &near;
             w.visited = 0; w.marginal = 0;
@@ -1216,3 +1224,6 @@ void ot_node_far_periodic(const otree *t, int n, const double *p, double *out) {
  * number of host cores): set, and read back what the runtime will use. */
 void ot_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int ot_get_threads(void) { return omp_get_max_threads(); }
+
+/* Linear term of the marginal band of the following walks (see otree). */
+void ot_set_tau_lin(otree *t, double lin) { t->tau_lin = lin; }

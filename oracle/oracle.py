@@ -78,6 +78,7 @@ def _load():
         lib.ot_potential_lists.argtypes = [P, ctypes.c_int, P, P, P, P, ctypes.c_double, ctypes.c_int, P]
         lib.ot_direct.argtypes = [P, P, i64, ctypes.c_double, P]
         lib.ot_set_threads.argtypes = [ctypes.c_int]
+        lib.ot_set_tau_lin.argtypes = [P, ctypes.c_double]
         lib.ot_get_threads.restype = ctypes.c_int
         lib.ot_solve_groups.argtypes = [P, ctypes.c_int, P, P, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                         P, P]
@@ -112,6 +113,26 @@ def set_threads(n):
 
 def get_threads():
     return int(_load().ot_get_threads())
+
+
+U32 = 2.0 ** -24  # unit roundoff of fp32
+
+
+def fp32_band_for(B):
+    """fp32_band for coordinates of magnitude at most B."""
+    return (18.0 * U32, 12.0 * np.sqrt(3.0) * U32 * float(B))
+
+
+def fp32_band(grid):
+    """Marginal band (tau, tau_lin) of an fp32 opening test on `grid`, from the fp32
+    rounding of its operands: per axis the gap between a cell centre and a node's
+    centre of mass is off by at most 3 u B (B the largest coordinate of the box:
+    both rounded to fp32, then subtracted), so d^2 moves by at most
+    2 sqrt(3) d 3 u B + 3 u d^2; s = l / theta + delta by 3 u s, s^2 by 6 u s^2.
+    Near the threshold (d ~ s): |d^2 - s^2| changes by at most 9 u s^2 + 6 sqrt(3) u B s.
+    Twice that: tau = 18 u, tau_lin = 12 sqrt(3) u B."""
+    lo = np.asarray(grid.box_lo, np.float64)
+    return fp32_band_for(np.max(np.abs(np.concatenate([lo, lo + grid.box_size]))))
 
 
 def make_key(depth, ix, iy, iz):
@@ -153,6 +174,16 @@ class OracleTree:
                 self.h = None
         except Exception:
             pass
+
+    def _band(self, tau):
+        """tau: a relative band, or (relative, linear) as fp32_band gives: sets the linear term for the next walk
+        and returns the relative one."""
+        if isinstance(tau, (tuple, list)):
+            rel, lin = float(tau[0]), float(tau[1])
+        else:
+            rel, lin = float(tau), 0.0
+        self.lib.ot_set_tau_lin(self.h, lin)
+        return rel
 
     # -- geometry -----------------------------------------------------------
     def node_info(self):
@@ -213,7 +244,7 @@ class OracleTree:
             self.moments()
         ng = self.n_groups(group_cells)
         th = np.broadcast_to(np.asarray(theta, np.float64), (ng,)).copy()
-        self.lib.ot_walk_mac(self.h, int(group_cells), _p(th), float(tau), int(mac))
+        self.lib.ot_walk_mac(self.h, int(group_cells), _p(th), self._band(tau), int(mac))
         self.group_cells = group_cells
         tf = ctypes.c_int64()
         tn = ctypes.c_int64()
@@ -268,7 +299,7 @@ class OracleTree:
         gs = np.ascontiguousarray(groups, np.int64)
         phi = np.empty((gs.size, group_cells))
         counts = np.empty((gs.size, 4), np.int64)
-        self.lib.ot_solve_groups_mac(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau), float(G),
+        self.lib.ot_solve_groups_mac(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), self._band(tau), float(G),
                                      int(order), int(mac), _p(counts), _p(phi))
         return phi, counts
 
@@ -295,7 +326,7 @@ class OracleTree:
         phi = np.empty((gs.size, group_cells))
         counts = np.empty((gs.size, 4), np.int64)
         qsum = np.empty(gs.size)
-        self.lib.ot_solve_groups_periodic(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau),
+        self.lib.ot_solve_groups_periodic(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), self._band(tau),
                                           float(G), _p(counts), _p(phi), _p(qsum))
         return (phi, counts, qsum) if with_qsum else (phi, counts)
 
@@ -327,7 +358,7 @@ class OracleTree:
         gs = np.ascontiguousarray(groups, np.int64)
         acc = np.empty((gs.size, group_cells, 3))
         counts = np.empty((gs.size, 4), np.int64)
-        self.lib.ot_solve_groups_accel(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), float(tau), float(G),
+        self.lib.ot_solve_groups_accel(self.h, int(group_cells), _p(th), _p(gs), int(gs.size), self._band(tau), float(G),
                                        int(order), _p(counts), _p(acc))
         return acc, counts
 

@@ -507,10 +507,12 @@ __device__ __forceinline__ GroupBox<real> group_box(const LeafInfo &L, int gcell
 // Groups per leaf block and the group (within the block) of octant `sub`.
 __device__ __forceinline__ int groups_per_leaf(int gcells) { return kCellsPerBlock / gcells; }
 
-__device__ __forceinline__ float group_theta(const WalkArgs &a, int64_t canon_group) {
-    float th = a.theta_group[canon_group];
+__device__ __forceinline__ float clamp_theta(float th) {
     if (!(th == th)) th = 1e-3f;
     return th < 1e-3f ? 1e-3f : (th > 1.0f ? 1.0f : th);
+}
+__device__ __forceinline__ float group_theta(const WalkArgs &a, int64_t canon_group) {
+    return clamp_theta(a.theta_group[canon_group]);
 }
 
 // Group walk state of one wavefront.  The group vote of the potential kernel

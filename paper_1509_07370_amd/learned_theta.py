@@ -5,12 +5,21 @@ per-group error, features, network forward / gradient / Adam); this module
 only orders the calls and keeps small host-side bookkeeping (label envelope,
 mini-batch order, files).
 
-Labels come from the method itself: for every group the largest theta on the
-grid {0.20, 0.25, ..., 1.00} such that the group's RMS relative error against
-the exact direct sum stays within the target for that theta and every smaller
-one.  At run time the network's bf16 output drives bh_walk_potential; a 1%
-sample of cells is checked against the direct sum and a fixed conservative
-theta (0.4) is used instead if the sample misses the target.
+Labels come from the method itself, from tables of every group's RMS relative
+error against the exact direct sum and of its far/near counts at each theta of
+the grid {0.20, 0.25, ..., 1.00}:
+  * "target": the largest theta whose error, and the error of every smaller
+    theta, meets the target (each group on its own);
+  * "lagrange": the cost-aware split of one error budget over the groups,
+    theta_g = argmin_theta cost_g(theta) + lambda err_g(theta)^2, with cost_g the
+    group's walk time from a linear model of the counts (fitted to timed
+    sweeps) and lambda the median over the training grids of the multiplier
+    that makes a grid's global RMS meet the target.
+At run time the network's bf16 output drives bh_walk_potential; a 1% sample of
+cells is checked against the direct sum and a fixed conservative theta (0.4)
+is used instead if the sample misses the target.  calibrate_on_sample picks
+the network's output shift for one grid from the same sample (the analogue of
+choosing a fixed theta by a sweep).
 
 Usage on a GPU:
   python -m paper_1509_07370_amd.learned_theta train --target 1e-3 --out paper_1509_07370_amd/data/theta_mlp_1e-3.npz
@@ -53,6 +62,60 @@ def error_table(bh: BarnesHut, rho: torch.Tensor, direct: torch.Tensor, thetas=T
         B.bh_group_rms_error(bh.ctx, bh.grid, phi, direct, rms[k])
     bh.check()
     return rms.cpu().numpy()
+
+
+def count_table(bh: BarnesHut, rho: torch.Tensor, thetas=THETA_GRID, precision=B.BH_FP32, reps=5):
+    """[len(thetas), n_groups, 2] far / near counts of every group at each theta, and the timed step (moments +
+    fused walk and sums) in ms at each theta."""
+    ng = bh.info["n_groups"]
+    phi = torch.empty_like(rho)
+    cn = torch.zeros((ng, 2), dtype=torch.int32, device=rho.device)
+    counts = np.empty((len(thetas), ng, 2), np.int32)
+    ms = np.empty(len(thetas))
+    for k, th in enumerate(thetas):
+        def step(th=float(th)):
+            bh.build_moments(rho)
+            B.bh_walk_potential(bh.ctx, bh.grid, bh.m, th, None, precision, 1.0, phi, None)
+        step()
+        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, float(th), None, precision, 1.0, phi, cn)
+        counts[k] = cn.cpu().numpy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        ms[k] = (time.perf_counter() - t0) * 1e3 / reps
+    return counts, ms
+
+
+def fit_time_model(counts_per_grid, ms_per_grid):
+    """Least-squares ms = a * sum(far) + b * sum(near) + c over every (grid, theta): per-entry walk times."""
+    rows, y = [], []
+    for c, ms in zip(counts_per_grid, ms_per_grid):
+        for k in range(c.shape[0]):
+            rows.append([c[k, :, 0].sum(), c[k, :, 1].sum(), 1.0])
+            y.append(ms[k])
+    coef, *_ = np.linalg.lstsq(np.array(rows, np.float64), np.array(y), rcond=None)
+    return float(coef[0]), float(coef[1]), float(coef[2])
+
+
+def lagrangian_labels(errs: np.ndarray, counts: np.ndarray, model, lam: float, thetas=THETA_GRID) -> np.ndarray:
+    """theta_g = argmin over the grid of cost_g(theta) + lam * err_g(theta)^2 (cost in ms from the time model)."""
+    a, b, _ = model
+    J = a * counts[:, :, 0] + b * counts[:, :, 1] + lam * errs.astype(np.float64) ** 2
+    return np.asarray(thetas)[np.argmin(J, axis=0)].astype(np.float32)
+
+
+def lambda_for_target(errs: np.ndarray, counts: np.ndarray, model, target: float, thetas=THETA_GRID) -> float:
+    """Smallest multiplier whose labels give the grid a global RMS within the target (bisection in log lambda)."""
+    lo, hi = 1e-12, 1e12
+    for _ in range(120):
+        mid = float(np.sqrt(lo * hi))
+        if estimated_rms(errs, lagrangian_labels(errs, counts, model, mid, thetas), thetas) <= target:
+            hi = mid
+        else:
+            lo = mid
+    return hi
 
 
 def labels_from_errors(errs: np.ndarray, target: float, thetas=THETA_GRID) -> np.ndarray:
@@ -174,6 +237,26 @@ def sampled_rms(bh: BarnesHut, phi: torch.Tensor, frac=0.01, seed=0, minimum=100
     return float(torch.sqrt((rel * rel).mean()))
 
 
+def calibrate_on_sample(bh, rho, net, phi, theta, target, precision=B.BH_FP32, margin=0.95,
+                        shifts=np.round(np.arange(-0.3, 0.6001, 0.025), 3), frac=0.01, seed=0):
+    """The smallest output shift whose learned step meets margin * target on a seeded 1% sample of cells against
+    the exact direct sum (None if none does).  Sets net.meta['theta_shift'] to it and returns it."""
+    n = bh.info["n_cells"]
+    k = min(n, max(1000, int(frac * n)))
+    rng = np.random.default_rng(seed)
+    tg = torch.tensor(np.sort(rng.choice(n, k, replace=False)), dtype=torch.int64, device=phi.device)
+    bh.build_moments(rho)
+    d = bh.direct(tg)
+    for s_ in shifts:
+        bh.build_moments(rho)
+        B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, float(s_), precision, 1.0, phi, theta)
+        rel = (phi.reshape(-1).index_select(0, tg) - d) / d
+        if float(torch.sqrt((rel * rel).mean())) <= margin * target:
+            net.meta["theta_shift"] = float(s_)
+            return float(s_)
+    return None
+
+
 def solve_with_fallback(bh, rho, net, phi, feat, theta, target, precision=B.BH_FP32, G=1.0):
     """Learned theta, judged by a 1% sampled direct sum; fixed theta 0.4 if it misses the target."""
     solve_learned(bh, rho, net, phi, feat, theta, precision, G)
@@ -186,8 +269,10 @@ def solve_with_fallback(bh, rho, net, phi, feat, theta, target, precision=B.BH_F
 
 # ------------------------------------------------------------------ training workloads
 
-def training_grids():
-    """Seeded perturbations of the uniform-sphere and MacLaurin workloads."""
+def training_grids(extended=False):
+    """Seeded perturbations of the uniform-sphere and MacLaurin workloads; `extended` adds
+    3-level meshes shaped like the held-out cores (e in {0.7, 0.8, 0.9, 0.95}, a1 in {0.2, 0.3})
+    and two 3-level spheres."""
     from amr_inputs import maclaurin_spheroid, uniform_sphere
     out = []
     for e in (0.75, 0.85, 0.9, 0.95):
@@ -197,6 +282,9 @@ def training_grids():
     for R in (0.25, 0.4):
         for ro in (1e-3, 1e-5):
             out.append(uniform_sphere(radius=R, rho_out=ro, max_level=2))
+    if extended:
+        out += [maclaurin_spheroid(e=e, a1=a1, max_level=3) for e in (0.7, 0.8, 0.9, 0.95) for a1 in (0.2, 0.3)]
+        out += [uniform_sphere(radius=R, rho_out=1e-4, max_level=3) for R in (0.2, 0.3)]
     return out
 
 
@@ -229,8 +317,8 @@ def calibrate_shift(net, feats_per_grid, errs_per_grid, target, shifts=np.arange
     return float(shifts[-1])
 
 
-def build_dataset(grids, target, log=print):
-    feats, labs, errs = [], [], []
+def build_dataset(grids, target, log=print, labels="target"):
+    feats, labs, errs, counts, times = [], [], [], [], []
     for g in grids:
         t0 = time.time()
         bh = BarnesHut(g)
@@ -239,11 +327,27 @@ def build_dataset(grids, target, log=print):
         table = error_table(bh, rho, direct)
         f = group_features(bh, rho).cpu().numpy()
         feats.append(f)
-        labs.append(labels_from_errors(table, target))
         errs.append(table)
-        log("data %s: %d groups, %.1f s, mean label %.3f" % (g.name, f.shape[0], time.time() - t0, labs[-1].mean()))
+        if labels == "lagrange":
+            c, ms = count_table(bh, rho)
+            counts.append(c)
+            times.append(ms)
+        else:
+            labs.append(labels_from_errors(table, target))
+        log("data %s: %d groups, %.1f s" % (g.name, f.shape[0], time.time() - t0))
         bh.close()
-    return feats, labs, errs
+    info = {}
+    if labels == "lagrange":
+        model = fit_time_model(counts, times)
+        lams = [lambda_for_target(e, c, model, target) for e, c in zip(errs, counts)]
+        lam = float(np.median(lams))
+        labs = [lagrangian_labels(e, c, model, lam) for e, c in zip(errs, counts)]
+        info = dict(time_model=model, lam=lam, grid_lams=lams)
+        log("time model: %.3e ms per far entry, %.3e per near entry, %.3f ms fixed; lambda %.3g (grids %s)" % (
+            model[0], model[1], model[2], lam, np.round(lams, 1).tolist()))
+    for y in labs:
+        log("mean label %.3f" % y.mean())
+    return feats, labs, errs, info
 
 
 def evaluate(net: ThetaNet, grids, target, precision=B.BH_FP32, reps=10, log=print):
@@ -284,16 +388,29 @@ def evaluate(net: ThetaNet, grids, target, precision=B.BH_FP32, reps=10, log=pri
         rec = dict(grid=g.name, meta={k: v for k, v in g.meta.items() if k in ("e", "a1")}, cells=n,
                    learned=dict(rms=rms_of(phi), ms=ms_l, mcells=n / ms_l / 1e3, theta_mean=float(th.mean()),
                                 theta_p10=float(np.percentile(th, 10)), theta_p90=float(np.percentile(th, 90)),
-                                sampled_rms=sampled_rms(bh, phi)),
+                                sampled_rms=sampled_rms(bh, phi), shift=net.shift),
                    fixed=fixed)
+        # the shift chosen for this grid on its own 1% sample
+        stored = net.shift
+        s_ = calibrate_on_sample(bh, rho, net, phi, theta, target, precision)
+        if s_ is not None:
+            ms_c = timed(lambda: solve_learned(bh, rho, net, phi, feat, theta, precision))
+            rec["learned_calibrated"] = dict(shift=s_, rms=rms_of(phi), ms=ms_c, mcells=n / ms_c / 1e3)
+        net.meta["theta_shift"] = stored
         ok = [f for f in fixed if f["rms"] <= target]
         best = max(ok, key=lambda f: f["theta"]) if ok else None
         rec["best_fixed"] = best
         if best:
             rec["learned_speedup_vs_best_fixed"] = best["ms"] / ms_l
+            if "learned_calibrated" in rec:
+                rec["calibrated_speedup_vs_best_fixed"] = best["ms"] / rec["learned_calibrated"]["ms"]
         log("eval e=%.3f: learned rms %.2e %.3f ms (theta mean %.3f) | best fixed theta %s rms %s %s ms" % (
             g.meta.get("e", 0), rec["learned"]["rms"], ms_l, th.mean(), best and best["theta"],
             best and "%.2e" % best["rms"], best and "%.3f" % best["ms"]))
+        if "learned_calibrated" in rec:
+            c = rec["learned_calibrated"]
+            log("    calibrated on the 1%% sample: shift %.3f, rms %.2e, %.3f ms (x%.3f vs best fixed)" % (
+                c["shift"], c["rms"], c["ms"], rec.get("calibrated_speedup_vs_best_fixed", float("nan"))))
         out.append(rec)
         bh.close()
     return out
@@ -307,6 +424,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--labels", choices=["target", "lagrange"], default="target")
+    ap.add_argument("--extended", action="store_true", help="add the 3-level training meshes")
     args = ap.parse_args(argv)
     from amr_inputs.mlp_init import glorot_init
 
@@ -320,10 +439,12 @@ def main(argv=None):
         print(json.dumps(dict(target=net.meta.get("target"), shift=net.shift, results=res)))
         return 0
     target = float(args.target)
-    F, Y, E = build_dataset(training_grids(), target, log)
+    F, Y, E, info = build_dataset(training_grids(args.extended), target, log, labels=args.labels)
     X, y = np.concatenate(F), np.concatenate(Y)
     net = ThetaNet.fresh(ctx, X, glorot_init(42).astype(np.float32),
-                         meta=dict(target=target, epochs=args.epochs, lr=args.lr, n_train=int(len(y)), seed=42))
+                         meta=dict(target=target, epochs=args.epochs, lr=args.lr, n_train=int(len(y)), seed=42,
+                                   labels=args.labels, extended=bool(args.extended),
+                                   **{k: v for k, v in info.items() if k in ("time_model", "lam")}))
     fx = torch.tensor(X, device="cuda")
     fy = torch.tensor(y, device="cuda")
     t0 = time.time()

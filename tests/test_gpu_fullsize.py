@@ -14,6 +14,7 @@ import pytest
 
 from amr_inputs import cloud_core, maclaurin_spheroid
 from oracle import OracleTree
+from oracle.oracle import fp32_band_for
 from periodic_bounds import EPS_FP32_ROWS, N_TABLE, storage_terms, walk_tolerance
 
 pytestmark = pytest.mark.gpu
@@ -27,7 +28,8 @@ from paper_1509_07370_amd import learned_theta as LT  # noqa: E402
 from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-TAU = {B.BH_FP64: 1e-12, B.BH_FP32: 2e-6}
+# fp32: the band derived from fp32 rounding (every test grid lies in the unit box)
+TAU = {B.BH_FP64: 1e-12, B.BH_FP32: fp32_band_for(1.0)}
 TOL = {B.BH_FP64: 1e-12, B.BH_FP32: 1e-5}
 
 
@@ -247,6 +249,51 @@ def test_batched_workload_in_bench_configuration():
         groups = np.unique(np.concatenate([np.random.default_rng(k).choice(ng, 4, replace=False), heavy]))
         t = OracleTree(grids[k])
         ref, oc = t.solve_groups(groups, theta=0.8, tau=TAU[B.BH_FP32])
+        clean = oc[:, 3] == 0
+        assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
+        _check_groups(phi[k].reshape(-1).cpu().numpy()[_morton_cells(groups)], ref, oc, TOL[B.BH_FP32])
+    B.bh_batch_destroy(batch)
+    for h in handles:
+        B.bh_grid_destroy(h)
+    B.bh_ctx_destroy(ctx)
+
+
+def test_small_grids_batch_in_bench_configuration():
+    """The bench's 128 small Plummer-mix grids (2^3 base blocks, up to 3 levels) in one persistent launch replayed
+    from a captured graph at theta 0.85: every grid equals its own single-grid solve bit for bit, and sampled groups
+    (random and the heaviest) of four grids match the oracle's walk and sums, counts equal outside marginal groups."""
+    import bench
+
+    grids = bench.small_grids()
+    ctx = B.bh_ctx_create(0)
+    handles = [B.bh_grid_create_from(ctx, g) for g in grids]
+    batch = B.bh_batch_create(ctx, handles)
+    rho = [torch.tensor(g.rho, device="cuda") for g in grids]
+    phi = [torch.full_like(r, float("nan")) for r in rho]
+    B.bh_batch_capture(ctx, batch, rho, phi, 0.85, None, B.BH_FP32, 1.0)
+    for _ in range(2):
+        B.bh_batch_replay(ctx, batch)
+    B.bh_batch_check(ctx, batch)
+    counts = B.bh_batch_counts(ctx, batch)
+    sizes = [g.ncells for g in grids]
+    base = np.concatenate([[0], np.cumsum([n // 64 for n in sizes])])
+    one = torch.empty_like(phi[0])
+    for k, h in enumerate(handles):
+        m = B.bh_build_moments(ctx, h, rho[k])
+        one = torch.empty_like(rho[k])
+        B.bh_walk_potential(ctx, h, m, 0.85, None, B.BH_FP32, 1.0, one, None)
+        torch.cuda.synchronize()
+        B.bh_moments_destroy(m)
+        assert torch.equal(one, phi[k]), k
+    rng = np.random.default_rng(128)
+    picks = {int(np.argmin(sizes)), int(np.argmax(sizes))} | set(int(x) for x in rng.choice(len(grids), 2, replace=False))
+    for k in sorted(picks):
+        ng = sizes[k] // 64
+        c = counts[base[k]:base[k + 1]]
+        heavy = np.argsort(c[:, 0] * 35 + c[:, 1] * 88)[-2:]
+        groups = np.unique(np.concatenate([np.random.default_rng(k).choice(ng, 4, replace=False), heavy]))
+        t = OracleTree(grids[k])
+        ref, oc = t.solve_groups(groups, theta=0.85, tau=TAU[B.BH_FP32])
         clean = oc[:, 3] == 0
         assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
         _check_groups(phi[k].reshape(-1).cpu().numpy()[_morton_cells(groups)], ref, oc, TOL[B.BH_FP32])

@@ -24,12 +24,14 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from oracle import OracleTree  # noqa: E402
+from oracle import OracleTree
+from oracle.oracle import fp32_band_for  # noqa: E402
 from paper_1509_07370_amd import binding as B  # noqa: E402
 from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
 
 SIZES = [32, 64, 128, 256, 512]
-TAU = {B.BH_FP64: 1e-12, B.BH_FP32: 2e-6}
+# fp32: the band derived from fp32 rounding (every test grid lies in the unit box)
+TAU = {B.BH_FP64: 1e-12, B.BH_FP32: fp32_band_for(1.0)}
 GRIDS = {
     "random_amr": lambda: random_amr(21, nbase=2, max_level=3, p_refine=0.3, zero_fraction=0.1),
     "maclaurin_l1": lambda: maclaurin_spheroid(max_level=1),

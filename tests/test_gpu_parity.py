@@ -15,6 +15,7 @@ import pytest
 
 from amr_inputs import maclaurin_spheroid, random_amr, single_block, uniform_sphere
 from oracle import OracleTree
+from oracle.oracle import fp32_band_for
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +26,8 @@ if not torch.cuda.is_available():
 from paper_1509_07370_amd import binding as B  # noqa: E402
 from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
 
-TAU = {B.BH_FP64: 1e-12, B.BH_FP32: 2e-6}
+# fp32: the band derived from fp32 rounding (every test grid lies in the unit box)
+TAU = {B.BH_FP64: 1e-12, B.BH_FP32: fp32_band_for(1.0)}
 
 GRIDS = {
     "single_block": lambda: single_block(seed=3, sigma=1.0),

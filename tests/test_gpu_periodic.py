@@ -29,7 +29,7 @@ import pytest
 
 from amr_inputs import maclaurin_spheroid, random_amr
 from oracle import OracleTree
-from oracle.oracle import ewald_hessian
+from oracle.oracle import ewald_hessian, fp32_band_for
 from periodic_bounds import (EPS_FP32_ROWS, EPS_FP64_ROWS, HESS_ERR, N_TABLE, TABLE_ERR, measured_lookup_errors,
                              storage_terms, walk_tolerance)
 
@@ -42,7 +42,8 @@ if not torch.cuda.is_available():
 from paper_1509_07370_amd import binding as B  # noqa: E402
 from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
 
-TAU = {B.BH_FP64: 1e-12, B.BH_FP32: 2e-6}
+# fp32: the band derived from fp32 rounding (every test grid lies in the unit box)
+TAU = {B.BH_FP64: 1e-12, B.BH_FP32: fp32_band_for(1.0)}
 STORE_EPS = {B.BH_FP64: EPS_FP64_ROWS, B.BH_FP32: EPS_FP32_ROWS}
 
 GRIDS = {
