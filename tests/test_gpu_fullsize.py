@@ -148,6 +148,23 @@ def test_benchmark_mesh_in_bench_configuration():
     rel = ((phi - direct) / direct).reshape(-1)
     assert float(torch.sqrt((rel * rel).mean())) <= 1e-3
     net.close()
+    # the network for RMS 1e-4, whose thetas vary from group to group on this mesh: the same per-group parity
+    net = LT.ThetaNet.load(bh.ctx, os.path.join(ROOT, "paper_1509_07370_amd", "data", "theta_mlp_1e-4.npz"))
+    counts.zero_()
+    bh.build_moments(rho)
+    B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, B.BH_FP32, 1.0, phi, theta, counts)
+    bh.check()
+    th = theta.cpu().numpy()
+    assert th.min() < th.max() and len(np.unique(th)) >= 3, np.unique(th)
+    c = counts.cpu().numpy()
+    rng = np.random.default_rng(6)
+    groups = np.unique(np.concatenate([_sample_groups(ng, c, seed=6),
+                                       [rng.choice(np.flatnonzero(th == v)) for v in np.unique(th)]]))
+    ref, oc = t.solve_groups(groups, theta=th.astype(np.float64), tau=TAU[B.BH_FP32])
+    clean = oc[:, 3] == 0
+    assert np.array_equal(oc[clean, 1], c[groups[clean], 0]) and np.array_equal(oc[clean, 2], c[groups[clean], 1])
+    _check_groups(phi.reshape(-1).cpu().numpy()[_morton_cells(groups)], ref, oc, 1e-5)
+    net.close()
     bh.close()
 
 
