@@ -1087,12 +1087,61 @@ struct Tiles {
         wave_lds_sync();
         near_sum(n, any_own, keep);
     }
+    // fp32 tiles that hold none of the wavefront's cells: the 8 cells of a
+    // bottom node are the corners of a cube of side h (Morton order: bit 0 x,
+    // bit 1 y, bit 2 z), so a lane needs its offsets (a, a - h) to the node's
+    // first cell per axis, their squares, and one sum per pair.  Each node is
+    // repacked into 16 values -- first cell, the three lattice steps, the 8
+    // masses -- read back with four broadcasts instead of eight.
+    static constexpr bool kLattice = sizeof(real) == 4;
+    __device__ void near_pack(int n) {
+        const int lane = threadIdx.x & 63;
+        real *P = reinterpret_cast<real *>(T + 64);
+        if (lane < 8 * n) {
+            const V4 c = T[lane];
+            const int b = lane >> 3, k = lane & 7;
+            P[16 * b + 6 + k] = c.w;
+            if (k == 0) {
+                P[16 * b + 0] = c.x;
+                P[16 * b + 1] = c.y;
+                P[16 * b + 2] = c.z;
+                P[16 * b + 3] = T[lane + 1].x - c.x;
+                P[16 * b + 4] = T[lane + 2].y - c.y;
+                P[16 * b + 5] = T[lane + 4].z - c.z;
+            }
+        }
+        wave_lds_sync();
+    }
+    __device__ real near_lattice(int n) const {
+        const V4 *P = T + 64;
+        real part = 0;
+        for (int b = 0; b < n; b++) {
+            const V4 h1 = P[4 * b], h2 = P[4 * b + 1], h3 = P[4 * b + 2], h4 = P[4 * b + 3];
+            const real ax = me.x - h1.x, ay = me.y - h1.y, az = me.z - h1.z;
+            const real bx = ax - h1.w, by = ay - h2.x, bz = az - h2.y;
+            const real x0 = ax * ax, x1 = bx * bx, y0 = ay * ay, y1 = by * by, z0 = az * az, z1 = bz * bz;
+            const real s00 = x0 + y0, s10 = x1 + y0, s01 = x0 + y1, s11 = x1 + y1;
+            part = fmaf(h2.z, rsq_any(s00 + z0), part);
+            part = fmaf(h2.w, rsq_any(s10 + z0), part);
+            part = fmaf(h3.x, rsq_any(s01 + z0), part);
+            part = fmaf(h3.y, rsq_any(s11 + z0), part);
+            part = fmaf(h3.z, rsq_any(s00 + z1), part);
+            part = fmaf(h3.w, rsq_any(s10 + z1), part);
+            part = fmaf(h4.x, rsq_any(s01 + z1), part);
+            part = fmaf(h4.y, rsq_any(s11 + z1), part);
+        }
+        return part;
+    }
     __device__ void near_sum(int n, bool any_own, bool keep) {
         real part = 0;
-        if (!any_own)
+        if (kLattice && !any_own) {
+            near_pack(n);
+            part = near_lattice(n);
+        } else if (!any_own) {
             for (int j = 0; j < 8 * n; j++) part = near_pair(me.x, me.y, me.z, T[j], part);
-        else
+        } else {
             for (int j = 0; j < 8 * n; j++) part = near_pair_self(me.x, me.y, me.z, T[j], part);
+        }
         if (keep) acc_near += (double)part;
         wave_lds_sync();
     }
