@@ -324,6 +324,22 @@ int bh_ewald_destroy(bh_ewald *table);
  * D_xx D_yy D_zz D_xy D_xz D_yz; D_xxx D_yyy D_zzz D_xxy D_xxz D_xyy D_yyz
  * D_xzz D_yzz D_xyz. */
 int bh_ewald_export(bh_ctx *ctx, const bh_ewald *table, double *values);
+/* Number of values bh_ewald_near_series returns. */
+#define BH_EWALD_NEAR_TERMS 11
+/* The series of the smooth part D near the origin that the fp32 periodic
+ * walks use for near-cell pairs within radius L of each other (appendix
+ * "Periodic boundaries": D is smooth there, has the cube's symmetry and the
+ * Laplacian 4 pi / L^3).  In units of L, with X = (R_x / L)^2, Y, Z and
+ * e1 = X + Y + Z, e2 = XY + YZ + ZX, e3 = XYZ:
+ *   D L = c0 + c1 e1 + c2 e1^2 + c3 e2 + c4 e1^3 + c5 e1 e2 + c6 e3
+ *       + c7 e1^4 + c8 e1^2 e2 + c9 e2^2 + c10 e1 e3,
+ * c0 = D(0) L and c1 = 2 pi / 3 from the Ewald sums, c2..c10 fitted to them by
+ * least squares when the table is created.  coeffs[BH_EWALD_NEAR_TERMS]
+ * (host): c0..c10; *radius (host): the radius in units of L within which the
+ * walks use the series, 0 if the fit missed its accuracy and the table serves
+ * every pair; *max_err (host): the largest |series - D L| found at the fit
+ * points and a second set of check points.  Errors: BH_EINVAL (NULL). */
+int bh_ewald_near_series(bh_ctx *ctx, const bh_ewald *table, double *coeffs, double *radius, double *max_err);
 /* Synchronising host copy of S = sum m |r - X|^2 of every node (by node id),
  * as built by the last bh_build_moments. */
 int bh_moments_export_trace(bh_ctx *ctx, const bh_moments *m, double *S);

@@ -76,6 +76,7 @@ _SIGS = {
     "bh_ewald_create": (ctypes.c_int, [P, f64, ctypes.c_int, PP]),
     "bh_ewald_destroy": (ctypes.c_int, [P]),
     "bh_ewald_export": (ctypes.c_int, [P, P, P]),
+    "bh_ewald_near_series": (ctypes.c_int, [P, P, P, P, P]),
     "bh_moments_export_trace": (ctypes.c_int, [P, P, P]),
     "bh_walk_potential_periodic": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64, P, P]),
     "bh_direct_periodic": (ctypes.c_int, [P, P, P, P, P, i64, f64, P]),
@@ -348,6 +349,18 @@ def bh_ewald_export(ctx, table, n_points):
     v = np.empty((n_points, n_points, n_points, EWALD_VALUES))
     _check(_lib.bh_ewald_export(ctx, table, _ptr(v)), ctx)
     return v
+
+
+EWALD_NEAR_TERMS = 11
+
+
+def bh_ewald_near_series(ctx, table):
+    """(coefficients c0..c10, radius in units of L (0: unused), largest error at the check points)."""
+    c = np.empty(EWALD_NEAR_TERMS)
+    r = ctypes.c_double()
+    e = ctypes.c_double()
+    _check(_lib.bh_ewald_near_series(ctx, table, _ptr(c), ctypes.byref(r), ctypes.byref(e)), ctx)
+    return c, r.value, e.value
 
 
 def bh_moments_export_trace(ctx, m, n_nodes):

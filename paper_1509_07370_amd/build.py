@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbh.so")
 SOURCES = ["bh_api.cpp", "bh_topology.cpp", "bh_mlp_api.cpp", "bh_batch_api.cpp", "bh_kernels.hip", "bh_mlp.hip",
-           "bh_periodic.hip",
+           "bh_periodic.hip", "bh_ewald_series.cpp",
            "bh_static.hip"]
 ARCH = os.environ.get("BH_OFFLOAD_ARCH", "gfx950")
 

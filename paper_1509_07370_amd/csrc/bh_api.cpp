@@ -591,13 +591,18 @@ int bh_ewald_create(bh_ctx *ctx, double box_size, int n_points, bh_ewald **out) 
     hipError_t err;
     if ((err = dalloc(&e->d_t64, points * bh::kEwaldValues)) != hipSuccess ||
         (err = dalloc(&e->d_t64c, points * bh::kEwaldCompactDoubles)) != hipSuccess ||
-        (err = dalloc(&e->d_t32, points * bh::kEwaldCompactFloats)) != hipSuccess) {
+        (err = dalloc(&e->d_t32, points * bh::kEwaldCompactFloats)) != hipSuccess ||
+        (err = dalloc(&e->d_near, (size_t)bh::kEwaldNearTerms + 1)) != hipSuccess) {
         bh_ewald_destroy(e);
         return hip_fail(ctx, err, "device allocation of the table");
     }
     if ((err = bh::launch_ewald_table(e, ctx->stream)) != hipSuccess) {
         bh_ewald_destroy(e);
         return hip_fail(ctx, err, "table kernel");
+    }
+    if ((err = bh::fit_ewald_near_series(e, ctx->stream)) != hipSuccess) {
+        bh_ewald_destroy(e);
+        return hip_fail(ctx, err, "near-origin series");
     }
     *out = e;
     return BH_OK;
@@ -609,7 +614,18 @@ int bh_ewald_destroy(bh_ewald *e) {
     hfree(e->d_t64);
     hfree(e->d_t64c);
     hfree(e->d_t32);
+    hfree(e->d_near);
     delete e;
+    return BH_OK;
+}
+
+int bh_ewald_near_series(bh_ctx *ctx, const bh_ewald *e, double *coeffs, double *radius, double *max_err) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!e || !coeffs || !radius || !max_err) return fail(ctx, BH_EINVAL, "table handle or an output is NULL");
+    for (int k = 0; k < bh::kEwaldNearTerms; k++) coeffs[k] = e->near_coef[k];
+    *radius = e->near_radius;
+    *max_err = e->near_err;
     return BH_OK;
 }
 

@@ -94,6 +94,7 @@ struct WalkArgs {
     const void *ewald;
     double ewald_sp;
     int ewald_n;
+    const float *ewald_near;  // near-origin series of D (fp32 periodic walks), or null
     const double *node_s;
 };
 
@@ -136,6 +137,7 @@ constexpr int kEwaldValues = 20;  // D, gradient (3), Hessian (6), third derivat
 // 96 bytes (six).
 constexpr int kEwaldCompactFloats = 12;
 constexpr int kEwaldCompactDoubles = 12;
+constexpr int kEwaldNearTerms = 11;  // D0, the r^2 term, 9 terms of degree 4, 6 and 8
 }
 
 // Every handle records the device it was created on: its destroy call frees
@@ -147,6 +149,13 @@ struct bh_ewald {
     int n = 0;        // points per axis over [0, L/2]
     double sp = 0.0;  // spacing (L/2) / (n - 1)
     double *d_t64 = nullptr;   // [n^3][20] D and its derivatives to third order (export)
+    // series of D L near the origin (|R| <= near_radius L), fitted at creation:
+    // D0, 2 pi / 3, then the coefficients of e1^2, e2, e1^3, e1 e2, e3, e1^4,
+    // e1^2 e2, e2^2, e1 e3 (e1 = X + Y + Z, e2 = XY + YZ + ZX, e3 = XYZ, X = (R_x / L)^2 ...)
+    double near_coef[bh::kEwaldNearTerms] = {};
+    double near_radius = 0.0;  // 0: not used (the fit missed its accuracy)
+    double near_err = 0.0;     // largest |series - D L| at the check points
+    float *d_near = nullptr;   // the coefficients in fp32, then near_radius^2
     double *d_t64c = nullptr;  // [n^3][12] compact rows of the fp64 walks and direct sum
     float *d_t32 = nullptr;    // [n^3][12] compact rows of the fp32 walks
 };
@@ -235,6 +244,8 @@ hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipSt
 // Periodic Green's function table, periodic fused walk + sums, periodic
 // direct sum.
 hipError_t launch_ewald_table(const bh_ewald *e, hipStream_t s);
+hipError_t launch_ewald_points(double L, const double *u, int n, double *out, hipStream_t s);
+hipError_t fit_ewald_near_series(bh_ewald *e, hipStream_t s);
 hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
                                           const float *theta_group, int precision, double G, double *phi,
                                           int32_t *counts, hipStream_t s);

@@ -1246,6 +1246,7 @@ struct TilesPeriodic {
     int own_lo;
     double acc_far, acc_near;
     EwaldView<real> ew;
+    const float *near_c;  // series of D L near the origin (fp32 walks), then the radius^2; null: table only
     real cg[3], box, box_inv, bg;
     real dscale, qscale;  // table value -> D, and the Q:H sum -> Q:H / 6 (fp32 rows are scaled by powers of L)
 
@@ -1270,6 +1271,7 @@ struct TilesPeriodic {
         dscale = box_inv;
         qscale = (real)(1.0 / ((sizeof(real) == 4 ? 3.0 : 6.0) * a.box * a.box * a.box));
         node_s = a.node_s;
+        near_c = sizeof(real) == 4 ? a.ewald_near : nullptr;
     }
     __device__ void init() { acc_far = acc_near = 0.0; }
     __device__ real image(real x, real c) const { return x - box * rint((x - c) * box_inv); }
@@ -1369,18 +1371,51 @@ struct TilesPeriodic {
         wave_lds_sync();
     }
     // up to 8 bottom nodes given by their first cell, lane l holds that of
-    // node l >> 3; each cell m (1/|R| + D), the cell itself D(0) only
+    // node l >> 3; each cell m (1/|R| + D), the cell itself D(0) only.  In
+    // fp32, D comes from the near-origin series while every pair of the tile
+    // lies within its radius (the usual case for near cells), else the whole
+    // tile is summed again through the table.
+    __device__ real near_series(int n, bool &inside) const {
+        const real c0 = near_c[0], c1 = near_c[1], c2 = near_c[2], c3 = near_c[3], c4 = near_c[4], c5 = near_c[5];
+        const real c6 = near_c[6], c7 = near_c[7], c8 = near_c[8], c9 = near_c[9], c10 = near_c[10];
+        const real rad2 = near_c[11];
+        real part = 0;
+        bool out = false;
+        for (int j = 0; j < 8 * n; j++) {
+            const V4 s = T[j];
+            real dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+            dx -= box * rint(dx * box_inv);
+            dy -= box * rint(dy * box_inv);
+            dz -= box * rint(dz * box_inv);
+            const real ux = dx * box_inv, uy = dy * box_inv, uz = dz * box_inv;
+            const real X = ux * ux, Y = uy * uy, Z = uz * uz;
+            const real XY = X * Y;
+            const real e1 = (X + Y) + Z, e2 = fmaf(Z, X + Y, XY), e3 = XY * Z;
+            out |= e1 > rad2;
+            const real a = fmaf(e1, fmaf(e1, fmaf(e1, c7, c4), c2), c1);
+            const real b = fmaf(e1, fmaf(e1, c8, c5), fmaf(e2, c9, c3));
+            const real dl = fmaf(e1, a, fmaf(e2, b, fmaf(e3, fmaf(e1, c10, c6), c0)));
+            const real ri = e1 > (real)0 ? rsq_any(e1) * box_inv : (real)0;
+            part = fmaf(s.w, ri + dl * dscale, part);
+        }
+        inside = __ballot(out) == 0;
+        return part;
+    }
     __device__ void near_tile(int lane, int n, int cid, bool keep = true) {
         if (lane < 8 * n) T[lane] = cells[(int64_t)cid + (lane & 7)];
         wave_lds_sync();
         const V4 *t = T;
-        const real part = pipelined(
-            8 * n, [t](int j) { return t[j]; },
-            [this, t](const Pair &c, const real(&v)[kEwaldValues], int j) {
-                const real r2 = c.dx * c.dx + c.dy * c.dy + c.dz * c.dz;
-                const real ri = r2 > (real)0 ? rsq_any(r2) : (real)0;
-                return t[j].w * (ri + ewald_eval<real>(c.ep, v, nullptr) * dscale);
-            });
+        real part = 0;
+        bool done = false;
+        if (near_c) part = near_series(n, done);
+        if (!done)
+            part = pipelined(
+                8 * n, [t](int j) { return t[j]; },
+                [this, t](const Pair &c, const real(&v)[kEwaldValues], int j) {
+                    const real r2 = c.dx * c.dx + c.dy * c.dy + c.dz * c.dz;
+                    const real ri = r2 > (real)0 ? rsq_any(r2) : (real)0;
+                    return t[j].w * (ri + ewald_eval<real>(c.ep, v, nullptr) * dscale);
+                });
         if (keep) acc_near += (double)part;
         wave_lds_sync();
     }
@@ -1791,6 +1826,7 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
     a.box = g->topo.box;
     a.ewald = precision == BH_FP64 ? (const void *)e->d_t64c : (const void *)e->d_t32;
+    a.ewald_near = precision == BH_FP32 && e->near_radius > 0.0 ? e->d_near : nullptr;
     a.ewald_sp = e->sp;
     a.ewald_n = e->n;
     a.node_s = m->d_s;

@@ -175,6 +175,25 @@ __global__ __launch_bounds__(128) void ewald_table_kernel(double L, int n, doubl
     }
 }
 
+// D L (dimensionless) at points u given in units of L, one thread per point:
+// the same Ewald sums as the table, at any point (the near-origin series is
+// fitted to and checked against these).
+__global__ __launch_bounds__(128) void ewald_points_kernel(double L, const double *__restrict__ u, int n,
+                                                           double *__restrict__ out) {
+    const int q = blockIdx.x * 128 + threadIdx.x;
+    if (q >= n) return;
+    const double p[3] = {u[3 * q] * L, u[3 * q + 1] * L, u[3 * q + 2] * L};
+    EwaldAcc acc;
+    ewald_sums(L, p, acc);
+    out[q] = acc.v[0] * L;
+}
+
+hipError_t launch_ewald_points(double L, const double *u, int n, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ewald_points_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, L, u, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_ewald_table(const bh_ewald *e, hipStream_t s) {
     const int64_t total = (int64_t)e->n * e->n * e->n;
     hipLaunchKernelGGL(ewald_table_kernel, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, e->L, e->n, e->sp,

@@ -5,6 +5,8 @@ O9 and O10, through the C ABI.
   point equal the oracle's Ewald sums (1e-12 of the scale of each
   derivative); the third derivatives equal central differences of the
   oracle's Hessian;
+* the near-origin series of D that the fp32 walks use for near cells equals
+  the oracle's Ewald sums within its radius (1e-7);
 * the nodes' S = sum m |r - X|^2 equals the oracle's (1e-12);
 * the periodic direct sum (table lookups) equals the oracle's exact one
   within the table's error, derived from the lookup's third-order remainder
@@ -29,7 +31,7 @@ import pytest
 
 from amr_inputs import maclaurin_spheroid, random_amr
 from oracle import OracleTree
-from oracle.oracle import ewald_hessian, fp32_band_for
+from oracle.oracle import ewald, ewald_hessian, fp32_band_for
 from periodic_bounds import (EPS_FP32_ROWS, EPS_FP64_ROWS, HESS_ERR, N_TABLE, TABLE_ERR, measured_lookup_errors,
                              storage_terms, walk_tolerance)
 
@@ -104,6 +106,31 @@ def test_table_equals_the_ewald_sums(L):
     pick = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1), (3, 2)]
     fd = np.stack([Hd[d][:, h] for h, d in pick], 1)
     assert np.max(np.abs(v[:, 10:20] - fd)) <= 1e-7 * np.max(np.abs(fd))
+    bh.close()
+
+
+@pytest.mark.parametrize("L", [1.0, 2.5])
+def test_near_series_equals_the_ewald_sums(L):
+    """The near-origin series of D L that the fp32 periodic walks use for near cells, against the oracle's
+    Ewald sums (O9) at random points within its radius: within 1e-7 (the fit's own check reports a few 1e-9;
+    the table's lookups measure about 1e-7).  The series is dimensionless, so it is the same for every box."""
+    bh = BarnesHut(random_amr(61, nbase=2, max_level=0))
+    table = B.bh_ewald_create(bh.ctx, L, N_TABLE)
+    c, radius, err = B.bh_ewald_near_series(bh.ctx, table)
+    B.bh_ewald_destroy(table)
+    assert radius >= 0.1 and err <= 5e-8
+    assert abs(c[1] - 2.0 * np.pi / 3.0) <= 1e-15
+    rng = np.random.default_rng(11)
+    d = rng.normal(size=(4000, 3))
+    u = d / np.linalg.norm(d, axis=1)[:, None] * (radius * rng.random(4000) ** (1.0 / 3.0))[:, None]
+    u[0] = 0.0
+    exact = ewald(u * L, L)[0] * L
+    X, Y, Z = (u ** 2).T
+    e1, e2, e3 = X + Y + Z, X * Y + Y * Z + Z * X, X * Y * Z
+    series = (c[0] + c[1] * e1 + c[2] * e1 ** 2 + c[3] * e2 + c[4] * e1 ** 3 + c[5] * e1 * e2 + c[6] * e3
+              + c[7] * e1 ** 4 + c[8] * e1 ** 2 * e2 + c[9] * e2 ** 2 + c[10] * e1 * e3)
+    assert np.max(np.abs(series - exact)) <= 1e-7
+    assert abs(c[0] - exact[0]) <= 1e-12  # D(0) L, the simple cubic lattice's constant
     bh.close()
 
 
