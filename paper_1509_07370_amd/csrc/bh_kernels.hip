@@ -113,19 +113,34 @@ __device__ void store_node(const MomOut &o, int id, double M, double X, double Y
 // ---------------------------------------------------------------- moments
 
 // Butterfly sum / max over the 8 lanes of an aligned group of 8 (every lane
-// ends with the same bits: each level adds the same two partial sums).
+// ends with the same bits: each level adds the same two partial sums), with
+// the lane exchanges as DPP moves rather than LDS permutes: lane ^ 1 and
+// lane ^ 2 are quad permutations; after them every lane of a quad holds the
+// quad's result, so the last level may take the other quad's from lane 7 - i
+// (the half-row mirror) instead of lane ^ 4 -- the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane 7 - i within each 8
 __device__ __forceinline__ double sum8(double v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
     return v;
 }
 __device__ __forceinline__ double max8(double v) {
-    for (int o = 1; o < 8; o <<= 1) {
-        const double u = __shfl_xor(v, o, 64);
-        v = u > v ? u : v;
-    }
-    return v;
+    double u = dpp_f64<kDppXor1>(v);
+    v = u > v ? u : v;
+    u = dpp_f64<kDppXor2>(v);
+    v = u > v ? u : v;
+    u = dpp_f64<kDppHalfMirror>(v);
+    return u > v ? u : v;
 }
 
 // One node from its 8 children held by the 8 lanes of a group (child c in
