@@ -1219,7 +1219,9 @@ struct TilesAcc {
         const bool any_own = __ballot(own) != 0;
         wave_lds_sync();
         real p = 0, x = 0, y = 0, z = 0;
-        if (!any_own)
+        if (sizeof(real) == 4 && !any_own)
+            near_lattice_acc(n, p, x, y, z);
+        else if (!any_own)
             for (int j = 0; j < 8 * n; j++) near_pair_acc<real, false>(me.x, me.y, me.z, T[j], p, x, y, z);
         else
             for (int j = 0; j < 8 * n; j++) near_pair_acc<real, true>(me.x, me.y, me.z, T[j], p, x, y, z);
@@ -1230,6 +1232,48 @@ struct TilesAcc {
             gz += (double)z;
         }
         wave_lds_sync();
+    }
+    // fp32 tiles away from the wavefront's cells, on the bottom nodes' cell
+    // lattice as in Tiles (the offsets a and a - h per axis serve the
+    // gradient too); the repacked node records sit behind the tile.
+    __device__ void near_lattice_acc(int n, real &p, real &x, real &y, real &z) {
+        const int lane = threadIdx.x & 63;
+        real *Pf = reinterpret_cast<real *>(T + 64);
+        if (lane < 8 * n) {
+            const V4 c = T[lane];
+            const int b = lane >> 3, k = lane & 7;
+            Pf[16 * b + 6 + k] = c.w;
+            if (k == 0) {
+                Pf[16 * b + 0] = c.x;
+                Pf[16 * b + 1] = c.y;
+                Pf[16 * b + 2] = c.z;
+                Pf[16 * b + 3] = T[lane + 1].x - c.x;
+                Pf[16 * b + 4] = T[lane + 2].y - c.y;
+                Pf[16 * b + 5] = T[lane + 4].z - c.z;
+            }
+        }
+        wave_lds_sync();
+        const V4 *P = T + 64;
+        for (int b = 0; b < n; b++) {
+            const V4 h1 = P[4 * b], h2 = P[4 * b + 1], h3 = P[4 * b + 2], h4 = P[4 * b + 3];
+            const real ax = me.x - h1.x, ay = me.y - h1.y, az = me.z - h1.z;
+            const real d[2][3] = {{ax, ay, az}, {ax - h1.w, ay - h2.x, az - h2.y}};
+            const real sq[2][3] = {{d[0][0] * d[0][0], d[0][1] * d[0][1], d[0][2] * d[0][2]},
+                                   {d[1][0] * d[1][0], d[1][1] * d[1][1], d[1][2] * d[1][2]}};
+            const real m[8] = {h2.z, h2.w, h3.x, h3.y, h3.z, h3.w, h4.x, h4.y};
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int i = k & 1, j = (k >> 1) & 1, l = k >> 2;
+                const real r2 = (sq[i][0] + sq[j][1]) + sq[l][2];
+                const real ri = rsq_any(r2);
+                const real mri = m[k] * ri;
+                const real w = mri * ri * ri;
+                p += mri;
+                x -= w * d[i][0];
+                y -= w * d[j][1];
+                z -= w * d[l][2];
+            }
+        }
     }
     __device__ void finish(const WalkArgs &a, int64_t cell) const {
         if (a.phi) a.phi[cell] = -a.G * phi;
