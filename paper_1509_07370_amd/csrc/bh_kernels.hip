@@ -1026,6 +1026,31 @@ __device__ __forceinline__ void near_pair_acc(real px, real py, real pz, const V
     gz -= w * dz;
 }
 
+// Repacks a staged near tile of n bottom nodes (T[8b + k] = cell k of node
+// b, Morton order: bit 0 x, bit 1 y, bit 2 z) into 16 values per node behind
+// it, at T + 64: the first cell, the lattice steps along x, y and z, then the
+// 8 masses (four 16-byte records per node).  The 8 cells of a bottom node are
+// the corners of a cube, so a pair needs only the target's offsets to the
+// first cell and to the far corner per axis.
+__device__ __forceinline__ void near_lattice_pack(float4 *T, int n) {
+    const int lane = threadIdx.x & 63;
+    float *P = reinterpret_cast<float *>(T + 64);
+    if (lane < 8 * n) {
+        const float4 c = T[lane];
+        const int b = lane >> 3, k = lane & 7;
+        P[16 * b + 6 + k] = c.w;
+        if (k == 0) {
+            P[16 * b + 0] = c.x;
+            P[16 * b + 1] = c.y;
+            P[16 * b + 2] = c.z;
+            P[16 * b + 3] = T[lane + 1].x - c.x;
+            P[16 * b + 4] = T[lane + 2].y - c.y;
+            P[16 * b + 5] = T[lane + 4].z - c.z;
+        }
+    }
+    wave_lds_sync();
+}
+
 // Per-wavefront tile evaluation.  Far tile: up to 64 node records (3 x V4
 // each) staged in T by lane, then read back by every lane as broadcasts.
 // Near tile: up to 8 bottom nodes = 64 cells.  Each tile is summed in `real`
@@ -1102,31 +1127,12 @@ struct Tiles {
         wave_lds_sync();
         near_sum(n, any_own, keep);
     }
-    // fp32 tiles that hold none of the wavefront's cells: the 8 cells of a
-    // bottom node are the corners of a cube of side h (Morton order: bit 0 x,
-    // bit 1 y, bit 2 z), so a lane needs its offsets (a, a - h) to the node's
-    // first cell per axis, their squares, and one sum per pair.  Each node is
-    // repacked into 16 values -- first cell, the three lattice steps, the 8
-    // masses -- read back with four broadcasts instead of eight.
+    // fp32 tiles that hold none of the wavefront's cells, on the bottom
+    // nodes' cell lattice (near_lattice_pack): a lane takes its offsets a and
+    // a - h to each node's first cell per axis and their squares once per
+    // node, and one sum per pair; the repacked node is read back with four
+    // broadcasts instead of eight.
     static constexpr bool kLattice = sizeof(real) == 4;
-    __device__ void near_pack(int n) {
-        const int lane = threadIdx.x & 63;
-        real *P = reinterpret_cast<real *>(T + 64);
-        if (lane < 8 * n) {
-            const V4 c = T[lane];
-            const int b = lane >> 3, k = lane & 7;
-            P[16 * b + 6 + k] = c.w;
-            if (k == 0) {
-                P[16 * b + 0] = c.x;
-                P[16 * b + 1] = c.y;
-                P[16 * b + 2] = c.z;
-                P[16 * b + 3] = T[lane + 1].x - c.x;
-                P[16 * b + 4] = T[lane + 2].y - c.y;
-                P[16 * b + 5] = T[lane + 4].z - c.z;
-            }
-        }
-        wave_lds_sync();
-    }
     __device__ real near_lattice(int n) const {
         const V4 *P = T + 64;
         real part = 0;
@@ -1150,7 +1156,7 @@ struct Tiles {
     __device__ void near_sum(int n, bool any_own, bool keep) {
         real part = 0;
         if (kLattice && !any_own) {
-            near_pack(n);
+            if constexpr (kLattice) near_lattice_pack(T, n);
             part = near_lattice(n);
         } else if (!any_own) {
             for (int j = 0; j < 8 * n; j++) part = near_pair(me.x, me.y, me.z, T[j], part);
@@ -1237,22 +1243,7 @@ struct TilesAcc {
     // lattice as in Tiles (the offsets a and a - h per axis serve the
     // gradient too); the repacked node records sit behind the tile.
     __device__ void near_lattice_acc(int n, real &p, real &x, real &y, real &z) {
-        const int lane = threadIdx.x & 63;
-        real *Pf = reinterpret_cast<real *>(T + 64);
-        if (lane < 8 * n) {
-            const V4 c = T[lane];
-            const int b = lane >> 3, k = lane & 7;
-            Pf[16 * b + 6 + k] = c.w;
-            if (k == 0) {
-                Pf[16 * b + 0] = c.x;
-                Pf[16 * b + 1] = c.y;
-                Pf[16 * b + 2] = c.z;
-                Pf[16 * b + 3] = T[lane + 1].x - c.x;
-                Pf[16 * b + 4] = T[lane + 2].y - c.y;
-                Pf[16 * b + 5] = T[lane + 4].z - c.z;
-            }
-        }
-        wave_lds_sync();
+        if constexpr (sizeof(real) == 4) near_lattice_pack(T, n);
         const V4 *P = T + 64;
         for (int b = 0; b < n; b++) {
             const V4 h1 = P[4 * b], h2 = P[4 * b + 1], h3 = P[4 * b + 2], h4 = P[4 * b + 3];
