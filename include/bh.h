@@ -479,6 +479,17 @@ int bh_group_rms_error(bh_ctx *ctx, const bh_grid *grid, const double *phi_dev, 
  * input normalisation mean[12], scale[12] (copied).  Adam state starts at 0. */
 int bh_mlp_create(bh_ctx *ctx, bh_mlp **net, const float *params, const float *mean, const float *scale);
 int bh_mlp_set_params(bh_ctx *ctx, bh_mlp *net, const float *params);
+/* Smallest theta bh_theta_infer and bh_learned_walk_potential may return for
+ * this network, snapped up to the grid 0.20, 0.25, ..., 1.00 (default 0.20,
+ * the bottom of the grid).  A network trained on labels that never go below
+ * some theta extrapolates badly under it, and the walk's cost grows steeply
+ * as theta falls (the far-node count of a group goes roughly as 1/theta^3), so
+ * a handful of groups pushed there by the output shift can cost more than the
+ * rest of the grid; the floor is the smallest training label.  bh_mlp_forward
+ * (the continuous, unsnapped output used in training) is not affected.
+ * Returns BH_EINVAL unless 0.2 <= theta_floor <= 1.  Host-only; takes effect
+ * for launches enqueued after the call. */
+int bh_mlp_set_theta_floor(bh_ctx *ctx, bh_mlp *net, float theta_floor);
 /* Synchronising host copy of the parameters. */
 int bh_mlp_get_params(bh_ctx *ctx, const bh_mlp *net, float *params);
 /* theta_dev[n] = clamp(network(feat_dev[n][12]) - theta_shift, 0.05, 1).

@@ -98,6 +98,7 @@ _SIGS = {
     "bh_group_rms_error": (ctypes.c_int, [P, P, P, P, P]),
     "bh_mlp_create": (ctypes.c_int, [P, PP, P, P, P]),
     "bh_mlp_set_params": (ctypes.c_int, [P, P, P]),
+    "bh_mlp_set_theta_floor": (ctypes.c_int, [P, P, ctypes.c_float]),
     "bh_mlp_get_params": (ctypes.c_int, [P, P, P]),
     "bh_mlp_forward": (ctypes.c_int, [P, P, P, i64, ctypes.c_int, ctypes.c_float, P]),
     "bh_mlp_grad": (ctypes.c_int, [P, P, P, P, i64, P, P]),
@@ -424,6 +425,10 @@ def bh_mlp_forward(ctx, net, feat, theta, bf16=True, shift=0.0):
     _check(_lib.bh_mlp_forward(ctx, net, _dev(feat, "float32"), n, int(bool(bf16)), float(shift),
                                _dev(theta, "float32")), ctx)
     return theta
+
+
+def bh_mlp_set_theta_floor(ctx, net, theta_floor):
+    _check(_lib.bh_mlp_set_theta_floor(ctx, net, float(theta_floor)), ctx)
 
 
 def bh_learned_walk_potential(ctx, grid, m, net, shift, precision, G, phi, theta=None, counts=None):

@@ -28,6 +28,7 @@ struct bh_mlp {
     float *d_m = nullptr, *d_v = nullptr;         // Adam moments
     float *d_partials = nullptr;                  // [kMlpChunks][kMlpParams + 1]
     int step = 0;
+    int theta_floor_k = 0;  // inference never returns a theta below 0.20 + 0.05 * theta_floor_k
 };
 
 namespace bh {

@@ -246,6 +246,7 @@ ThetaNetArgs theta_net_args(const bh_grid *g, const bh_moments *m, const bh_mlp 
     a.mean = net->d_mean;
     a.scale = net->d_scale;
     a.shift = shift;
+    a.kmin = net->theta_floor_k;
     a.mom = m->d_mom;
     a.geom = g->d_geom;
     a.leaf_parent = g->d_leaf_parent;

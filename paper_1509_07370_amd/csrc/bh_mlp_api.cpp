@@ -121,6 +121,17 @@ int bh_mlp_set_params(bh_ctx *ctx, bh_mlp *net, const float *params) {
     return BH_OK;
 }
 
+int bh_mlp_set_theta_floor(bh_ctx *ctx, bh_mlp *net, float theta_floor) {
+    if (!ctx) return BH_EINVAL;
+    if (!net) return fail(ctx, BH_EINVAL, "network NULL");
+    if (!std::isfinite(theta_floor) || theta_floor < 0.2f || theta_floor > 1.0f)
+        return fail(ctx, BH_EINVAL, "theta_floor must lie in [0.2, 1]");
+    // the same snap as the inference: up to the next grid value, a value on the grid kept
+    const int k = (int)std::ceil((theta_floor - 1e-6f - 0.2f) * 20.0f);
+    net->theta_floor_k = k < 0 ? 0 : (k > 16 ? 16 : k);
+    return BH_OK;
+}
+
 int bh_mlp_get_params(bh_ctx *ctx, const bh_mlp *net, float *params) {
     int rc = require_gpu(ctx);
     if (rc) return rc;

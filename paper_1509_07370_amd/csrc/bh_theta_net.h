@@ -38,6 +38,7 @@ struct ThetaNetArgs {
     const uint16_t *w;  // bf16 parameters, layout above (16-byte aligned)
     const float *mean, *scale;
     float shift;
+    int kmin;  // smallest index on the grid 0.20 + 0.05 k the snapped theta may take
     const double *mom;
     const double *geom;
     const int32_t *leaf_parent;  // [n_leaf] parent node of the leaf block's node (the node itself at the root)
@@ -161,9 +162,10 @@ __device__ inline float groups_theta16(const ThetaNetArgs &n, const LeafInfo *le
     // safety shift are defined (the shift is calibrated charging each
     // prediction the error of the next grid value up): the walk then uses a
     // value whose error was measured, and a network saturating just below 1
-    // walks at 1
+    // walks at 1; the network's floor keeps a group off thetas below what it
+    // was trained on
     int kk = (int)ceilf((th - 1e-6f - 0.2f) * 20.0f);
-    kk = kk < 0 ? 0 : (kk > 16 ? 16 : kk);
+    kk = kk < n.kmin ? n.kmin : (kk > 16 ? 16 : kk);
     return (float)(0.2 + 0.05 * (double)kk);
 }
 

@@ -13,8 +13,14 @@ the grid {0.20, 0.25, ..., 1.00}:
   * "lagrange": the cost-aware split of one error budget over the groups,
     theta_g = argmin_theta cost_g(theta) + lambda err_g(theta)^2, with cost_g the
     group's walk time from a linear model of the counts (fitted to timed
-    sweeps) and lambda the median over the training grids of the multiplier
-    that makes a grid's global RMS meet the target.
+    sweeps) and lambda, per training grid, the smallest multiplier that makes
+    that grid's global RMS meet the target: each label is the group's theta in
+    the cheapest allocation that brings its own grid to the target.
+A network keeps the smallest label it was trained on as its theta floor
+(bh_mlp_set_theta_floor): under it the network extrapolates, and a group pushed
+there by the output shift walks far longer than the rest.  A network may be
+trained for another opening test or far-field order of bh_walk_potential_ex
+(the walk options, kept in its metadata with the floor).
 At run time the network's bf16 output drives bh_walk_potential; a 1% sample of
 cells is checked against the direct sum and a fixed conservative theta (0.4)
 is used instead if the sample misses the target.  calibrate_on_sample picks
@@ -23,6 +29,10 @@ choosing a fixed theta by a sweep).
 
 Usage on a GPU:
   python -m paper_1509_07370_amd.learned_theta train --target 1e-3 --out paper_1509_07370_amd/data/theta_mlp_1e-3.npz
+  python -m paper_1509_07370_amd.learned_theta train --target 1e-4 --labels lagrange \
+      --out paper_1509_07370_amd/data/theta_mlp_lagrange_1e-4.npz
+  python -m paper_1509_07370_amd.learned_theta train --target 1e-3 --labels lagrange --opening group_box --order 0 \
+      --out paper_1509_07370_amd/data/theta_mlp_paper_lagrange_1e-3.npz
 """
 from __future__ import annotations
 
@@ -39,6 +49,27 @@ from . import binding as B
 from .solver import BarnesHut
 
 THETA_GRID = np.round(np.arange(0.20, 1.0001, 0.05), 2)
+DEFAULT_WALK = (B.BH_MAC_CELLS, 2)  # (opening test, far-field order) of bh_walk_potential
+OPENING = {"cells": B.BH_MAC_CELLS, "group_box": B.BH_MAC_GROUP_BOX}
+
+
+def walk(bh, theta, theta_group, precision, G, phi, counts=None, options=DEFAULT_WALK):
+    """bh_walk_potential, or bh_walk_potential_ex for another opening test / far-field order."""
+    if tuple(options) == DEFAULT_WALK:
+        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, theta, theta_group, precision, G, phi, counts)
+    else:
+        B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, theta, theta_group, precision, G, phi, counts,
+                               mac=options[0], order=options[1])
+
+
+def learned_walk(bh, net, shift, precision, G, phi, theta, counts=None):
+    """The network's per-group thetas (into ``theta``), then the walk with them: the one fused call for the
+    default walk, bh_theta_infer then bh_walk_potential_ex for other walk options."""
+    if net.walk_options == DEFAULT_WALK:
+        B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, float(shift), precision, G, phi, theta, counts)
+    else:
+        B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, theta, float(shift))
+        walk(bh, 0.5, theta, precision, G, phi, counts, net.walk_options)
 FALLBACK_THETA = 0.4
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 
@@ -51,20 +82,21 @@ def direct_potential(bh: BarnesHut, rho: torch.Tensor) -> torch.Tensor:
 
 
 def error_table(bh: BarnesHut, rho: torch.Tensor, direct: torch.Tensor, thetas=THETA_GRID,
-                precision=B.BH_FP32) -> np.ndarray:
+                precision=B.BH_FP32, options=DEFAULT_WALK) -> np.ndarray:
     """[len(thetas), n_groups] per-group RMS relative error of the walk at each theta."""
     ng = bh.info["n_groups"]
     bh.build_moments(rho)
     phi = torch.empty_like(rho)
     rms = torch.empty((len(thetas), ng), dtype=torch.float32, device=rho.device)
     for k, th in enumerate(thetas):
-        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, float(th), None, precision, 1.0, phi, None)
+        walk(bh, float(th), None, precision, 1.0, phi, None, options)
         B.bh_group_rms_error(bh.ctx, bh.grid, phi, direct, rms[k])
     bh.check()
     return rms.cpu().numpy()
 
 
-def count_table(bh: BarnesHut, rho: torch.Tensor, thetas=THETA_GRID, precision=B.BH_FP32, reps=5):
+def count_table(bh: BarnesHut, rho: torch.Tensor, thetas=THETA_GRID, precision=B.BH_FP32, reps=5,
+                options=DEFAULT_WALK):
     """[len(thetas), n_groups, 2] far / near counts of every group at each theta, and the timed step (moments +
     fused walk and sums) in ms at each theta."""
     ng = bh.info["n_groups"]
@@ -75,9 +107,9 @@ def count_table(bh: BarnesHut, rho: torch.Tensor, thetas=THETA_GRID, precision=B
     for k, th in enumerate(thetas):
         def step(th=float(th)):
             bh.build_moments(rho)
-            B.bh_walk_potential(bh.ctx, bh.grid, bh.m, th, None, precision, 1.0, phi, None)
+            walk(bh, th, None, precision, 1.0, phi, None, options)
         step()
-        B.bh_walk_potential(bh.ctx, bh.grid, bh.m, float(th), None, precision, 1.0, phi, cn)
+        walk(bh, float(th), None, precision, 1.0, phi, cn, options)
         counts[k] = cn.cpu().numpy()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -141,6 +173,8 @@ class ThetaNet:
         self.scale = np.asarray(scale, np.float32)
         self.h = B.bh_mlp_create(ctx, params, self.mean, self.scale)
         self.meta = dict(meta or {})
+        if "theta_floor" in self.meta:
+            B.bh_mlp_set_theta_floor(ctx, self.h, self.meta["theta_floor"])
 
     @classmethod
     def fresh(cls, ctx, feat_host: np.ndarray, params, meta=None):
@@ -166,6 +200,16 @@ class ThetaNet:
     @property
     def shift(self) -> float:
         return float(self.meta.get("theta_shift", 0.0))
+
+    @property
+    def floor(self) -> float:
+        """Smallest theta the inference returns (the smallest training label; 0.2 for older networks)."""
+        return float(self.meta.get("theta_floor", 0.2))
+
+    @property
+    def walk_options(self):
+        """(opening test, far-field order) of the walk the network was trained for."""
+        return (int(self.meta.get("mac", DEFAULT_WALK[0])), int(self.meta.get("order", DEFAULT_WALK[1])))
 
     def predict(self, feat: torch.Tensor, bf16=True, out=None, shift=None) -> torch.Tensor:
         if out is None:
@@ -213,7 +257,7 @@ def solve_learned(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi: torch.Te
     sums with those thetas (the thetas used land in ``theta``).  ``feat`` is unused (kept for callers that
     stage features)."""
     bh.build_moments(rho)
-    B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, net.shift, precision, G, phi, theta)
+    learned_walk(bh, net, net.shift, precision, G, phi, theta)
     return phi
 
 
@@ -222,7 +266,7 @@ def solve_learned_two_step(bh: BarnesHut, rho: torch.Tensor, net: ThetaNet, phi:
     """The same step in two launches: bh_theta_infer, then bh_walk_potential with the theta array."""
     bh.build_moments(rho)
     B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, theta, net.shift)
-    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta, precision, G, phi, None)
+    walk(bh, 0.5, theta, precision, G, phi, None, net.walk_options)
     return phi
 
 
@@ -249,7 +293,7 @@ def calibrate_on_sample(bh, rho, net, phi, theta, target, precision=B.BH_FP32, m
     d = bh.direct(tg)
     for s_ in shifts:
         bh.build_moments(rho)
-        B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, float(s_), precision, 1.0, phi, theta)
+        learned_walk(bh, net, s_, precision, 1.0, phi, theta)
         rel = (phi.reshape(-1).index_select(0, tg) - d) / d
         if float(torch.sqrt((rel * rel).mean())) <= margin * target:
             net.meta["theta_shift"] = float(s_)
@@ -263,7 +307,7 @@ def solve_with_fallback(bh, rho, net, phi, feat, theta, target, precision=B.BH_F
     err = sampled_rms(bh, phi)
     if err <= target:
         return phi, dict(mode="learned", sampled_rms=err)
-    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, FALLBACK_THETA, None, precision, G, phi, None)
+    walk(bh, FALLBACK_THETA, None, precision, G, phi, None, net.walk_options)
     return phi, dict(mode="fallback", sampled_rms_learned=err, sampled_rms=sampled_rms(bh, phi))
 
 
@@ -309,6 +353,7 @@ def calibrate_shift(net, feats_per_grid, errs_per_grid, target, shifts=np.arange
         ok = True
         for f, e in zip(feats_per_grid, errs_per_grid):
             th = net.predict(torch.tensor(f, device="cuda"), bf16=True, shift=float(s)).cpu().numpy()
+            th = np.maximum(th, net.floor)
             if estimated_rms(e, th) > target:
                 ok = False
                 break
@@ -317,19 +362,19 @@ def calibrate_shift(net, feats_per_grid, errs_per_grid, target, shifts=np.arange
     return float(shifts[-1])
 
 
-def build_dataset(grids, target, log=print, labels="target"):
+def build_dataset(grids, target, log=print, labels="target", options=DEFAULT_WALK):
     feats, labs, errs, counts, times = [], [], [], [], []
     for g in grids:
         t0 = time.time()
         bh = BarnesHut(g)
         rho = torch.tensor(g.rho, device="cuda")
         direct = direct_potential(bh, rho)
-        table = error_table(bh, rho, direct)
+        table = error_table(bh, rho, direct, options=options)
         f = group_features(bh, rho).cpu().numpy()
         feats.append(f)
         errs.append(table)
         if labels == "lagrange":
-            c, ms = count_table(bh, rho)
+            c, ms = count_table(bh, rho, options=options)
             counts.append(c)
             times.append(ms)
         else:
@@ -340,11 +385,10 @@ def build_dataset(grids, target, log=print, labels="target"):
     if labels == "lagrange":
         model = fit_time_model(counts, times)
         lams = [lambda_for_target(e, c, model, target) for e, c in zip(errs, counts)]
-        lam = float(np.median(lams))
-        labs = [lagrangian_labels(e, c, model, lam) for e, c in zip(errs, counts)]
-        info = dict(time_model=model, lam=lam, grid_lams=lams)
-        log("time model: %.3e ms per far entry, %.3e per near entry, %.3f ms fixed; lambda %.3g (grids %s)" % (
-            model[0], model[1], model[2], lam, np.round(lams, 1).tolist()))
+        labs = [lagrangian_labels(e, c, model, lam) for e, c, lam in zip(errs, counts, lams)]
+        info = dict(time_model=model, grid_lams=lams)
+        log("time model: %.3e ms per far entry, %.3e per near entry, %.3f ms fixed; lambda per grid %s" % (
+            model[0], model[1], model[2], np.round(lams, 1).tolist()))
     for y in labs:
         log("mean label %.3f" % y.mean())
     return feats, labs, errs, info
@@ -380,7 +424,7 @@ def evaluate(net: ThetaNet, grids, target, precision=B.BH_FP32, reps=10, log=pri
         for th in THETA_GRID:
             def run(th=float(th)):
                 bh.build_moments(rho)
-                B.bh_walk_potential(bh.ctx, bh.grid, bh.m, th, None, precision, 1.0, phi, None)
+                walk(bh, th, None, precision, 1.0, phi, None, net.walk_options)
             ms = timed(run)
             fixed.append(dict(theta=float(th), rms=rms_of(phi), ms=ms))
         ms_l = timed(lambda: solve_learned(bh, rho, net, phi, feat, theta, precision))
@@ -426,6 +470,9 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--labels", choices=["target", "lagrange"], default="target")
     ap.add_argument("--extended", action="store_true", help="add the 3-level training meshes")
+    ap.add_argument("--opening", choices=sorted(OPENING), default="cells",
+                    help="opening test of the walk the labels come from (bh_walk_potential_ex)")
+    ap.add_argument("--order", type=int, choices=[0, 2], default=2, help="far-field order of that walk")
     args = ap.parse_args(argv)
     from amr_inputs.mlp_init import glorot_init
 
@@ -439,12 +486,14 @@ def main(argv=None):
         print(json.dumps(dict(target=net.meta.get("target"), shift=net.shift, results=res)))
         return 0
     target = float(args.target)
-    F, Y, E, info = build_dataset(training_grids(args.extended), target, log, labels=args.labels)
+    options = (OPENING[args.opening], args.order)
+    F, Y, E, info = build_dataset(training_grids(args.extended), target, log, labels=args.labels, options=options)
     X, y = np.concatenate(F), np.concatenate(Y)
     net = ThetaNet.fresh(ctx, X, glorot_init(42).astype(np.float32),
                          meta=dict(target=target, epochs=args.epochs, lr=args.lr, n_train=int(len(y)), seed=42,
                                    labels=args.labels, extended=bool(args.extended),
-                                   **{k: v for k, v in info.items() if k in ("time_model", "lam")}))
+                                   theta_floor=float(y.min()), mac=int(options[0]), order=int(options[1]),
+                                   **{k: v for k, v in info.items() if k in ("time_model", "grid_lams")}))
     fx = torch.tensor(X, device="cuda")
     fy = torch.tensor(y, device="cuda")
     t0 = time.time()

@@ -9,7 +9,10 @@
   given the same theta array, and the fallback triggers on an impossible target;
 * the one-pass inference (matrix-core network, 16 groups per wavefront) equals
   features + bf16 forward, snapped, on every group of a grid whose last
-  wavefront holds 8 groups.
+  wavefront holds 8 groups;
+* a network's theta floor lifts exactly the groups below it, in the inference
+  and in the fused learned walk, and a network trained for the paper's opening
+  test and monopole far field runs the walk with those options.
 """
 import numpy as np
 import pytest
@@ -269,7 +272,8 @@ def test_theta_infer_equals_the_oracle_features_and_bf16_network(which):
             bh.check()
             t = th.cpu().numpy().astype(np.float64)
             cont = omlp.forward_bf16(p, F, net.mean.astype(np.float64), net.scale.astype(np.float64)) - shift
-            want = omlp.snap_up(cont)
+            # the shipped network carries a floor (its smallest training label, on the grid)
+            want = np.maximum(omlp.snap_up(cont), net.floor)
             near_edge = np.abs((cont - 0.2) * 20.0 - np.round((cont - 0.2) * 20.0)) < 0.1
             same = np.abs(t - want) < 1e-6
             print("[theta_infer vs oracle] %s %s shift %.1f: %d groups, %d differ (%d near a grid edge), "
@@ -343,4 +347,53 @@ def test_what_the_shipped_networks_gain():
     print("[learned gain] target 1e-4: learned %.3f ms (%s), best fixed theta %.2f %.3f ms: x%.3f" % (
         ms_learned, info["mode"], best, ms_fixed, ms_fixed / ms_learned))
     net.close()
+    bh.close()
+
+
+def test_theta_floor_and_walk_options():
+    """bh_mlp_set_theta_floor: the inference returns max(theta, floor snapped up to the grid) for every group,
+    the fused learned walk writes and walks with the same thetas, out-of-range floors are rejected; a network
+    whose metadata names the group-cube opening test and the monopole far field drives bh_walk_potential_ex with
+    them."""
+    g = maclaurin_spheroid(max_level=1)
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    X = LT.group_features(bh, rho).cpu().numpy()
+    net = LT.ThetaNet.fresh(bh.ctx, X, (glorot_init(7) * 3).astype(np.float32))
+    free = torch.empty(ng, dtype=torch.float32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, free, 0.1)
+    t0 = free.cpu().numpy()
+    assert t0.min() < 0.5 < t0.max(), "the test needs predictions on both sides of the floor"
+    for floor, want_floor in ((0.5, 0.5), (0.52, 0.55), (0.2, 0.2), (1.0, 1.0)):
+        B.bh_mlp_set_theta_floor(bh.ctx, net.h, floor)
+        th = torch.empty_like(free)
+        B.bh_theta_infer(bh.ctx, bh.grid, bh.m, net.h, th, 0.1)
+        assert np.array_equal(th.cpu().numpy(), np.maximum(t0, np.float32(0.2 + 0.05 * round((want_floor - 0.2) * 20))))
+    B.bh_mlp_set_theta_floor(bh.ctx, net.h, 0.5)
+    phi, ref = torch.empty_like(rho), torch.empty_like(rho)
+    used = torch.empty_like(free)
+    B.bh_learned_walk_potential(bh.ctx, bh.grid, bh.m, net.h, 0.1, B.BH_FP32, 1.0, phi, used)
+    assert float(used.min()) == 0.5 and np.array_equal(used.cpu().numpy(), np.maximum(t0, np.float32(0.5)))
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, used, B.BH_FP32, 1.0, ref, None)
+    assert torch.equal(phi, ref)
+    for bad in (0.1, 1.5, float("nan")):
+        with pytest.raises(B.BHError):
+            B.bh_mlp_set_theta_floor(bh.ctx, net.h, bad)
+    net.close()
+    # the paper's walk options travel with the network
+    paper = LT.ThetaNet.fresh(bh.ctx, X, glorot_init(7).astype(np.float32),
+                              meta=dict(theta_floor=0.3, mac=B.BH_MAC_GROUP_BOX, order=0, theta_shift=0.05))
+    assert paper.walk_options == (B.BH_MAC_GROUP_BOX, 0) and paper.floor == 0.3
+    theta = torch.empty_like(free)
+    LT.solve_learned(bh, rho, paper, phi, None, theta)
+    assert float(theta.min()) >= 0.3
+    bh.build_moments(rho)
+    B.bh_walk_potential_ex(bh.ctx, bh.grid, bh.m, 0.5, theta, B.BH_FP32, 1.0, ref, None,
+                           mac=B.BH_MAC_GROUP_BOX, order=0)
+    assert torch.equal(phi, ref)
+    B.bh_walk_potential(bh.ctx, bh.grid, bh.m, 0.5, theta, B.BH_FP32, 1.0, ref, None)
+    assert not torch.equal(phi, ref)
+    paper.close()
     bh.close()
