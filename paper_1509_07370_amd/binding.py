@@ -77,6 +77,7 @@ _SIGS = {
     "bh_ewald_destroy": (ctypes.c_int, [P]),
     "bh_ewald_export": (ctypes.c_int, [P, P, P]),
     "bh_ewald_near_series": (ctypes.c_int, [P, P, P, P, P]),
+    "bh_ewald_set_local_budget": (ctypes.c_int, [P, P, f64, P]),
     "bh_moments_export_trace": (ctypes.c_int, [P, P, P]),
     "bh_walk_potential_periodic": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64, P, P]),
     "bh_direct_periodic": (ctypes.c_int, [P, P, P, P, P, i64, f64, P]),
@@ -353,6 +354,15 @@ def bh_ewald_export(ctx, table, n_points):
 
 
 EWALD_NEAR_TERMS = 11
+EWALD_LOCAL_BUDGET = 5e-5
+
+
+def bh_ewald_set_local_budget(ctx, table, budget):
+    """Error budget of the group-centre cubic of the fp32 periodic walks (0: off); returns the largest cell side
+    whose groups take it."""
+    h = ctypes.c_double()
+    _check(_lib.bh_ewald_set_local_budget(ctx, table, float(budget), ctypes.byref(h)), ctx)
+    return h.value
 
 
 def bh_ewald_near_series(ctx, table):

@@ -629,6 +629,15 @@ int bh_ewald_near_series(bh_ctx *ctx, const bh_ewald *e, double *coeffs, double 
     return BH_OK;
 }
 
+int bh_ewald_set_local_budget(bh_ctx *ctx, bh_ewald *e, double budget, double *h_max) {
+    if (!ctx) return BH_EINVAL;
+    if (!e) return fail(ctx, BH_EINVAL, "table handle is NULL");
+    if (!std::isfinite(budget) || budget < 0.0) return fail(ctx, BH_EINVAL, "budget must be finite and >= 0");
+    e->local_budget = budget;
+    if (h_max) *h_max = bh::ewald_local_hmax(e);
+    return BH_OK;
+}
+
 int bh_ewald_export(bh_ctx *ctx, const bh_ewald *e, double *values) {
     int rc = require_gpu(ctx);
     if (rc) return rc;

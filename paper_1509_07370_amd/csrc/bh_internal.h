@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -95,6 +96,8 @@ struct WalkArgs {
     double ewald_sp;
     int ewald_n;
     const float *ewald_near;  // near-origin series of D (fp32 periodic walks), or null
+    double ewald_local_hmax;  // fp32 periodic walks: groups of cells no larger sum D through one cubic about
+                              // the group centre (0: never)
     const double *node_s;
 };
 
@@ -138,6 +141,9 @@ constexpr int kEwaldValues = 20;  // D, gradient (3), Hessian (6), third derivat
 constexpr int kEwaldCompactFloats = 12;
 constexpr int kEwaldCompactDoubles = 12;
 constexpr int kEwaldNearTerms = 11;  // D0, the r^2 term, 9 terms of degree 4, 6 and 8
+// default error budget of the group-centre cubic of D (per unit mass, units of 1/L; the table's own
+// lookup bound is about 1.1e-6 at 33^3 points)
+constexpr double kEwaldLocalBudget = BH_EWALD_LOCAL_BUDGET;
 }
 
 // Every handle records the device it was created on: its destroy call frees
@@ -158,6 +164,9 @@ struct bh_ewald {
     float *d_near = nullptr;   // the coefficients in fp32, then near_radius^2
     double *d_t64c = nullptr;  // [n^3][12] compact rows of the fp64 walks and direct sum
     float *d_t32 = nullptr;    // [n^3][12] compact rows of the fp32 walks
+    // worst-case error per unit mass (in units of 1/L) that the fp32 walks may add by summing D over a group
+    // through one cubic about the group centre (0: every pair through its own table point)
+    double local_budget = bh::kEwaldLocalBudget;
 };
 
 struct bh_grid {
@@ -246,6 +255,16 @@ hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipSt
 hipError_t launch_ewald_table(const bh_ewald *e, hipStream_t s);
 hipError_t launch_ewald_points(double L, const double *u, int n, double *out, hipStream_t s);
 hipError_t fit_ewald_near_series(bh_ewald *e, hipStream_t s);
+// Largest cell side whose 64-cell wavefronts sum D through the group-centre
+// cubic within the table's budget: 32 (w + u)^4 <= budget (units of L), with
+// w = sqrt(3) sp / (2L) the reach of a pair lookup and u = 1.5 sqrt(3) h / L
+// the farthest cell centre of a 4x4x4 octant from its centre.
+inline double ewald_local_hmax(const bh_ewald *e) {
+    if (!(e->local_budget > 0.0)) return 0.0;
+    const double reach = std::pow(e->local_budget / 32.0, 0.25);
+    const double u = reach - std::sqrt(3.0) * 0.5 * e->sp / e->L;
+    return u > 0.0 ? u * e->L / (1.5 * std::sqrt(3.0)) : 0.0;
+}
 hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
                                           const float *theta_group, int precision, double G, double *phi,
                                           int32_t *counts, hipStream_t s);

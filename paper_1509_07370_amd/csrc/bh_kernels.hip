@@ -1283,6 +1283,49 @@ struct TilesAcc {
 // A near pair adds m psi(R) = m (1/|R| + D(R)), the cell itself m D(0).
 // The staged far record: (X', M), the quadrupole as in the path's far
 // record, and S in the third vector's third slot.
+// Sum over the wavefront of an fp32 value, complete in lane 63: butterflies
+// within rows of 16 lanes (quad permutations, half-row and row mirrors), then
+// the row sums carried across rows by the row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ float wave_total_f32(float v) {
+    int t;
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false);
+    v += __int_as_float(t);
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false);
+    v += __int_as_float(t);
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false);
+    v += __int_as_float(t);
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false);
+    v += __int_as_float(t);
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false);
+    v += __int_as_float(t);
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false);
+    v += __int_as_float(t);
+    return v;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+// Coefficients of the group-centre cubic of the smooth part, in u / L (u the
+// cell's offset from the octant centre): 0 the value; 1-3 the gradient x y z;
+// 4-9 second derivatives xx yy zz xy xz yz; 10-19 third derivatives in the
+// table's order xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz.
+constexpr int kLocalCoefs = 20;
+
+__device__ __forceinline__ double local_cubic(const double (&c)[kLocalCoefs], double x, double y, double z) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    const double lin = c[0] + (c[1] * x + c[2] * y + c[3] * z);
+    const double quad = 0.5 * (c[4] * xx + c[5] * yy + c[6] * zz) + (c[7] * x * y + c[8] * x * z + c[9] * y * z);
+    const double cube = (c[10] * xx * x + c[11] * yy * y + c[12] * zz * z) / 6.0 +
+                        0.5 * (c[13] * xx * y + c[14] * xx * z + c[15] * x * yy + c[16] * yy * z + c[17] * x * zz +
+                               c[18] * y * zz) +
+                        c[19] * x * y * z;
+    return lin + quad + cube;
+}
+
 template <typename real>
 struct TilesPeriodic {
     using V4 = typename Prec<real>::V4;
@@ -1299,6 +1342,11 @@ struct TilesPeriodic {
     const float *near_c;  // series of D L near the origin (fp32 walks), then the radius^2; null: table only
     real cg[3], box, box_inv, bg;
     real dscale, qscale;  // table value -> D, and the Q:H sum -> Q:H / 6 (fp32 rows are scaled by powers of L)
+    // group-centre cubic of the smooth part (fp32 walks of small enough cells): lane c < 20 holds coefficient c
+    // of sum_s [m_s D + Q_s : H / 6 + bg S_s](c + u) in u / L, c the octant's centre (local_coef_order below)
+    bool local;
+    real local_lim;  // a source at |R_a| <= local_lim on every axis has one nearest image for every cell
+    double loc;
 
     __device__ void setup(const WalkArgs &a, const LeafInfo &L, int sub) {
 #pragma clang fp contract(off)
@@ -1322,8 +1370,13 @@ struct TilesPeriodic {
         qscale = (real)(1.0 / ((sizeof(real) == 4 ? 3.0 : 6.0) * a.box * a.box * a.box));
         node_s = a.node_s;
         near_c = sizeof(real) == 4 ? a.ewald_near : nullptr;
+        local = sizeof(real) == 4 && L.h <= a.ewald_local_hmax;
+        local_lim = (real)(0.5 * a.box - 1.5 * L.h - 1e-5 * a.box);
     }
-    __device__ void init() { acc_far = acc_near = 0.0; }
+    __device__ void init() {
+        acc_far = acc_near = 0.0;
+        loc = 0.0;
+    }
     __device__ real image(real x, real c) const { return x - box * rint((x - c) * box_inv); }
 
     __device__ void load(int64_t id, V4 &a, V4 &b, V4 &c) const {
@@ -1347,6 +1400,109 @@ struct TilesPeriodic {
             put(lane, a, b, c);
         }
         wave_lds_sync();
+    }
+    // One source's part of the group-centre cubic: the source at R = c - X
+    // from the octant centre, the table's cubic about R's point (the
+    // expansion a pair lookup makes) re-expanded about u = 0 and mass
+    // weighted; a far node (q, w not null: q = (Qxx/2, Qyy/2, Qzz/2, Qxy),
+    // w = (Qxz, Qyz, S, -)) adds its quadrupole's Hessian term, whose Hessian
+    // is first order in the offset as in far_eval, and bg S.  Odd powers of a
+    // coordinate take the sign of R's coordinate (the table is folded).
+    __device__ void local_source(float Rx, float Ry, float Rz, float m, const float4 *q, const float4 *w,
+                                 float (&c)[kLocalCoefs]) const {
+        const EwaldPoint<float> p = ewald_point(ew, Rx, Ry, Rz);
+        float v[kEwaldValues];
+        ewald_fetch(ew, p.row, v);
+        const float x = p.dx, y = p.dy, z = p.dz;
+        const float kxx = v[10] * x + v[13] * y + v[14] * z;
+        const float kyy = v[15] * x + v[11] * y + v[16] * z;
+        const float kzz = v[17] * x + v[18] * y + v[12] * z;
+        const float kxy = v[13] * x + v[15] * y + v[19] * z;
+        const float kxz = v[14] * x + v[19] * y + v[17] * z;
+        const float kyz = v[19] * x + v[16] * y + v[18] * z;
+        const float t3 = 1.0f / 3.0f;
+        // value D0 + d.(g + (H + K/3) d / 2), gradient g + (H + K/2) d, Hessian H + K (K = T d)
+        const float wx = (v[4] + kxx * t3) * x + (v[7] + kxy * t3) * y + (v[8] + kxz * t3) * z;
+        const float wy = (v[7] + kxy * t3) * x + (v[5] + kyy * t3) * y + (v[9] + kyz * t3) * z;
+        const float wz = (v[8] + kxz * t3) * x + (v[9] + kyz * t3) * y + (v[6] + kzz * t3) * z;
+        const float val = v[0] + x * (v[1] + 0.5f * wx) + y * (v[2] + 0.5f * wy) + z * (v[3] + 0.5f * wz);
+        const float gx = v[1] + (v[4] + 0.5f * kxx) * x + (v[7] + 0.5f * kxy) * y + (v[8] + 0.5f * kxz) * z;
+        const float gy = v[2] + (v[7] + 0.5f * kxy) * x + (v[5] + 0.5f * kyy) * y + (v[9] + 0.5f * kyz) * z;
+        const float gz = v[3] + (v[8] + 0.5f * kxz) * x + (v[9] + 0.5f * kyz) * y + (v[6] + 0.5f * kzz) * z;
+        const float sx = p.sx, sy = p.sy, sz = p.sz;
+        const float hxx = v[4] + kxx, hyy = v[5] + kyy, hzz = v[6] + kzz;
+        const float hxy = (v[7] + kxy) * (sx * sy), hxz = (v[8] + kxz) * (sx * sz), hyz = (v[9] + kyz) * (sy * sz);
+        const float txxx = sx * v[10], tyyy = sy * v[11], tzzz = sz * v[12], txxy = sy * v[13], txxz = sz * v[14];
+        const float txyy = sx * v[15], tyyz = sz * v[16], txzz = sx * v[17], tyzz = sy * v[18];
+        const float txyz = (sx * sy * sz) * v[19];
+        const float md = m * (float)dscale;
+        c[0] = md * val;
+        c[1] = md * (sx * gx);
+        c[2] = md * (sy * gy);
+        c[3] = md * (sz * gz);
+        c[4] = md * hxx;
+        c[5] = md * hyy;
+        c[6] = md * hzz;
+        c[7] = md * hxy;
+        c[8] = md * hxz;
+        c[9] = md * hyz;
+        c[10] = md * txxx;
+        c[11] = md * tyyy;
+        c[12] = md * tzzz;
+        c[13] = md * txxy;
+        c[14] = md * txxz;
+        c[15] = md * txyy;
+        c[16] = md * tyyz;
+        c[17] = md * txzz;
+        c[18] = md * tyzz;
+        c[19] = md * txyz;
+        if (q) {
+            const float4 Q = *q, W = *w;
+            const float qs = (float)qscale;
+            c[0] += qs * ((Q.x * hxx + Q.y * hyy + Q.z * hzz) + (Q.w * hxy + W.x * hxz + W.y * hyz)) + (float)bg * W.z;
+            c[1] += qs * ((Q.x * txxx + Q.y * txyy + Q.z * txzz) + (Q.w * txxy + W.x * txxz + W.y * txyz));
+            c[2] += qs * ((Q.x * txxy + Q.y * tyyy + Q.z * tyzz) + (Q.w * txyy + W.x * txyz + W.y * tyyz));
+            c[3] += qs * ((Q.x * txxz + Q.y * tyyz + Q.z * tzzz) + (Q.w * txyz + W.x * txzz + W.y * tyzz));
+        }
+    }
+    // the wavefront's sum of every lane's coefficients, added to lane c's loc
+    __device__ void local_add(const float (&c)[kLocalCoefs], int lane) {
+        int tv = 0;
+#pragma unroll
+        for (int k = 0; k < kLocalCoefs; k++) {
+            const int t = __builtin_amdgcn_readlane(__float_as_int(wave_total_f32(c[k])), 63);
+            tv = lane == k ? t : tv;
+        }
+        loc += (double)__int_as_float(tv);
+    }
+    // whether every staged source (lanes < n, the position in s) is at the same nearest image from all the
+    // octant's cells
+    __device__ bool local_ok(bool mine, float sx, float sy, float sz) const {
+        const bool bad = mine && (fabsf((float)cg[0] - sx) > (float)local_lim || fabsf((float)cg[1] - sy) > (float)local_lim ||
+                                  fabsf((float)cg[2] - sz) > (float)local_lim);
+        return __ballot(bad) == 0;
+    }
+    // a far tile of a local group: 1/|R| and the quadrupole pair by pair (the positions staged at the image
+    // nearest the octant centre), the smooth part through the cubic
+    __device__ void far_local(int n, int lane) {
+        const float4 *t = reinterpret_cast<const float4 *>(T);
+        const float4 m = reinterpret_cast<const float4 &>(me);
+        float part = 0.0f;
+        for (int j = 0; j < n; j++) {
+            const float4 p = t[3 * j], q = t[3 * j + 1], w = t[3 * j + 2];
+            const float dx = m.x - p.x, dy = m.y - p.y, dz = m.z - p.z;
+            const float ri = rsq_any(dx * dx + dy * dy + dz * dz);
+            const float ri2 = ri * ri;
+            const float quad = (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) + (q.w * dx * dy + w.x * dx * dz + w.y * dy * dz);
+            part += p.w * ri + quad * (ri2 * ri2 * ri);
+        }
+        acc_far += (double)part;
+        float c[kLocalCoefs] = {};
+        if (lane < n) {
+            const float4 p = t[3 * lane], q = t[3 * lane + 1], w = t[3 * lane + 2];
+            local_source((float)cg[0] - p.x, (float)cg[1] - p.y, (float)cg[2] - p.z, p.w, &q, &w, c);
+        }
+        local_add(c, lane);
     }
     // The cell's nearest image R of a staged position and its table point.
     struct Pair {
@@ -1411,6 +1567,17 @@ struct TilesPeriodic {
         return p.w * (ri + D * dscale) + quad * (ri2 * ri2 * ri) + qh + bg * u.z;
     }
     __device__ void sum_far(int n, bool keep = true) {
+        if constexpr (sizeof(real) == 4) {
+            if (local) {
+                const int lane = __lane_id();
+                const V4 p = T[3 * (lane < n ? lane : 0)];
+                if (local_ok(lane < n, p.x, p.y, p.z)) {
+                    far_local(n, lane);
+                    wave_lds_sync();
+                    return;
+                }
+            }
+        }
         const V4 *t = T;
         const real part = pipelined(
             n, [t](int j) { return t[3 * j]; },
@@ -1452,8 +1619,36 @@ struct TilesPeriodic {
         return part;
     }
     __device__ void near_tile(int lane, int n, int cid, bool keep = true) {
-        if (lane < 8 * n) T[lane] = cells[(int64_t)cid + (lane & 7)];
+        V4 s{};
+        if (lane < 8 * n) {
+            s = cells[(int64_t)cid + (lane & 7)];
+            if (local) {  // at the image nearest the octant centre (pairs below take their own images anyway)
+                s.x = image(s.x, cg[0]);
+                s.y = image(s.y, cg[1]);
+                s.z = image(s.z, cg[2]);
+            }
+            T[lane] = s;
+        }
         wave_lds_sync();
+        if constexpr (sizeof(real) == 4) {
+            if (local && local_ok(lane < 8 * n, s.x, s.y, s.z)) {
+                const float4 *t = reinterpret_cast<const float4 *>(T);
+                real part = 0;
+                for (int j = 0; j < 8 * n; j++) {
+                    const float4 q = t[j];
+                    const float dx = me.x - q.x, dy = me.y - q.y, dz = me.z - q.z;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    part = fmaf(q.w, r2 > 0.0f ? rsq_any(r2) : 0.0f, part);
+                }
+                acc_near += (double)part;
+                float c[kLocalCoefs] = {};
+                if (lane < 8 * n) local_source((float)cg[0] - s.x, (float)cg[1] - s.y, (float)cg[2] - s.z, s.w, nullptr,
+                                               nullptr, c);
+                local_add(c, lane);
+                wave_lds_sync();
+                return;
+            }
+        }
         const V4 *t = T;
         real part = 0;
         bool done = false;
@@ -1469,7 +1664,19 @@ struct TilesPeriodic {
         if (keep) acc_near += (double)part;
         wave_lds_sync();
     }
-    __device__ void finish(const WalkArgs &a, int64_t cell) const { a.phi[cell] = -a.G * (acc_far + acc_near); }
+    __device__ void finish(const WalkArgs &a, int64_t cell) const {
+        double smooth = 0.0;
+        if constexpr (sizeof(real) == 4) {
+            if (local) {
+                double c[kLocalCoefs];
+#pragma unroll
+                for (int k = 0; k < kLocalCoefs; k++) c[k] = readlane_f64(loc, k);
+                smooth = local_cubic(c, (double)((me.x - cg[0]) * box_inv), (double)((me.y - cg[1]) * box_inv),
+                                     (double)((me.z - cg[2]) * box_inv));
+            }
+        }
+        a.phi[cell] = -a.G * (acc_far + acc_near + smooth);
+    }
 };
 
 struct PotArgs {
@@ -1877,6 +2084,7 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     a.box = g->topo.box;
     a.ewald = precision == BH_FP64 ? (const void *)e->d_t64c : (const void *)e->d_t32;
     a.ewald_near = precision == BH_FP32 && e->near_radius > 0.0 ? e->d_near : nullptr;
+    a.ewald_local_hmax = precision == BH_FP32 && g->group_cells >= 64 ? ewald_local_hmax(e) : 0.0;
     a.ewald_sp = e->sp;
     a.ewald_n = e->n;
     a.node_s = m->d_s;

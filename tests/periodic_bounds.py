@@ -12,6 +12,11 @@ N_TABLE^3 points on [0, 1/2]^3 (spacing sp = 1/64).
   largest |H| L^3 and |T| L^4, the rounding changes D by at most
   eps (Hs (3u)^2 / 2 + Ts (3u)^3 / 6) / L per unit mass and the Hessian by at
   most eps (Hs + 3u Ts) / L^3 per unit of sum_ab |Q_ab| / 6.
+* Group-centre cubic (fp32 walks, groups of small cells): the same
+  expansions reach |delta| <= sqrt(3) sp / 2 + |u|max, u the offset of a cell
+  from the centre of its 4x4x4 octant (|u_a| <= 1.5 h per axis), so the bounds
+  above are taken at that reach (local_reach) and the storage terms with
+  |u_a| <= sp / (2L) + 1.5 h / L.
 """
 import numpy as np
 
@@ -24,22 +29,35 @@ EPS_FP32_ROWS = 2.0 ** -11         # fp16 storage in the fp32 walks' rows
 EPS_FP64_ROWS = 2.0 ** -24         # fp32 storage in the fp64 rows
 
 
-def storage_terms(table_values, L, eps):
+def storage_terms(table_values, L, eps, h_local=0.0):
     """(per unit mass, per unit of sum |Q| / 6) changes from the rows' storage;
-    table_values: the fp64 export [n, n, n, 20]."""
+    table_values: the fp64 export [n, n, n, 20]; h_local: the cell side of a
+    group summed through the group-centre cubic (0: pair lookups)."""
     v = table_values.reshape(-1, 20)
     Hs = np.max(np.abs(v[:, 4:10])) * L ** 3
     Ts = np.max(np.abs(v[:, 10:20])) * L ** 4
-    u3 = 3 * (0.5 * L / (N_TABLE - 1)) / (2 * L)
+    u3 = 3 * ((0.5 * L / (N_TABLE - 1)) / (2 * L) + 1.5 * h_local / L)
     return eps * (0.5 * Hs * u3 ** 2 + Ts * u3 ** 3 / 6) / L, eps * (Hs + u3 * Ts) / L ** 3
 
 
-def walk_tolerance(masses_sum, qsum, L, storage, fp32):
-    """Per-group bound: table (D and, weighted by the group's far-node sum |Q| / 6, the Hessian), storage, and in
-    fp32 the rounding of O(1) terms (relative 1e-6 of sum m / d over the box, about 3 sum m / L) that cancel to the
-    small periodic potential."""
+def local_reach(h, L):
+    """|delta| / L the group-centre cubic reaches for a group of cells of side h."""
+    return DELTA + 1.5 * np.sqrt(3.0) * h / L
+
+
+def local_hmax(budget, L):
+    """Largest cell side whose groups take the group-centre cubic at an error budget (per unit mass, units of
+    1/L): D4 reach^4 / 24 <= budget."""
+    u = (budget * 24.0 / D4) ** 0.25 - DELTA
+    return max(u, 0.0) * L / (1.5 * np.sqrt(3.0))
+
+
+def walk_tolerance(masses_sum, qsum, L, storage, fp32, delta=DELTA):
+    """Per-group bound: table (D and, weighted by the group's far-node sum |Q| / 6, the Hessian, both at the
+    expansion's reach delta), storage, and in fp32 the rounding of O(1) terms (relative 1e-6 of sum m / d over the
+    box, about 3 sum m / L) that cancel to the small periodic potential."""
     ds, hs = storage
-    tol = TABLE_ERR * masses_sum / L + HESS_ERR * qsum + ds * masses_sum + hs * qsum
+    tol = D4 * delta ** 4 / 24 * masses_sum / L + D4 * delta ** 2 / 2 * qsum + ds * masses_sum + hs * qsum
     if fp32:
         tol = tol + 3e-6 * 3 * masses_sum / L
     return tol
