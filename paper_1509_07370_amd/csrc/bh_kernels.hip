@@ -1303,12 +1303,6 @@ __device__ __forceinline__ float wave_total_f32(float v) {
     return v;
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int k) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
-    return __hiloint2double(hi, lo);
-}
-
 // Coefficients of the group-centre cubic of the smooth part, in u / L (u the
 // cell's offset from the octant centre): 0 the value; 1-3 the gradient x y z;
 // 4-9 second derivatives xx yy zz xy xz yz; 10-19 third derivatives in the
@@ -1326,7 +1320,9 @@ __device__ __forceinline__ double local_cubic(const double (&c)[kLocalCoefs], do
     return lin + quad + cube;
 }
 
-template <typename real>
+// LOCAL: the group-centre cubic of the smooth part is compiled in (fp32, one
+// group per wavefront).
+template <typename real, bool LOCAL = false>
 struct TilesPeriodic {
     using V4 = typename Prec<real>::V4;
     static constexpr bool kNearAsync = false;
@@ -1342,11 +1338,12 @@ struct TilesPeriodic {
     const float *near_c;  // series of D L near the origin (fp32 walks), then the radius^2; null: table only
     real cg[3], box, box_inv, bg;
     real dscale, qscale;  // table value -> D, and the Q:H sum -> Q:H / 6 (fp32 rows are scaled by powers of L)
-    // group-centre cubic of the smooth part (fp32 walks of small enough cells): lane c < 20 holds coefficient c
-    // of sum_s [m_s D + Q_s : H / 6 + bg S_s](c + u) in u / L, c the octant's centre (local_coef_order below)
+    // group-centre cubic of the smooth part (fp32 walks of small enough cells): the coefficients of
+    // sum_s [m_s D + Q_s : H / 6 + bg S_s](c + u) in u / L, c the octant's centre (order of kLocalCoefs), summed
+    // by each lane over the sources it took, in its own slice of LDS, then over the wavefront once per group
     bool local;
     real local_lim;  // a source at |R_a| <= local_lim on every axis has one nearest image for every cell
-    double loc;
+    float4 *lsum;    // [kLocalCoefs / 4][64] float4 of this wavefront
 
     __device__ void setup(const WalkArgs &a, const LeafInfo &L, int sub) {
 #pragma clang fp contract(off)
@@ -1370,12 +1367,22 @@ struct TilesPeriodic {
         qscale = (real)(1.0 / ((sizeof(real) == 4 ? 3.0 : 6.0) * a.box * a.box * a.box));
         node_s = a.node_s;
         near_c = sizeof(real) == 4 ? a.ewald_near : nullptr;
-        local = sizeof(real) == 4 && L.h <= a.ewald_local_hmax;
-        local_lim = (real)(0.5 * a.box - 1.5 * L.h - 1e-5 * a.box);
+        local = false;
+        if constexpr (LOCAL) {
+            static_assert(sizeof(real) == 4, "the group-centre cubic is an fp32 path");
+            local = L.h <= a.ewald_local_hmax;
+            local_lim = (real)(0.5 * a.box - 1.5 * L.h - 1e-5 * a.box);
+            __shared__ float4 lds_sums[4][kLocalCoefs / 4][64];
+            lsum = &lds_sums[threadIdx.x >> 6][0][0];
+        }
     }
     __device__ void init() {
         acc_far = acc_near = 0.0;
-        loc = 0.0;
+        if (LOCAL && local) {
+            const int lane = __lane_id();
+#pragma unroll
+            for (int k = 0; k < kLocalCoefs / 4; k++) lsum[64 * k + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
     }
     __device__ real image(real x, real c) const { return x - box * rint((x - c) * box_inv); }
 
@@ -1465,15 +1472,17 @@ struct TilesPeriodic {
             c[3] += qs * ((Q.x * txxz + Q.y * tyyz + Q.z * tzzz) + (Q.w * txyz + W.x * txzz + W.y * tyzz));
         }
     }
-    // the wavefront's sum of every lane's coefficients, added to lane c's loc
+    // a lane's coefficients added to its running sums (its own LDS slice: no other lane reads it before finish)
     __device__ void local_add(const float (&c)[kLocalCoefs], int lane) {
-        int tv = 0;
 #pragma unroll
-        for (int k = 0; k < kLocalCoefs; k++) {
-            const int t = __builtin_amdgcn_readlane(__float_as_int(wave_total_f32(c[k])), 63);
-            tv = lane == k ? t : tv;
+        for (int k = 0; k < kLocalCoefs / 4; k++) {
+            float4 t = lsum[64 * k + lane];
+            t.x += c[4 * k];
+            t.y += c[4 * k + 1];
+            t.z += c[4 * k + 2];
+            t.w += c[4 * k + 3];
+            lsum[64 * k + lane] = t;
         }
-        loc += (double)__int_as_float(tv);
     }
     // whether every staged source (lanes < n, the position in s) is at the same nearest image from all the
     // octant's cells
@@ -1567,7 +1576,7 @@ struct TilesPeriodic {
         return p.w * (ri + D * dscale) + quad * (ri2 * ri2 * ri) + qh + bg * u.z;
     }
     __device__ void sum_far(int n, bool keep = true) {
-        if constexpr (sizeof(real) == 4) {
+        if constexpr (LOCAL) {
             if (local) {
                 const int lane = __lane_id();
                 const V4 p = T[3 * (lane < n ? lane : 0)];
@@ -1622,7 +1631,7 @@ struct TilesPeriodic {
         V4 s{};
         if (lane < 8 * n) {
             s = cells[(int64_t)cid + (lane & 7)];
-            if (local) {  // at the image nearest the octant centre (pairs below take their own images anyway)
+            if (LOCAL && local) {  // at the image nearest the octant centre (pairs below take their own images anyway)
                 s.x = image(s.x, cg[0]);
                 s.y = image(s.y, cg[1]);
                 s.z = image(s.z, cg[2]);
@@ -1630,7 +1639,7 @@ struct TilesPeriodic {
             T[lane] = s;
         }
         wave_lds_sync();
-        if constexpr (sizeof(real) == 4) {
+        if constexpr (LOCAL) {
             if (local && local_ok(lane < 8 * n, s.x, s.y, s.z)) {
                 const float4 *t = reinterpret_cast<const float4 *>(T);
                 real part = 0;
@@ -1666,11 +1675,19 @@ struct TilesPeriodic {
     }
     __device__ void finish(const WalkArgs &a, int64_t cell) const {
         double smooth = 0.0;
-        if constexpr (sizeof(real) == 4) {
+        if constexpr (LOCAL) {
             if (local) {
+                const int lane = __lane_id();
                 double c[kLocalCoefs];
 #pragma unroll
-                for (int k = 0; k < kLocalCoefs; k++) c[k] = readlane_f64(loc, k);
+                for (int k = 0; k < kLocalCoefs / 4; k++) {
+                    const float4 t = lsum[64 * k + lane];
+                    const float v4[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        c[4 * k + i] = (double)__int_as_float(
+                            __builtin_amdgcn_readlane(__float_as_int(wave_total_f32(v4[i])), 63));
+                }
                 smooth = local_cubic(c, (double)((me.x - cg[0]) * box_inv), (double)((me.y - cg[1]) * box_inv),
                                      (double)((me.z - cg[2]) * box_inv));
             }
@@ -2074,7 +2091,7 @@ __global__ __launch_bounds__(256, WAVES) void walk_potential_periodic_kernel(Wal
     const int lane = threadIdx.x & 63;
     const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
     if (u < 0) return;
-    fused_group<real, TilesPeriodic<real>, 2, GM>(a, u, w, lane, sm);
+    fused_group<real, TilesPeriodic<real, sizeof(real) == 4 && GM == 1>, 2, GM>(a, u, w, lane, sm);
 }
 
 hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
