@@ -1051,6 +1051,29 @@ __device__ __forceinline__ void near_lattice_pack(float4 *T, int n) {
     wave_lds_sync();
 }
 
+// Sum of m / |x - cell| over the n packed nodes (near_lattice_pack) for the
+// lane's cell x: per node the offsets a and a - h to its first cell per axis
+// and their squares once, then per cell two adds, the rsqrt and one FMA.
+__device__ __forceinline__ float near_lattice_sum(const float4 *P, int n, float mx, float my, float mz) {
+    float part = 0.0f;
+    for (int b = 0; b < n; b++) {
+        const float4 h1 = P[4 * b], h2 = P[4 * b + 1], h3 = P[4 * b + 2], h4 = P[4 * b + 3];
+        const float ax = mx - h1.x, ay = my - h1.y, az = mz - h1.z;
+        const float bx = ax - h1.w, by = ay - h2.x, bz = az - h2.y;
+        const float x0 = ax * ax, x1 = bx * bx, y0 = ay * ay, y1 = by * by, z0 = az * az, z1 = bz * bz;
+        const float s00 = x0 + y0, s10 = x1 + y0, s01 = x0 + y1, s11 = x1 + y1;
+        part = fmaf(h2.z, __builtin_amdgcn_rsqf(s00 + z0), part);
+        part = fmaf(h2.w, __builtin_amdgcn_rsqf(s10 + z0), part);
+        part = fmaf(h3.x, __builtin_amdgcn_rsqf(s01 + z0), part);
+        part = fmaf(h3.y, __builtin_amdgcn_rsqf(s11 + z0), part);
+        part = fmaf(h3.z, __builtin_amdgcn_rsqf(s00 + z1), part);
+        part = fmaf(h3.w, __builtin_amdgcn_rsqf(s10 + z1), part);
+        part = fmaf(h4.x, __builtin_amdgcn_rsqf(s01 + z1), part);
+        part = fmaf(h4.y, __builtin_amdgcn_rsqf(s11 + z1), part);
+    }
+    return part;
+}
+
 // Per-wavefront tile evaluation.  Far tile: up to 64 node records (3 x V4
 // each) staged in T by lane, then read back by every lane as broadcasts.
 // Near tile: up to 8 bottom nodes = 64 cells.  Each tile is summed in `real`
@@ -1134,24 +1157,8 @@ struct Tiles {
     // broadcasts instead of eight.
     static constexpr bool kLattice = sizeof(real) == 4;
     __device__ real near_lattice(int n) const {
-        const V4 *P = T + 64;
-        real part = 0;
-        for (int b = 0; b < n; b++) {
-            const V4 h1 = P[4 * b], h2 = P[4 * b + 1], h3 = P[4 * b + 2], h4 = P[4 * b + 3];
-            const real ax = me.x - h1.x, ay = me.y - h1.y, az = me.z - h1.z;
-            const real bx = ax - h1.w, by = ay - h2.x, bz = az - h2.y;
-            const real x0 = ax * ax, x1 = bx * bx, y0 = ay * ay, y1 = by * by, z0 = az * az, z1 = bz * bz;
-            const real s00 = x0 + y0, s10 = x1 + y0, s01 = x0 + y1, s11 = x1 + y1;
-            part = fmaf(h2.z, rsq_any(s00 + z0), part);
-            part = fmaf(h2.w, rsq_any(s10 + z0), part);
-            part = fmaf(h3.x, rsq_any(s01 + z0), part);
-            part = fmaf(h3.y, rsq_any(s11 + z0), part);
-            part = fmaf(h3.z, rsq_any(s00 + z1), part);
-            part = fmaf(h3.w, rsq_any(s10 + z1), part);
-            part = fmaf(h4.x, rsq_any(s01 + z1), part);
-            part = fmaf(h4.y, rsq_any(s11 + z1), part);
-        }
-        return part;
+        if constexpr (kLattice) return near_lattice_sum(T + 64, n, me.x, me.y, me.z);
+        return 0;
     }
     __device__ void near_sum(int n, bool any_own, bool keep) {
         real part = 0;
@@ -1535,6 +1542,15 @@ struct TilesPeriodic {
     __device__ real pipelined(int n, At at, Eval eval) const {
         real part = 0;
         if (n <= 0) return part;
+        if constexpr (LOCAL) {  // fallback tiles of this kernel are few: one row at a time, fewer registers held
+            real v[kEwaldValues];
+            for (int j = 0; j < n; j++) {
+                const Pair c = pair_at(at(j));
+                ewald_fetch(ew, c.ep.row, v);
+                part += eval(c, v, j);
+            }
+            return part;
+        }
         Pair ca = pair_at(at(0)), cb;
         real va[kEwaldValues], vb[kEwaldValues];
         ewald_fetch(ew, ca.ep.row, va);
@@ -1641,13 +1657,22 @@ struct TilesPeriodic {
         wave_lds_sync();
         if constexpr (LOCAL) {
             if (local && local_ok(lane < 8 * n, s.x, s.y, s.z)) {
-                const float4 *t = reinterpret_cast<const float4 *>(T);
+                // the tile's nodes lie within L/2 - 1.5h of the octant centre, so the 8 cells of a node keep
+                // their lattice after the imaging above; tiles holding the wavefront's own cells skip the self
+                // pair pair by pair
+                const bool own = lane < 8 * n && cid >= own_lo && cid < own_lo + 64;
                 real part = 0;
-                for (int j = 0; j < 8 * n; j++) {
-                    const float4 q = t[j];
-                    const float dx = me.x - q.x, dy = me.y - q.y, dz = me.z - q.z;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    part = fmaf(q.w, r2 > 0.0f ? rsq_any(r2) : 0.0f, part);
+                if (__ballot(own) == 0) {
+                    near_lattice_pack(T, n);
+                    part = near_lattice_sum(T + 64, n, me.x, me.y, me.z);
+                } else {
+                    const float4 *t = reinterpret_cast<const float4 *>(T);
+                    for (int j = 0; j < 8 * n; j++) {
+                        const float4 q = t[j];
+                        const float dx = me.x - q.x, dy = me.y - q.y, dz = me.z - q.z;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        part = fmaf(q.w, r2 > 0.0f ? rsq_any(r2) : 0.0f, part);
+                    }
                 }
                 acc_near += (double)part;
                 float c[kLocalCoefs] = {};
@@ -2084,14 +2109,14 @@ hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, dou
 // (MAC mode 2), the sums through the periodic Green's function table
 // (TilesPeriodic).
 constexpr int kPeriodicWaves32 = 4, kPeriodicWaves64 = 2;
-template <typename real, int WAVES, int GM>
+template <typename real, int WAVES, int GM, bool LOCAL = false>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_periodic_kernel(WalkArgs a) {
     __shared__ FusedSmem<real, GM> sm;
     const int w = wave_index();
     const int lane = threadIdx.x & 63;
     const int64_t u = dispatch_unit(a, (int64_t)blockIdx.x * 4 + w);
     if (u < 0) return;
-    fused_group<real, TilesPeriodic<real, sizeof(real) == 4 && GM == 1>, 2, GM>(a, u, w, lane, sm);
+    fused_group<real, TilesPeriodic<real, LOCAL>, 2, GM>(a, u, w, lane, sm);
 }
 
 hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
@@ -2114,8 +2139,12 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
         else
             hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64, 1>), grid, block, 0, s, a);
     } else {
+        // groups summing D through the group-centre cubic only in the kernel compiled for it
         if (fused_gm(g) == 2)
             hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 2>), grid, block, 0, s, a);
+        else if (a.ewald_local_hmax > 0.0)
+            hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 1, true>), grid, block, 0, s,
+                               a);
         else
             hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 1>), grid, block, 0, s, a);
     }
