@@ -365,7 +365,9 @@ int bh_ewald_set_local_budget(bh_ctx *ctx, bh_ewald *table, double budget, doubl
  * as built by the last bh_build_moments. */
 int bh_moments_export_trace(bh_ctx *ctx, const bh_moments *m, double *S);
 /* The periodic walk and sum (above) in one launch; arguments as
- * bh_walk_potential.  The grid's box must be the table's (to 1e-12).  The
+ * bh_walk_potential.  In fp32, groups of cells no larger than the table's
+ * budget admits sum D through the group-centre cubic
+ * (bh_ewald_set_local_budget).  The grid's box must be the table's (to 1e-12).  The
  * fused walks' dispatch order and cost records apply as for
  * bh_walk_potential.  Errors: BH_EINVAL (theta, precision, G, box size),
  * BH_ESTATE, BH_EDEVICE; stack overflow as bh_walk_potential. */
