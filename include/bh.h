@@ -341,24 +341,26 @@ int bh_ewald_export(bh_ctx *ctx, const bh_ewald *table, double *values);
  * points and a second set of check points.  Errors: BH_EINVAL (NULL). */
 int bh_ewald_near_series(bh_ctx *ctx, const bh_ewald *table, double *coeffs, double *radius, double *max_err);
 /* Error budget of the group-centre cubic in the fp32 periodic walks.  D is
- * smooth, so over the cells x = c + u of a group (centre c) the sum over the
- * group's sources of m_s D(x - X_s) (and, for far nodes, the quadrupole's
- * Hessian term) is one cubic in u: each source's third-order expansion about
- * its table point (the same expansion a pair lookup makes) re-expanded about
- * u = 0, summed over the sources, and evaluated once per cell.  A pair then
- * costs what it costs without a box (1/|R| and the quadrupole), and each
- * source one table row per wavefront instead of one per pair.  The expansion
+ * smooth, so over the cells x = c + u near a centre c the sum over a group's
+ * sources of m_s D(x - X_s) (and, for far nodes, the quadrupole's Hessian
+ * term) is one cubic in u: each source's third-order expansion about its table
+ * point (the same expansion a pair lookup makes) re-expanded about u = 0,
+ * summed over the sources, and evaluated once per cell.  A pair then costs
+ * what it costs without a box (1/|R| and the quadrupole).  The expansion
  * reaches |delta| <= sqrt(3) sp / 2 + |u|max instead of sqrt(3) sp / 2, so its
  * remainder grows; with |D^(4)| <= 24 / (L/2)^5 it is at most
- * 32 |delta / L|^4 / L per unit mass.  A group takes this path when that bound
- * stays within budget (per unit mass, in units of 1/L; at creation
- * BH_EWALD_LOCAL_BUDGET, against about 1.1e-6 for a 33^3 table's own
- * lookup), its wavefront holds one group (group_cells >= 64), and every source
- * of a tile lies at the same nearest image from all its cells (else that tile
- * is summed pair by pair).  budget = 0: every pair through its own table
- * point.  *h_max (host, may be NULL): the largest cell side whose groups take
- * the path, 0 for none.  Errors: BH_EINVAL (NULL table, budget negative or not
- * finite). */
+ * 32 |delta / L|^4 / L per unit mass.  The centre is the wavefront's 4x4x4
+ * octant's (|u| <= 1.5 sqrt(3) h; one table row per source) when that bound
+ * stays within budget, else each bottom node's (2x2x2 cells, |u| <= sqrt(3)
+ * h / 2; eight cubics per wavefront, one table row per source and bottom
+ * node) when that one does, else every pair is looked up.  The budget is per
+ * unit mass, in units of 1/L: at creation BH_EWALD_LOCAL_BUDGET, against about
+ * 1.1e-6 for a 33^3 table's own lookup.  Only wavefronts holding one group
+ * (group_cells >= 64) take a cubic, and a tile any of whose sources lies at
+ * different nearest images from the octant's cells is summed pair by pair.
+ * budget = 0: every pair through its own table point.  *h_max (host, may be
+ * NULL): the largest cell side whose groups take a cubic, 0 for none.
+ * Errors: BH_EINVAL (NULL table, budget negative or not finite). */
 #define BH_EWALD_LOCAL_BUDGET 5e-5
 int bh_ewald_set_local_budget(bh_ctx *ctx, bh_ewald *table, double budget, double *h_max);
 /* Synchronising host copy of S = sum m |r - X|^2 of every node (by node id),

@@ -634,7 +634,7 @@ int bh_ewald_set_local_budget(bh_ctx *ctx, bh_ewald *e, double budget, double *h
     if (!e) return fail(ctx, BH_EINVAL, "table handle is NULL");
     if (!std::isfinite(budget) || budget < 0.0) return fail(ctx, BH_EINVAL, "budget must be finite and >= 0");
     e->local_budget = budget;
-    if (h_max) *h_max = bh::ewald_local_hmax(e);
+    if (h_max) *h_max = bh::ewald_local_hmax(e, bh::kLocalSpreadNode);
     return BH_OK;
 }
 

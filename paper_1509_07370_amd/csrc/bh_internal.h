@@ -96,8 +96,9 @@ struct WalkArgs {
     double ewald_sp;
     int ewald_n;
     const float *ewald_near;  // near-origin series of D (fp32 periodic walks), or null
-    double ewald_local_hmax;  // fp32 periodic walks: groups of cells no larger sum D through one cubic about
-                              // the group centre (0: never)
+    double ewald_local_hmax;  // fp32 periodic walks: groups of cells no larger sum D through cubics about the
+                              // centres of their bottom nodes (0: never)
+    double ewald_local_hoct;  // ... and no larger than this, through one cubic about the octant's centre
     const double *node_s;
 };
 
@@ -255,15 +256,17 @@ hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipSt
 hipError_t launch_ewald_table(const bh_ewald *e, hipStream_t s);
 hipError_t launch_ewald_points(double L, const double *u, int n, double *out, hipStream_t s);
 hipError_t fit_ewald_near_series(bh_ewald *e, hipStream_t s);
-// Largest cell side whose 64-cell wavefronts sum D through the group-centre
-// cubic within the table's budget: 32 (w + u)^4 <= budget (units of L), with
-// w = sqrt(3) sp / (2L) the reach of a pair lookup and u = 1.5 sqrt(3) h / L
-// the farthest cell centre of a 4x4x4 octant from its centre.
-inline double ewald_local_hmax(const bh_ewald *e) {
+// Largest cell side whose cubics of D stay within the table's budget:
+// 32 (w + u)^4 <= budget (units of L), with w = sqrt(3) sp / (2L) the reach of
+// a pair lookup and u = spread h / L the farthest cell centre from the
+// cubic's centre: 1.5 sqrt(3) for the centre of a 4x4x4 octant, sqrt(3) / 2
+// for the centre of a bottom node (2x2x2 cells).
+constexpr double kLocalSpreadOctant = 1.5 * 1.7320508075688772, kLocalSpreadNode = 0.5 * 1.7320508075688772;
+inline double ewald_local_hmax(const bh_ewald *e, double spread) {
     if (!(e->local_budget > 0.0)) return 0.0;
     const double reach = std::pow(e->local_budget / 32.0, 0.25);
     const double u = reach - std::sqrt(3.0) * 0.5 * e->sp / e->L;
-    return u > 0.0 ? u * e->L / (1.5 * std::sqrt(3.0)) : 0.0;
+    return u > 0.0 ? u * e->L / spread : 0.0;
 }
 hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
                                           const float *theta_group, int precision, double G, double *phi,

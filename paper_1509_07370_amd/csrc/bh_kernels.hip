@@ -1316,6 +1316,19 @@ __device__ __forceinline__ float wave_total_f32(float v) {
 // table's order xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz.
 constexpr int kLocalCoefs = 20;
 
+// Sum over the 8 lanes 8b..8b+7 of an fp32 value, in every one of them (quad
+// permutations, then the half-row mirror).
+__device__ __forceinline__ float group8_total_f32(float v) {
+    int t;
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false);
+    v += __int_as_float(t);
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false);
+    v += __int_as_float(t);
+    t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false);
+    v += __int_as_float(t);
+    return v;
+}
+
 __device__ __forceinline__ double local_cubic(const double (&c)[kLocalCoefs], double x, double y, double z) {
     const double xx = x * x, yy = y * y, zz = z * z;
     const double lin = c[0] + (c[1] * x + c[2] * y + c[3] * z);
@@ -1346,9 +1359,12 @@ struct TilesPeriodic {
     real cg[3], box, box_inv, bg;
     real dscale, qscale;  // table value -> D, and the Q:H sum -> Q:H / 6 (fp32 rows are scaled by powers of L)
     // group-centre cubic of the smooth part (fp32 walks of small enough cells): the coefficients of
-    // sum_s [m_s D + Q_s : H / 6 + bg S_s](c + u) in u / L, c the octant's centre (order of kLocalCoefs), summed
-    // by each lane over the sources it took, in its own slice of LDS, then over the wavefront once per group
-    bool local;
+    // sum_s [m_s D + Q_s : H / 6 + bg S_s](c + u) in u / L (order of kLocalCoefs), c the octant's centre, summed
+    // by each lane over the sources it took, in its own slice of LDS, then over the wavefront once per group.
+    // node8: one cubic per bottom node instead (lanes 8b..8b+7 hold the 8 cells of bottom node b of the
+    // octant), each about the node's centre and summed over its 8 lanes, each lane taking every 8th source
+    bool local, node8;
+    float lh;        // node8: h, the offset of a bottom node's centre from the octant's per axis; else 0
     real local_lim;  // a source at |R_a| <= local_lim on every axis has one nearest image for every cell
     float4 *lsum;    // [kLocalCoefs / 4][64] float4 of this wavefront
 
@@ -1378,6 +1394,8 @@ struct TilesPeriodic {
         if constexpr (LOCAL) {
             static_assert(sizeof(real) == 4, "the group-centre cubic is an fp32 path");
             local = L.h <= a.ewald_local_hmax;
+            node8 = local && L.h > a.ewald_local_hoct;
+            lh = node8 ? (float)h : 0.0f;
             local_lim = (real)(0.5 * a.box - 1.5 * L.h - 1e-5 * a.box);
             __shared__ float4 lds_sums[4][kLocalCoefs / 4][64];
             lsum = &lds_sums[threadIdx.x >> 6][0][0];
@@ -1392,6 +1410,8 @@ struct TilesPeriodic {
         }
     }
     __device__ real image(real x, real c) const { return x - box * rint((x - c) * box_inv); }
+    // the centre of this lane's cubic on axis d (cells in Morton order: lane bits 3, 4, 5 place the bottom node)
+    __device__ float lcentre(int d) const { return (float)cg[d] + (((__lane_id() >> (3 + d)) & 1) ? lh : -lh); }
 
     __device__ void load(int64_t id, V4 &a, V4 &b, V4 &c) const {
         a = rec[3 * id + 0];
@@ -1415,8 +1435,8 @@ struct TilesPeriodic {
         }
         wave_lds_sync();
     }
-    // One source's part of the group-centre cubic: the source at R = c - X
-    // from the octant centre, the table's cubic about R's point (the
+    // One source's part of the group-centre cubic, added to c: the source at
+    // R = c - X from the cubic's centre, the table's cubic about R's point (the
     // expansion a pair lookup makes) re-expanded about u = 0 and mass
     // weighted; a far node (q, w not null: q = (Qxx/2, Qyy/2, Qzz/2, Qxy),
     // w = (Qxz, Qyz, S, -)) adds its quadrupole's Hessian term, whose Hessian
@@ -1450,26 +1470,26 @@ struct TilesPeriodic {
         const float txyy = sx * v[15], tyyz = sz * v[16], txzz = sx * v[17], tyzz = sy * v[18];
         const float txyz = (sx * sy * sz) * v[19];
         const float md = m * (float)dscale;
-        c[0] = md * val;
-        c[1] = md * (sx * gx);
-        c[2] = md * (sy * gy);
-        c[3] = md * (sz * gz);
-        c[4] = md * hxx;
-        c[5] = md * hyy;
-        c[6] = md * hzz;
-        c[7] = md * hxy;
-        c[8] = md * hxz;
-        c[9] = md * hyz;
-        c[10] = md * txxx;
-        c[11] = md * tyyy;
-        c[12] = md * tzzz;
-        c[13] = md * txxy;
-        c[14] = md * txxz;
-        c[15] = md * txyy;
-        c[16] = md * tyyz;
-        c[17] = md * txzz;
-        c[18] = md * tyzz;
-        c[19] = md * txyz;
+        c[0] += md * val;
+        c[1] += md * (sx * gx);
+        c[2] += md * (sy * gy);
+        c[3] += md * (sz * gz);
+        c[4] += md * hxx;
+        c[5] += md * hyy;
+        c[6] += md * hzz;
+        c[7] += md * hxy;
+        c[8] += md * hxz;
+        c[9] += md * hyz;
+        c[10] += md * txxx;
+        c[11] += md * tyyy;
+        c[12] += md * tzzz;
+        c[13] += md * txxy;
+        c[14] += md * txxz;
+        c[15] += md * txyy;
+        c[16] += md * tyyz;
+        c[17] += md * txzz;
+        c[18] += md * tyzz;
+        c[19] += md * txyz;
         if (q) {
             const float4 Q = *q, W = *w;
             const float qs = (float)qscale;
@@ -1513,10 +1533,13 @@ struct TilesPeriodic {
             part += p.w * ri + quad * (ri2 * ri2 * ri);
         }
         acc_far += (double)part;
+        const float c0 = lcentre(0), c1 = lcentre(1), c2 = lcentre(2);
+        // the lane's sources: its own node, or (node8) every 8th node from its slot in the bottom node
+        const int step = node8 ? 8 : 64;
         float c[kLocalCoefs] = {};
-        if (lane < n) {
-            const float4 p = t[3 * lane], q = t[3 * lane + 1], w = t[3 * lane + 2];
-            local_source((float)cg[0] - p.x, (float)cg[1] - p.y, (float)cg[2] - p.z, p.w, &q, &w, c);
+        for (int j = node8 ? (lane & 7) : lane; j < n; j += step) {
+            const float4 p = t[3 * j], q = t[3 * j + 1], w = t[3 * j + 2];
+            local_source(c0 - p.x, c1 - p.y, c2 - p.z, p.w, &q, &w, c);
         }
         local_add(c, lane);
     }
@@ -1675,9 +1698,14 @@ struct TilesPeriodic {
                     }
                 }
                 acc_near += (double)part;
+                const float c0 = lcentre(0), c1 = lcentre(1), c2 = lcentre(2);
+                const float4 *t = reinterpret_cast<const float4 *>(T);
+                const int step = node8 ? 8 : 64;
                 float c[kLocalCoefs] = {};
-                if (lane < 8 * n) local_source((float)cg[0] - s.x, (float)cg[1] - s.y, (float)cg[2] - s.z, s.w, nullptr,
-                                               nullptr, c);
+                for (int j = node8 ? (lane & 7) : lane; j < 8 * n; j += step) {
+                    const float4 q = t[j];
+                    local_source(c0 - q.x, c1 - q.y, c2 - q.z, q.w, nullptr, nullptr, c);
+                }
                 local_add(c, lane);
                 wave_lds_sync();
                 return;
@@ -1710,11 +1738,12 @@ struct TilesPeriodic {
                     const float v4[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
                     for (int i = 0; i < 4; i++)
-                        c[4 * k + i] = (double)__int_as_float(
-                            __builtin_amdgcn_readlane(__float_as_int(wave_total_f32(v4[i])), 63));
+                        c[4 * k + i] = node8 ? (double)group8_total_f32(v4[i])
+                                             : (double)__int_as_float(__builtin_amdgcn_readlane(
+                                                   __float_as_int(wave_total_f32(v4[i])), 63));
                 }
-                smooth = local_cubic(c, (double)((me.x - cg[0]) * box_inv), (double)((me.y - cg[1]) * box_inv),
-                                     (double)((me.z - cg[2]) * box_inv));
+                smooth = local_cubic(c, (double)((me.x - lcentre(0)) * (float)box_inv),
+                                     (double)((me.y - lcentre(1)) * (float)box_inv), (double)((me.z - lcentre(2)) * (float)box_inv));
             }
         }
         a.phi[cell] = -a.G * (acc_far + acc_near + smooth);
@@ -2108,7 +2137,7 @@ hipError_t launch_walk_potential_opts(const bh_grid *g, const bh_moments *m, dou
 // Periodic box (appendix "Periodic boundaries"): the walk with nearest images
 // (MAC mode 2), the sums through the periodic Green's function table
 // (TilesPeriodic).
-constexpr int kPeriodicWaves32 = 4, kPeriodicWaves64 = 2;
+constexpr int kPeriodicWaves32 = 4, kPeriodicWaves64 = 2, kPeriodicWavesCubic = 4;
 template <typename real, int WAVES, int GM, bool LOCAL = false>
 __global__ __launch_bounds__(256, WAVES) void walk_potential_periodic_kernel(WalkArgs a) {
     __shared__ FusedSmem<real, GM> sm;
@@ -2126,7 +2155,9 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     a.box = g->topo.box;
     a.ewald = precision == BH_FP64 ? (const void *)e->d_t64c : (const void *)e->d_t32;
     a.ewald_near = precision == BH_FP32 && e->near_radius > 0.0 ? e->d_near : nullptr;
-    a.ewald_local_hmax = precision == BH_FP32 && g->group_cells >= 64 ? ewald_local_hmax(e) : 0.0;
+    const bool cubic = precision == BH_FP32 && g->group_cells >= 64;
+    a.ewald_local_hmax = cubic ? ewald_local_hmax(e, kLocalSpreadNode) : 0.0;
+    a.ewald_local_hoct = cubic ? ewald_local_hmax(e, kLocalSpreadOctant) : 0.0;
     a.ewald_sp = e->sp;
     a.ewald_n = e->n;
     a.node_s = m->d_s;
@@ -2143,8 +2174,8 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
         if (fused_gm(g) == 2)
             hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 2>), grid, block, 0, s, a);
         else if (a.ewald_local_hmax > 0.0)
-            hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 1, true>), grid, block, 0, s,
-                               a);
+            hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWavesCubic, 1, true>), grid, block, 0,
+                               s, a);
         else
             hipLaunchKernelGGL((walk_potential_periodic_kernel<float, kPeriodicWaves32, 1>), grid, block, 0, s, a);
     }

@@ -14,9 +14,10 @@ N_TABLE^3 points on [0, 1/2]^3 (spacing sp = 1/64).
   most eps (Hs + 3u Ts) / L^3 per unit of sum_ab |Q_ab| / 6.
 * Group-centre cubic (fp32 walks, groups of small cells): the same
   expansions reach |delta| <= sqrt(3) sp / 2 + |u|max, u the offset of a cell
-  from the centre of its 4x4x4 octant (|u_a| <= 1.5 h per axis), so the bounds
-  above are taken at that reach (local_reach) and the storage terms with
-  |u_a| <= sp / (2L) + 1.5 h / L.
+  from the cubic's centre: that of its 4x4x4 octant (|u_a| <= 1.5 h per axis)
+  or, for somewhat larger cells, that of its bottom node (|u_a| <= h / 2).  The
+  bounds above are taken at that reach (local_reach) and the storage terms
+  with |u_a| <= sp / (2L) + u_axis / L.
 """
 import numpy as np
 
@@ -29,27 +30,42 @@ EPS_FP32_ROWS = 2.0 ** -11         # fp16 storage in the fp32 walks' rows
 EPS_FP64_ROWS = 2.0 ** -24         # fp32 storage in the fp64 rows
 
 
-def storage_terms(table_values, L, eps, h_local=0.0):
+AXIS_OCTANT, AXIS_NODE = 1.5, 0.5  # largest per-axis offset of a cell from the cubic's centre, in cell sides
+
+
+def storage_terms(table_values, L, eps, u_axis=0.0):
     """(per unit mass, per unit of sum |Q| / 6) changes from the rows' storage;
-    table_values: the fp64 export [n, n, n, 20]; h_local: the cell side of a
-    group summed through the group-centre cubic (0: pair lookups)."""
+    table_values: the fp64 export [n, n, n, 20]; u_axis: the largest per-axis
+    offset of a cell from the centre of its group-centre cubic (0: pair
+    lookups)."""
     v = table_values.reshape(-1, 20)
     Hs = np.max(np.abs(v[:, 4:10])) * L ** 3
     Ts = np.max(np.abs(v[:, 10:20])) * L ** 4
-    u3 = 3 * ((0.5 * L / (N_TABLE - 1)) / (2 * L) + 1.5 * h_local / L)
+    u3 = 3 * ((0.5 * L / (N_TABLE - 1)) / (2 * L) + u_axis / L)
     return eps * (0.5 * Hs * u3 ** 2 + Ts * u3 ** 3 / 6) / L, eps * (Hs + u3 * Ts) / L ** 3
 
 
-def local_reach(h, L):
-    """|delta| / L the group-centre cubic reaches for a group of cells of side h."""
-    return DELTA + 1.5 * np.sqrt(3.0) * h / L
+def local_reach(h, L, axis=AXIS_OCTANT):
+    """|delta| / L the group-centre cubic reaches for cells of side h whose per-axis offset from its centre is at
+    most axis * h."""
+    return DELTA + np.sqrt(3.0) * axis * h / L
 
 
-def local_hmax(budget, L):
-    """Largest cell side whose groups take the group-centre cubic at an error budget (per unit mass, units of
-    1/L): D4 reach^4 / 24 <= budget."""
+def local_hmax(budget, L, axis=AXIS_OCTANT):
+    """Largest cell side taking a cubic with that spread at an error budget (per unit mass, units of 1/L):
+    D4 reach^4 / 24 <= budget."""
     u = (budget * 24.0 / D4) ** 0.25 - DELTA
-    return max(u, 0.0) * L / (1.5 * np.sqrt(3.0))
+    return max(u, 0.0) * L / (np.sqrt(3.0) * axis)
+
+
+def local_axis(h, budget, L):
+    """Per-axis spread (in cell sides) of the cubic a group of cells of side h takes in an fp32 periodic walk:
+    AXIS_OCTANT, AXIS_NODE, or 0 (every pair looked up)."""
+    if h <= local_hmax(budget, L, AXIS_OCTANT):
+        return AXIS_OCTANT
+    if h <= local_hmax(budget, L, AXIS_NODE):
+        return AXIS_NODE
+    return 0.0
 
 
 def walk_tolerance(masses_sum, qsum, L, storage, fp32, delta=DELTA):

@@ -15,8 +15,8 @@ import pytest
 from amr_inputs import cloud_core, maclaurin_spheroid
 from oracle import OracleTree
 from oracle.oracle import fp32_band_for
-from periodic_bounds import (DELTA, EPS_FP32_ROWS, N_TABLE, local_hmax, local_reach, storage_terms,
-                             walk_tolerance)
+from periodic_bounds import (AXIS_NODE, AXIS_OCTANT, DELTA, EPS_FP32_ROWS, N_TABLE, local_axis, local_hmax,
+                             local_reach, storage_terms, walk_tolerance)
 
 pytestmark = pytest.mark.gpu
 
@@ -207,10 +207,10 @@ def test_benchmark_mesh_accelerations():
 
 def test_benchmark_mesh_periodic_in_bench_configuration():
     """bh_walk_potential_periodic as bench.py times it (theta 1, fp32, 33^3 table, the default error budget of the
-    group-centre cubic: groups of the two finest levels sum D through it, the others look every pair up) on the
-    benchmark mesh: sampled groups (random, the heaviest, and one on each side of the cubic's cell-size limit)
-    against the oracle's O10 walk and sums, counts equal outside marginal groups, potentials within the derived
-    bound at each group's reach."""
+    group-centre cubic: groups of the two finest levels sum D through one cubic about their octant's centre, those
+    of level 1 through one per bottom node) on the benchmark mesh: sampled groups (random, the heaviest, and one of
+    each kind) against the oracle's O10 walk and sums, counts equal outside marginal groups, potentials within the
+    derived bound at each group's reach."""
     g = maclaurin_spheroid(e=0.9, a1=0.25, rho_in=1.0, rho_out=1e-5, nbase=4, max_level=3)
     assert g.box_size == 1.0
     bh = BarnesHut(g)
@@ -218,7 +218,7 @@ def test_benchmark_mesh_periodic_in_bench_configuration():
     ng = bh.info["n_groups"]
     table = B.bh_ewald_create(bh.ctx, g.box_size, N_TABLE)
     hmax = B.bh_ewald_set_local_budget(bh.ctx, table, B.EWALD_LOCAL_BUDGET)
-    assert abs(hmax - local_hmax(B.EWALD_LOCAL_BUDGET, g.box_size)) <= 1e-12
+    assert abs(hmax - local_hmax(B.EWALD_LOCAL_BUDGET, g.box_size, AXIS_NODE)) <= 1e-12
     phi = torch.empty_like(rho)
     counts = torch.zeros((ng, 2), dtype=torch.int32, device="cuda")
     bh.build_moments(rho)
@@ -227,9 +227,11 @@ def test_benchmark_mesh_periodic_in_bench_configuration():
     c = counts.cpu().numpy()
     heavy = np.argsort(c[:, 0] * 35 + c[:, 1] * 88)[-2:]
     hg_all = g.box_size / (g.nbase * 8 * 2.0 ** np.asarray(g.level)[np.asarray(g.leaf_blocks)[np.arange(ng) // 8]])
+    axis_all = np.array([local_axis(h, B.EWALD_LOCAL_BUDGET, g.box_size) for h in hg_all])
     rng = np.random.default_rng(5)
-    sides = [rng.choice(np.flatnonzero(hg_all > hmax)), rng.choice(np.flatnonzero(hg_all <= hmax))]
-    groups = np.unique(np.concatenate([rng.choice(ng, 4, replace=False), heavy, sides]))
+    kinds = [rng.choice(np.flatnonzero(axis_all == a)) for a in np.unique(axis_all)]
+    assert {AXIS_OCTANT, AXIS_NODE} <= set(np.unique(axis_all))
+    groups = np.unique(np.concatenate([rng.choice(ng, 4, replace=False), heavy, kinds]))
     t = OracleTree(g)
     ref, oc, qs = t.solve_groups_periodic(groups, theta=1.0, tau=TAU[B.BH_FP32], with_qsum=True)
     clean = oc[:, 3] == 0
@@ -239,14 +241,17 @@ def test_benchmark_mesh_periodic_in_bench_configuration():
     _, _, _, m = t.cells()
     exported = B.bh_ewald_export(bh.ctx, table, N_TABLE)
     hg = hg_all[groups][clean]
-    loc = hg <= hmax
+    ax = axis_all[groups][clean]
+    loc = ax > 0
     tol = np.array([walk_tolerance(m.sum(), qs[clean][k], g.box_size,
-                                   storage_terms(exported, g.box_size, EPS_FP32_ROWS, hg[k] if loc[k] else 0.0), True,
-                                   local_reach(hg[k], g.box_size) if loc[k] else DELTA) for k in range(len(hg))])
+                                   storage_terms(exported, g.box_size, EPS_FP32_ROWS, ax[k] * hg[k]), True,
+                                   local_reach(hg[k], g.box_size, ax[k]) if loc[k] else DELTA)
+                    for k in range(len(hg))])
     ratio = np.max(np.abs(got[clean] - ref[clean]), axis=1) / tol
-    print("[periodic full size] %d groups (%d through the group-centre cubic), largest diff/tolerance %.2e, "
-          "per group %s" % (clean.sum(), loc.sum(), ratio.max(), np.array2string(ratio, precision=2)))
-    assert loc.any() and (~loc).any()
+    print("[periodic full size] %d groups (%d through the octant's cubic, %d through bottom-node cubics), largest "
+          "diff/tolerance %.2e, per group %s" % (clean.sum(), (ax == AXIS_OCTANT).sum(), (ax == AXIS_NODE).sum(),
+                                                 ratio.max(), np.array2string(ratio, precision=2)))
+    assert (ax == AXIS_OCTANT).any() and (ax == AXIS_NODE).any()
     assert np.all(ratio <= 1.0), ratio
     B.bh_ewald_destroy(table)
     bh.close()

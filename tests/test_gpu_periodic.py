@@ -21,9 +21,10 @@ O9 and O10, through the C ABI.
   bound with the lookup's errors measured at random points, and a regression
   guard at 4x the largest difference the library gives today; the fp32 walks
   again with a wide error budget for the group-centre cubic of D (every group
-  of cells of side <= 0.071 sums D through one cubic about its centre), with
-  those groups' bounds taken at the cubic's reach; a tiny theta equals the GPU
-  periodic direct sum;
+  of cells of side <= 0.071 sums D through one cubic about its octant's
+  centre) and with a budget that sends the MacLaurin grid's groups through one
+  cubic per bottom node, those groups' bounds taken at the cubic's reach; a
+  tiny theta equals the GPU periodic direct sum;
 * bad arguments are refused.
 
 Error scale: periodic potentials have zero mean, so differences are taken
@@ -35,8 +36,8 @@ import pytest
 from amr_inputs import maclaurin_spheroid, random_amr
 from oracle import OracleTree
 from oracle.oracle import ewald, ewald_hessian, fp32_band_for
-from periodic_bounds import (DELTA, EPS_FP32_ROWS, EPS_FP64_ROWS, HESS_ERR, N_TABLE, TABLE_ERR, local_hmax,
-                             local_reach, measured_lookup_errors, storage_terms, walk_tolerance)
+from periodic_bounds import (AXIS_NODE, DELTA, EPS_FP32_ROWS, EPS_FP64_ROWS, HESS_ERR, N_TABLE, TABLE_ERR, local_axis,
+                             local_hmax, local_reach, measured_lookup_errors, storage_terms, walk_tolerance)
 
 pytestmark = pytest.mark.gpu
 
@@ -174,8 +175,12 @@ REGRESSION_MAX_DIFF = {
     # |delta| = 0.18 L, hence its larger differences, about 1% of their bound)
     ("random_amr", B.BH_FP32, 0.5, "wide"): 7.24e-4, ("maclaurin_l1", B.BH_FP32, 0.5, "wide"): 4.28e-7,
     ("random_amr", B.BH_FP32, 0.8, "wide"): 7.67e-4, ("maclaurin_l1", B.BH_FP32, 0.8, "wide"): 1.38e-6,
+    # fp32 with the bottom-node budget: maclaurin_l1 through one cubic per bottom node, random_amr pair by pair
+    ("random_amr", B.BH_FP32, 0.5, "node"): 7.98e-7, ("maclaurin_l1", B.BH_FP32, 0.5, "node"): 1.13e-7,
+    ("random_amr", B.BH_FP32, 0.8, "node"): 1.52e-6, ("maclaurin_l1", B.BH_FP32, 0.8, "node"): 2.67e-7,
 }
-WIDE_BUDGET = 5e-2  # groups of cells of side <= 0.071 (every group of both test grids) take the group-centre cubic
+WIDE_BUDGET = 5e-2  # groups of cells of side <= 0.071 (every group of both test grids) take the octant's cubic
+NODE_BUDGET = 1.5e-4  # cells of side 0.0127 < h <= 0.038 (maclaurin_l1's) take one cubic per bottom node
 
 
 def _group_h(g, gs):
@@ -196,15 +201,17 @@ def _oracle_groups(name, theta):
 
 
 @pytest.mark.parametrize("name", list(GRIDS))
-@pytest.mark.parametrize("precision,budget", [(B.BH_FP64, None), (B.BH_FP32, None), (B.BH_FP32, WIDE_BUDGET)])
+@pytest.mark.parametrize("precision,budget", [(B.BH_FP64, None), (B.BH_FP32, None), (B.BH_FP32, WIDE_BUDGET),
+                                              (B.BH_FP32, NODE_BUDGET)])
 @pytest.mark.parametrize("theta", [0.5, 0.8])
 def test_periodic_walk_equals_oracle(name, precision, budget, theta):
     g, bh, rho, table, t = setup(name)
     ng = bh.info["n_groups"]
     phi = torch.full_like(rho, float("nan"))
     counts = torch.full((ng, 2), -1, dtype=torch.int32, device="cuda")
-    hmax = B.bh_ewald_set_local_budget(bh.ctx, table, B.EWALD_LOCAL_BUDGET if budget is None else budget)
-    assert abs(hmax - local_hmax(B.EWALD_LOCAL_BUDGET if budget is None else budget, g.box_size)) <= 1e-12
+    eff = B.EWALD_LOCAL_BUDGET if budget is None else budget
+    hmax = B.bh_ewald_set_local_budget(bh.ctx, table, eff)
+    assert abs(hmax - local_hmax(eff, g.box_size, AXIS_NODE)) <= 1e-12
     try:
         B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, table, theta, None, precision, 1.0, phi, counts)
         bh.check()
@@ -221,18 +228,20 @@ def test_periodic_walk_equals_oracle(name, precision, budget, theta):
     # the table's errors (D per unit mass, the Hessian per unit of the group's far-node sum_ab |Q_ab| / 6),
     # and in fp32 the rounding of O(1) terms (relative 1e-6 of sum m / d over the box, about 3 m.sum() / L)
     # that cancel to the small periodic potential, and the storage of the table rows; per group
-    # the groups summing D through the group-centre cubic: their bounds at the cubic's reach
+    # the groups summing D through a group-centre cubic (about the octant's centre or each bottom node's): their
+    # bounds at the cubic's reach
     hg = _group_h(g, gs)[ok]
-    loc = (precision == B.BH_FP32) & (hg <= hmax)
-    if budget is not None:
-        assert loc.any()
+    axis = np.array([local_axis(h, eff, g.box_size) if precision == B.BH_FP32 else 0.0 for h in hg])
+    loc = axis > 0
+    if budget == WIDE_BUDGET or (budget == NODE_BUDGET and name == "maclaurin_l1"):
+        assert loc.all() and (budget == WIDE_BUDGET or np.all(axis == AXIS_NODE))
     exported = B.bh_ewald_export(bh.ctx, table, N_TABLE)
     storage = storage_terms(exported, g.box_size, STORE_EPS[precision])
     tol_g = np.empty(int(ok.sum()))
     for k in range(len(tol_g)):
-        st = storage_terms(exported, g.box_size, STORE_EPS[precision], hg[k]) if loc[k] else storage
+        st = storage_terms(exported, g.box_size, STORE_EPS[precision], axis[k] * hg[k]) if loc[k] else storage
         tol_g[k] = walk_tolerance(m.sum(), qs[ok][k], g.box_size, st, precision == B.BH_FP32,
-                                  local_reach(hg[k], g.box_size) if loc[k] else DELTA)
+                                  local_reach(hg[k], g.box_size, axis[k]) if loc[k] else DELTA)
     ratio = np.max(np.abs(p[ok] - ref[ok]), axis=1) / tol_g
     # the same bound with the lookup's errors measured instead of bounded (see measured_lookup_errors), for the
     # groups that look every pair up
@@ -250,7 +259,8 @@ def test_periodic_walk_equals_oracle(name, precision, budget, theta):
     assert np.all(ratio <= 1.0), (ratio, tol_g)
     assert np.all(ratio_m <= 1.0), (ratio_m, tol_m)
     # regression guard: 4x the largest difference this library gave on these groups (not a derived bound)
-    key = (name, precision, theta) if budget is None else (name, precision, theta, "wide")
+    key = (name, precision, theta) if budget is None else (name, precision, theta,
+                                                           "wide" if budget == WIDE_BUDGET else "node")
     assert np.max(np.abs(p[ok] - ref[ok])) <= 4.0 * REGRESSION_MAX_DIFF[key]
 
 
