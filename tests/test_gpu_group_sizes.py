@@ -11,6 +11,11 @@ group_cells cells; the paper's own group is a 32-cell warp), through the C ABI.
   sum (fp64 1e-12, fp32 1e-5) with the oracle's counts;
 * per-group theta arrays, the paper's cube test with the monopole far field,
   accelerations and the no-allocation entry point at 32 and 128 cells;
+* the periodic walk at 32, 128 and 512 cells (fp32: on the random grid the
+  finest level sums the Ewald term's smooth part through the octant's cubic,
+  the next through bottom-node cubics, the coarser pair by pair; 32-cell
+  groups always pair by pair) against the oracle's O10 with the same
+  partition, within each group's derived bound;
 * bad group sizes, and calls that need 64-cell groups, are refused.
 """
 import numpy as np
@@ -26,6 +31,8 @@ if not torch.cuda.is_available():
 
 from oracle import OracleTree
 from oracle.oracle import fp32_band_for  # noqa: E402
+from periodic_bounds import (DELTA, EPS_FP32_ROWS, EPS_FP64_ROWS, N_TABLE, local_axis, local_reach,  # noqa: E402
+                             storage_terms, walk_tolerance)
 from paper_1509_07370_amd import binding as B  # noqa: E402
 from paper_1509_07370_amd.solver import BarnesHut  # noqa: E402
 
@@ -196,6 +203,54 @@ def test_accelerations(G):
     scale = np.maximum(np.linalg.norm(ref, axis=2), 0.1 * np.sqrt(np.mean(np.sum(ref ** 2, axis=2))))
     err = np.linalg.norm(got - ref, axis=2) / scale
     assert np.max(err[clean]) <= 1e-12
+
+
+_periodic_oracle = {}
+
+
+@pytest.mark.parametrize("G", [32, 128, 512])
+@pytest.mark.parametrize("precision", [B.BH_FP64, B.BH_FP32])
+def test_periodic(G, precision):
+    g, bh, rho, t, keys = setup("random_amr", G)
+    ng = bh.info["n_groups"]
+    table = B.bh_ewald_create(bh.ctx, g.box_size, N_TABLE)
+    phi = torch.full_like(rho, float("nan"))
+    counts = torch.full((ng, 2), -1, dtype=torch.int32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, table, 0.7, None, precision, 1.0, phi, counts)
+    bh.check()
+    per = 512 // G
+    lv = np.asarray(g.level)[np.asarray(g.leaf_blocks)]
+    hg_all = g.box_size / (g.nbase * 8 * 2.0 ** lv[np.arange(ng) // per])
+    fp32 = precision == B.BH_FP32
+    axis_all = np.array([local_axis(h, B.EWALD_LOCAL_BUDGET, g.box_size) if fp32 and G >= 64 else 0.0
+                         for h in hg_all])
+    if G not in _periodic_oracle:  # a few random groups and one of each cell size, shared by both precisions
+        rng = np.random.default_rng(G)
+        sizes = [rng.choice(np.flatnonzero(hg_all == h)) for h in np.unique(hg_all)]
+        gs = np.unique(np.concatenate([rng.choice(ng, 5, replace=False), sizes]))
+        _periodic_oracle[G] = (gs,) + tuple(t.solve_groups_periodic(gs, group_cells=G, theta=0.7,
+                                                                     tau=TAU[B.BH_FP32], with_qsum=True))
+    gs, ref, oc, qs = _periodic_oracle[G]
+    clean = oc[:, 3] == 0
+    c = counts.cpu().numpy()[gs]
+    assert clean.sum() >= 3
+    assert np.array_equal(c[clean, 0], oc[clean, 1]) and np.array_equal(c[clean, 1], oc[clean, 2])
+    got = phi.cpu().numpy().reshape(-1)[group_cells_canonical(G, None, gs).ravel()].reshape(len(gs), G)
+    _, _, _, m = t.cells()
+    exported = B.bh_ewald_export(bh.ctx, table, N_TABLE)
+    eps = EPS_FP32_ROWS if fp32 else EPS_FP64_ROWS
+    ax, hg = axis_all[gs], hg_all[gs]
+    tol = np.array([walk_tolerance(m.sum(), qs[k], g.box_size, storage_terms(exported, g.box_size, eps, ax[k] * hg[k]),
+                                   fp32, local_reach(hg[k], g.box_size, ax[k]) if ax[k] > 0 else DELTA)
+                    for k in range(len(gs))])
+    ratio = np.max(np.abs(got - ref), axis=1) / tol
+    print("[periodic G=%d precision %d] %d groups, cubic placements %s, largest diff/tolerance %.2e"
+          % (G, precision, clean.sum(), np.unique(ax[clean]).tolist(), ratio[clean].max()))
+    assert np.all(ratio[clean] <= 1.0), ratio
+    if fp32 and G >= 64:
+        assert len(np.unique(axis_all)) == 3  # octant, bottom node and pair by pair all occur on this grid
+    B.bh_ewald_destroy(table)
 
 
 @pytest.mark.parametrize("G", [32, 256])
