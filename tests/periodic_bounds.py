@@ -73,7 +73,7 @@ def walk_tolerance(masses_sum, qsum, L, storage, fp32, delta=DELTA):
     expansion's reach delta), storage, and in fp32 the rounding of O(1) terms (relative 1e-6 of sum m / d over the
     box, about 3 sum m / L) that cancel to the small periodic potential."""
     ds, hs = storage
-    tol = D4 * delta ** 4 / 24 * masses_sum / L + D4 * delta ** 2 / 2 * qsum + ds * masses_sum + hs * qsum
+    tol = D4 * delta ** 4 / 24 * masses_sum / L + D4 * delta ** 2 / 2 * qsum / L ** 3 + ds * masses_sum + hs * qsum
     if fp32:
         tol = tol + 3e-6 * 3 * masses_sum / L
     return tol

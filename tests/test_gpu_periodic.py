@@ -264,6 +264,56 @@ def test_periodic_walk_equals_oracle(name, precision, budget, theta):
     assert np.max(np.abs(p[ok] - ref[ok])) <= 4.0 * REGRESSION_MAX_DIFF[key]
 
 
+@pytest.mark.parametrize("precision,budget", [(B.BH_FP64, None), (B.BH_FP32, None), (B.BH_FP32, WIDE_BUDGET)])
+def test_periodic_walk_in_a_box_of_side_2_5(precision, budget):
+    """The random grid scaled to a box of side 2.5 (the same densities, so every mass grows by 2.5^3): the table,
+    the walk and the group-centre cubics in units of L, against the oracle's O10 within each group's bound."""
+    import dataclasses
+    s = 2.5
+    g0 = GRIDS["random_amr"]()
+    g = dataclasses.replace(g0, box_size=s * g0.box_size, box_lo=s * np.asarray(g0.box_lo),
+                            lo=s * np.asarray(g0.lo), name="random_amr_2.5")
+    bh = BarnesHut(g)
+    rho = torch.tensor(g.rho, device="cuda")
+    ng = bh.info["n_groups"]
+    table = B.bh_ewald_create(bh.ctx, g.box_size, N_TABLE)
+    eff = B.EWALD_LOCAL_BUDGET if budget is None else budget
+    hmax = B.bh_ewald_set_local_budget(bh.ctx, table, eff)
+    assert abs(hmax - local_hmax(eff, g.box_size, AXIS_NODE)) <= 1e-12 * g.box_size
+    phi = torch.full_like(rho, float("nan"))
+    counts = torch.full((ng, 2), -1, dtype=torch.int32, device="cuda")
+    bh.build_moments(rho)
+    B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, table, 0.6, None, precision, 1.0, phi, counts)
+    bh.check()
+    t = OracleTree(g)
+    t.moments()
+    gs = np.unique(np.r_[0, ng - 1, np.random.default_rng(25).choice(ng, 10, replace=False)])
+    ref, oc, qs = t.solve_groups_periodic(gs, theta=0.6, tau=fp32_band_for(g.box_size), with_qsum=True)
+    ok = oc[:, 3] == 0
+    assert ok.sum() >= 3
+    c = counts.cpu().numpy()[gs]
+    assert np.array_equal(c[ok, 0], oc[ok, 1]) and np.array_equal(c[ok, 1], oc[ok, 2])
+    p = phi.cpu().numpy().reshape(-1)[np.concatenate([_group_cells(q) for q in gs])].reshape(len(gs), 64)
+    _, _, _, m = t.cells()
+    hg = _group_h(g, gs)[ok]
+    axis = np.array([local_axis(h, eff, g.box_size) if precision == B.BH_FP32 else 0.0 for h in hg])
+    if budget == WIDE_BUDGET:
+        assert np.all(axis > 0)
+    exported = B.bh_ewald_export(bh.ctx, table, N_TABLE)
+    tol = np.array([walk_tolerance(m.sum(), qs[ok][k], g.box_size,
+                                   storage_terms(exported, g.box_size, STORE_EPS[precision], axis[k] * hg[k]),
+                                   precision == B.BH_FP32,
+                                   local_reach(hg[k], g.box_size, axis[k]) if axis[k] > 0 else DELTA)
+                    for k in range(len(hg))])
+    ratio = np.max(np.abs(p[ok] - ref[ok]), axis=1) / tol
+    print("[periodic L=2.5] precision %d budget %s: %d groups (%d through a cubic), max diff %.2e, largest "
+          "diff/tolerance %.2e" % (precision, budget, ok.sum(), (axis > 0).sum(), np.max(np.abs(p[ok] - ref[ok])),
+                                   ratio.max()))
+    assert np.all(ratio <= 1.0), ratio
+    B.bh_ewald_destroy(table)
+    bh.close()
+
+
 def test_tiny_theta_equals_the_periodic_direct_sum():
     g, bh, rho, table, t = setup("random_amr")
     phi = torch.empty_like(rho)
@@ -277,6 +327,11 @@ def test_tiny_theta_equals_the_periodic_direct_sum():
 def test_bad_arguments_are_refused():
     g, bh, rho, table, t = setup("random_amr")
     phi = torch.empty_like(rho)
+    for bad in (-1e-5, float("nan"), float("inf")):
+        with pytest.raises(B.BHError):
+            B.bh_ewald_set_local_budget(bh.ctx, table, bad)
+    assert B.bh_ewald_set_local_budget(bh.ctx, table, 0.0) == 0.0
+    B.bh_ewald_set_local_budget(bh.ctx, table, B.EWALD_LOCAL_BUDGET)
     other = B.bh_ewald_create(bh.ctx, 2.0 * g.box_size, 9)
     with pytest.raises(B.BHError):
         B.bh_walk_potential_periodic(bh.ctx, bh.grid, bh.m, other, 0.5, None, B.BH_FP32, 1.0, phi, None)
