@@ -340,7 +340,7 @@ int bh_ewald_export(bh_ctx *ctx, const bh_ewald *table, double *values);
  * every pair; *max_err (host): the largest |series - D L| found at the fit
  * points and a second set of check points.  Errors: BH_EINVAL (NULL). */
 int bh_ewald_near_series(bh_ctx *ctx, const bh_ewald *table, double *coeffs, double *radius, double *max_err);
-/* Error budget of the group-centre cubic in the fp32 periodic walks.  D is
+/* Error budget of the group-centre cubic in the periodic walks.  D is
  * smooth, so over the cells x = c + u near a centre c the sum over a group's
  * sources of m_s D(x - X_s) (and, for far nodes, the quadrupole's Hessian
  * term) is one cubic in u: each source's third-order expansion about its table
@@ -367,8 +367,8 @@ int bh_ewald_set_local_budget(bh_ctx *ctx, bh_ewald *table, double budget, doubl
  * as built by the last bh_build_moments. */
 int bh_moments_export_trace(bh_ctx *ctx, const bh_moments *m, double *S);
 /* The periodic walk and sum (above) in one launch; arguments as
- * bh_walk_potential.  In fp32, groups of cells no larger than the table's
- * budget admits sum D through the group-centre cubic
+ * bh_walk_potential.  Groups of cells no larger than the table's budget
+ * admits sum D through the group-centre cubic
  * (bh_ewald_set_local_budget).  The grid's box must be the table's (to 1e-12).  The
  * fused walks' dispatch order and cost records apply as for
  * bh_walk_potential.  Errors: BH_EINVAL (theta, precision, G, box size),

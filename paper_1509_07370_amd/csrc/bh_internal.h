@@ -96,7 +96,7 @@ struct WalkArgs {
     double ewald_sp;
     int ewald_n;
     const float *ewald_near;  // near-origin series of D (fp32 periodic walks), or null
-    double ewald_local_hmax;  // fp32 periodic walks: groups of cells no larger sum D through cubics about the
+    double ewald_local_hmax;  // periodic walks: groups of cells no larger sum D through cubics about the
                               // centres of their bottom nodes (0: never)
     double ewald_local_hoct;  // ... and no larger than this, through one cubic about the octant's centre
     const double *node_s;
@@ -165,7 +165,7 @@ struct bh_ewald {
     float *d_near = nullptr;   // the coefficients in fp32, then near_radius^2
     double *d_t64c = nullptr;  // [n^3][12] compact rows of the fp64 walks and direct sum
     float *d_t32 = nullptr;    // [n^3][12] compact rows of the fp32 walks
-    // worst-case error per unit mass (in units of 1/L) that the fp32 walks may add by summing D over a group
+    // worst-case error per unit mass (in units of 1/L) that the walks may add by summing D over a group
     // through one cubic about the group centre (0: every pair through its own table point)
     double local_budget = bh::kEwaldLocalBudget;
 };

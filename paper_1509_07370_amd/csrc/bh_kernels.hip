@@ -1329,6 +1329,41 @@ __device__ __forceinline__ float group8_total_f32(float v) {
     return v;
 }
 
+// The same totals for fp64 values (each half moved by the same DPP pattern).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_src_f64(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double group8_total_f64(double v) {
+    v += dpp_src_f64<0xB1, 0xF>(v);
+    v += dpp_src_f64<0x4E, 0xF>(v);
+    v += dpp_src_f64<0x141, 0xF>(v);
+    return v;
+}
+__device__ __forceinline__ double wave_total_f64(double v) {
+    v = group8_total_f64(v);
+    v += dpp_src_f64<0x140, 0xF>(v);
+    v += dpp_src_f64<0x142, 0xA>(v);
+    v += dpp_src_f64<0x143, 0xC>(v);
+    return v;
+}
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+// The total of a lane-group of 8 (node8) or of the wavefront, in every lane that needs it, as a double.
+__device__ __forceinline__ double cubic_total(float v, bool node8) {
+    return node8 ? (double)group8_total_f32(v)
+                 : (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_total_f32(v)), 63));
+}
+__device__ __forceinline__ double cubic_total(double v, bool node8) {
+    return node8 ? group8_total_f64(v) : readlane_f64(wave_total_f64(v), 63);
+}
+
 __device__ __forceinline__ double local_cubic(const double (&c)[kLocalCoefs], double x, double y, double z) {
     const double xx = x * x, yy = y * y, zz = z * z;
     const double lin = c[0] + (c[1] * x + c[2] * y + c[3] * z);
@@ -1340,8 +1375,8 @@ __device__ __forceinline__ double local_cubic(const double (&c)[kLocalCoefs], do
     return lin + quad + cube;
 }
 
-// LOCAL: the group-centre cubic of the smooth part is compiled in (fp32, one
-// group per wavefront).
+// LOCAL: the group-centre cubic of the smooth part is compiled in (one group
+// per wavefront).
 template <typename real, bool LOCAL = false>
 struct TilesPeriodic {
     using V4 = typename Prec<real>::V4;
@@ -1358,15 +1393,15 @@ struct TilesPeriodic {
     const float *near_c;  // series of D L near the origin (fp32 walks), then the radius^2; null: table only
     real cg[3], box, box_inv, bg;
     real dscale, qscale;  // table value -> D, and the Q:H sum -> Q:H / 6 (fp32 rows are scaled by powers of L)
-    // group-centre cubic of the smooth part (fp32 walks of small enough cells): the coefficients of
+    // group-centre cubic of the smooth part (groups of small enough cells): the coefficients of
     // sum_s [m_s D + Q_s : H / 6 + bg S_s](c + u) in u / L (order of kLocalCoefs), c the octant's centre, summed
     // by each lane over the sources it took, in its own slice of LDS, then over the wavefront once per group.
     // node8: one cubic per bottom node instead (lanes 8b..8b+7 hold the 8 cells of bottom node b of the
     // octant), each about the node's centre and summed over its 8 lanes, each lane taking every 8th source
     bool local, node8;
-    float lh;        // node8: h, the offset of a bottom node's centre from the octant's per axis; else 0
+    real lh;         // node8: h, the offset of a bottom node's centre from the octant's per axis; else 0
     real local_lim;  // a source at |R_a| <= local_lim on every axis has one nearest image for every cell
-    float4 *lsum;    // [kLocalCoefs / 4][64] float4 of this wavefront
+    V4 *lsum;        // [kLocalCoefs / 4][64] of this wavefront, in the walk's precision
 
     __device__ void setup(const WalkArgs &a, const LeafInfo &L, int sub) {
 #pragma clang fp contract(off)
@@ -1392,12 +1427,11 @@ struct TilesPeriodic {
         near_c = sizeof(real) == 4 ? a.ewald_near : nullptr;
         local = false;
         if constexpr (LOCAL) {
-            static_assert(sizeof(real) == 4, "the group-centre cubic is an fp32 path");
             local = L.h <= a.ewald_local_hmax;
             node8 = local && L.h > a.ewald_local_hoct;
-            lh = node8 ? (float)h : 0.0f;
+            lh = node8 ? h : (real)0;
             local_lim = (real)(0.5 * a.box - 1.5 * L.h - 1e-5 * a.box);
-            __shared__ float4 lds_sums[4][kLocalCoefs / 4][64];
+            __shared__ V4 lds_sums[4][kLocalCoefs / 4][64];
             lsum = &lds_sums[threadIdx.x >> 6][0][0];
         }
     }
@@ -1406,12 +1440,12 @@ struct TilesPeriodic {
         if (LOCAL && local) {
             const int lane = __lane_id();
 #pragma unroll
-            for (int k = 0; k < kLocalCoefs / 4; k++) lsum[64 * k + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int k = 0; k < kLocalCoefs / 4; k++) lsum[64 * k + lane] = V4{0, 0, 0, 0};
         }
     }
     __device__ real image(real x, real c) const { return x - box * rint((x - c) * box_inv); }
     // the centre of this lane's cubic on axis d (cells in Morton order: lane bits 3, 4, 5 place the bottom node)
-    __device__ float lcentre(int d) const { return (float)cg[d] + (((__lane_id() >> (3 + d)) & 1) ? lh : -lh); }
+    __device__ real lcentre(int d) const { return cg[d] + (((__lane_id() >> (3 + d)) & 1) ? lh : -lh); }
 
     __device__ void load(int64_t id, V4 &a, V4 &b, V4 &c) const {
         a = rec[3 * id + 0];
@@ -1442,34 +1476,34 @@ struct TilesPeriodic {
     // w = (Qxz, Qyz, S, -)) adds its quadrupole's Hessian term, whose Hessian
     // is first order in the offset as in far_eval, and bg S.  Odd powers of a
     // coordinate take the sign of R's coordinate (the table is folded).
-    __device__ void local_source(float Rx, float Ry, float Rz, float m, const float4 *q, const float4 *w,
-                                 float (&c)[kLocalCoefs]) const {
-        const EwaldPoint<float> p = ewald_point(ew, Rx, Ry, Rz);
-        float v[kEwaldValues];
+    __device__ void local_source(real Rx, real Ry, real Rz, real m, const V4 *q, const V4 *w,
+                                 real (&c)[kLocalCoefs]) const {
+        const EwaldPoint<real> p = ewald_point(ew, Rx, Ry, Rz);
+        real v[kEwaldValues];
         ewald_fetch(ew, p.row, v);
-        const float x = p.dx, y = p.dy, z = p.dz;
-        const float kxx = v[10] * x + v[13] * y + v[14] * z;
-        const float kyy = v[15] * x + v[11] * y + v[16] * z;
-        const float kzz = v[17] * x + v[18] * y + v[12] * z;
-        const float kxy = v[13] * x + v[15] * y + v[19] * z;
-        const float kxz = v[14] * x + v[19] * y + v[17] * z;
-        const float kyz = v[19] * x + v[16] * y + v[18] * z;
-        const float t3 = 1.0f / 3.0f;
+        const real x = p.dx, y = p.dy, z = p.dz;
+        const real kxx = v[10] * x + v[13] * y + v[14] * z;
+        const real kyy = v[15] * x + v[11] * y + v[16] * z;
+        const real kzz = v[17] * x + v[18] * y + v[12] * z;
+        const real kxy = v[13] * x + v[15] * y + v[19] * z;
+        const real kxz = v[14] * x + v[19] * y + v[17] * z;
+        const real kyz = v[19] * x + v[16] * y + v[18] * z;
+        const real t3 = (real)1 / (real)3;
         // value D0 + d.(g + (H + K/3) d / 2), gradient g + (H + K/2) d, Hessian H + K (K = T d)
-        const float wx = (v[4] + kxx * t3) * x + (v[7] + kxy * t3) * y + (v[8] + kxz * t3) * z;
-        const float wy = (v[7] + kxy * t3) * x + (v[5] + kyy * t3) * y + (v[9] + kyz * t3) * z;
-        const float wz = (v[8] + kxz * t3) * x + (v[9] + kyz * t3) * y + (v[6] + kzz * t3) * z;
-        const float val = v[0] + x * (v[1] + 0.5f * wx) + y * (v[2] + 0.5f * wy) + z * (v[3] + 0.5f * wz);
-        const float gx = v[1] + (v[4] + 0.5f * kxx) * x + (v[7] + 0.5f * kxy) * y + (v[8] + 0.5f * kxz) * z;
-        const float gy = v[2] + (v[7] + 0.5f * kxy) * x + (v[5] + 0.5f * kyy) * y + (v[9] + 0.5f * kyz) * z;
-        const float gz = v[3] + (v[8] + 0.5f * kxz) * x + (v[9] + 0.5f * kyz) * y + (v[6] + 0.5f * kzz) * z;
-        const float sx = p.sx, sy = p.sy, sz = p.sz;
-        const float hxx = v[4] + kxx, hyy = v[5] + kyy, hzz = v[6] + kzz;
-        const float hxy = (v[7] + kxy) * (sx * sy), hxz = (v[8] + kxz) * (sx * sz), hyz = (v[9] + kyz) * (sy * sz);
-        const float txxx = sx * v[10], tyyy = sy * v[11], tzzz = sz * v[12], txxy = sy * v[13], txxz = sz * v[14];
-        const float txyy = sx * v[15], tyyz = sz * v[16], txzz = sx * v[17], tyzz = sy * v[18];
-        const float txyz = (sx * sy * sz) * v[19];
-        const float md = m * (float)dscale;
+        const real wx = (v[4] + kxx * t3) * x + (v[7] + kxy * t3) * y + (v[8] + kxz * t3) * z;
+        const real wy = (v[7] + kxy * t3) * x + (v[5] + kyy * t3) * y + (v[9] + kyz * t3) * z;
+        const real wz = (v[8] + kxz * t3) * x + (v[9] + kyz * t3) * y + (v[6] + kzz * t3) * z;
+        const real val = v[0] + x * (v[1] + (real)0.5 * wx) + y * (v[2] + (real)0.5 * wy) + z * (v[3] + (real)0.5 * wz);
+        const real gx = v[1] + (v[4] + (real)0.5 * kxx) * x + (v[7] + (real)0.5 * kxy) * y + (v[8] + (real)0.5 * kxz) * z;
+        const real gy = v[2] + (v[7] + (real)0.5 * kxy) * x + (v[5] + (real)0.5 * kyy) * y + (v[9] + (real)0.5 * kyz) * z;
+        const real gz = v[3] + (v[8] + (real)0.5 * kxz) * x + (v[9] + (real)0.5 * kyz) * y + (v[6] + (real)0.5 * kzz) * z;
+        const real sx = p.sx, sy = p.sy, sz = p.sz;
+        const real hxx = v[4] + kxx, hyy = v[5] + kyy, hzz = v[6] + kzz;
+        const real hxy = (v[7] + kxy) * (sx * sy), hxz = (v[8] + kxz) * (sx * sz), hyz = (v[9] + kyz) * (sy * sz);
+        const real txxx = sx * v[10], tyyy = sy * v[11], tzzz = sz * v[12], txxy = sy * v[13], txxz = sz * v[14];
+        const real txyy = sx * v[15], tyyz = sz * v[16], txzz = sx * v[17], tyzz = sy * v[18];
+        const real txyz = (sx * sy * sz) * v[19];
+        const real md = m * dscale;
         c[0] += md * val;
         c[1] += md * (sx * gx);
         c[2] += md * (sy * gy);
@@ -1491,19 +1525,21 @@ struct TilesPeriodic {
         c[18] += md * tyzz;
         c[19] += md * txyz;
         if (q) {
-            const float4 Q = *q, W = *w;
-            const float qs = (float)qscale;
-            c[0] += qs * ((Q.x * hxx + Q.y * hyy + Q.z * hzz) + (Q.w * hxy + W.x * hxz + W.y * hyz)) + (float)bg * W.z;
-            c[1] += qs * ((Q.x * txxx + Q.y * txyy + Q.z * txzz) + (Q.w * txxy + W.x * txxz + W.y * txyz));
-            c[2] += qs * ((Q.x * txxy + Q.y * tyyy + Q.z * tyzz) + (Q.w * txyy + W.x * txyz + W.y * tyyz));
-            c[3] += qs * ((Q.x * txxz + Q.y * tyyz + Q.z * tzzz) + (Q.w * txyz + W.x * txzz + W.y * tyzz));
+            const V4 Q = *q, W = *w;
+            // fp32 records hold Q/2 on the diagonal (qscale 1/(3 L^3)), fp64 records Q (qscale 1/(6 L^3))
+            const real o = sizeof(real) == 4 ? (real)1 : (real)2;
+            const real qs = qscale;
+            c[0] += qs * ((Q.x * hxx + Q.y * hyy + Q.z * hzz) + o * (Q.w * hxy + W.x * hxz + W.y * hyz)) + bg * W.z;
+            c[1] += qs * ((Q.x * txxx + Q.y * txyy + Q.z * txzz) + o * (Q.w * txxy + W.x * txxz + W.y * txyz));
+            c[2] += qs * ((Q.x * txxy + Q.y * tyyy + Q.z * tyzz) + o * (Q.w * txyy + W.x * txyz + W.y * tyyz));
+            c[3] += qs * ((Q.x * txxz + Q.y * tyyz + Q.z * tzzz) + o * (Q.w * txyz + W.x * txzz + W.y * tyzz));
         }
     }
     // a lane's coefficients added to its running sums (its own LDS slice: no other lane reads it before finish)
-    __device__ void local_add(const float (&c)[kLocalCoefs], int lane) {
+    __device__ void local_add(const real (&c)[kLocalCoefs], int lane) {
 #pragma unroll
         for (int k = 0; k < kLocalCoefs / 4; k++) {
-            float4 t = lsum[64 * k + lane];
+            V4 t = lsum[64 * k + lane];
             t.x += c[4 * k];
             t.y += c[4 * k + 1];
             t.z += c[4 * k + 2];
@@ -1513,32 +1549,37 @@ struct TilesPeriodic {
     }
     // whether every staged source (lanes < n, the position in s) is at the same nearest image from all the
     // octant's cells
-    __device__ bool local_ok(bool mine, float sx, float sy, float sz) const {
-        const bool bad = mine && (fabsf((float)cg[0] - sx) > (float)local_lim || fabsf((float)cg[1] - sy) > (float)local_lim ||
-                                  fabsf((float)cg[2] - sz) > (float)local_lim);
+    __device__ bool local_ok(bool mine, real sx, real sy, real sz) const {
+        const bool bad = mine && (fabs(cg[0] - sx) > local_lim || fabs(cg[1] - sy) > local_lim ||
+                                  fabs(cg[2] - sz) > local_lim);
         return __ballot(bad) == 0;
     }
     // a far tile of a local group: 1/|R| and the quadrupole pair by pair (the positions staged at the image
     // nearest the octant centre), the smooth part through the cubic
     __device__ void far_local(int n, int lane) {
-        const float4 *t = reinterpret_cast<const float4 *>(T);
-        const float4 m = reinterpret_cast<const float4 &>(me);
-        float part = 0.0f;
+        const V4 *t = T;
+        const V4 m = me;
+        real part = 0;
         for (int j = 0; j < n; j++) {
-            const float4 p = t[3 * j], q = t[3 * j + 1], w = t[3 * j + 2];
-            const float dx = m.x - p.x, dy = m.y - p.y, dz = m.z - p.z;
-            const float ri = rsq_any(dx * dx + dy * dy + dz * dz);
-            const float ri2 = ri * ri;
-            const float quad = (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) + (q.w * dx * dy + w.x * dx * dz + w.y * dy * dz);
+            const V4 p = t[3 * j], q = t[3 * j + 1], w = t[3 * j + 2];
+            const real dx = m.x - p.x, dy = m.y - p.y, dz = m.z - p.z;
+            const real ri = rsq_any(dx * dx + dy * dy + dz * dz);
+            const real ri2 = ri * ri;
+            real quad;
+            if constexpr (sizeof(real) == 4)  // Q/2 on the diagonal
+                quad = (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) + (q.w * dx * dy + w.x * dx * dz + w.y * dy * dz);
+            else
+                quad = (real)0.5 * (q.x * dx * dx + q.y * dy * dy + q.z * dz * dz) +
+                       (q.w * dx * dy + w.x * dx * dz + w.y * dy * dz);
             part += p.w * ri + quad * (ri2 * ri2 * ri);
         }
         acc_far += (double)part;
-        const float c0 = lcentre(0), c1 = lcentre(1), c2 = lcentre(2);
+        const real c0 = lcentre(0), c1 = lcentre(1), c2 = lcentre(2);
         // the lane's sources: its own node, or (node8) every 8th node from its slot in the bottom node
         const int step = node8 ? 8 : 64;
-        float c[kLocalCoefs] = {};
+        real c[kLocalCoefs] = {};
         for (int j = node8 ? (lane & 7) : lane; j < n; j += step) {
-            const float4 p = t[3 * j], q = t[3 * j + 1], w = t[3 * j + 2];
+            const V4 p = t[3 * j], q = t[3 * j + 1], w = t[3 * j + 2];
             local_source(c0 - p.x, c1 - p.y, c2 - p.z, p.w, &q, &w, c);
         }
         local_add(c, lane);
@@ -1681,29 +1722,29 @@ struct TilesPeriodic {
         if constexpr (LOCAL) {
             if (local && local_ok(lane < 8 * n, s.x, s.y, s.z)) {
                 // the tile's nodes lie within L/2 - 1.5h of the octant centre, so the 8 cells of a node keep
-                // their lattice after the imaging above; tiles holding the wavefront's own cells skip the self
-                // pair pair by pair
+                // their lattice after the imaging above; in fp32 tiles without the wavefront's own cells are
+                // summed on it, the others pair by pair, skipping the self pair
                 const bool own = lane < 8 * n && cid >= own_lo && cid < own_lo + 64;
                 real part = 0;
-                if (__ballot(own) == 0) {
-                    near_lattice_pack(T, n);
-                    part = near_lattice_sum(T + 64, n, me.x, me.y, me.z);
+                if (sizeof(real) == 4 && __ballot(own) == 0) {
+                    if constexpr (sizeof(real) == 4) {
+                        near_lattice_pack(T, n);
+                        part = near_lattice_sum(T + 64, n, me.x, me.y, me.z);
+                    }
                 } else {
-                    const float4 *t = reinterpret_cast<const float4 *>(T);
                     for (int j = 0; j < 8 * n; j++) {
-                        const float4 q = t[j];
-                        const float dx = me.x - q.x, dy = me.y - q.y, dz = me.z - q.z;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        part = fmaf(q.w, r2 > 0.0f ? rsq_any(r2) : 0.0f, part);
+                        const V4 q = T[j];
+                        const real dx = me.x - q.x, dy = me.y - q.y, dz = me.z - q.z;
+                        const real r2 = dx * dx + dy * dy + dz * dz;
+                        part += q.w * (r2 > (real)0 ? rsq_any(r2) : (real)0);
                     }
                 }
                 acc_near += (double)part;
-                const float c0 = lcentre(0), c1 = lcentre(1), c2 = lcentre(2);
-                const float4 *t = reinterpret_cast<const float4 *>(T);
+                const real c0 = lcentre(0), c1 = lcentre(1), c2 = lcentre(2);
                 const int step = node8 ? 8 : 64;
-                float c[kLocalCoefs] = {};
+                real c[kLocalCoefs] = {};
                 for (int j = node8 ? (lane & 7) : lane; j < 8 * n; j += step) {
-                    const float4 q = t[j];
+                    const V4 q = T[j];
                     local_source(c0 - q.x, c1 - q.y, c2 - q.z, q.w, nullptr, nullptr, c);
                 }
                 local_add(c, lane);
@@ -1734,16 +1775,13 @@ struct TilesPeriodic {
                 double c[kLocalCoefs];
 #pragma unroll
                 for (int k = 0; k < kLocalCoefs / 4; k++) {
-                    const float4 t = lsum[64 * k + lane];
-                    const float v4[4] = {t.x, t.y, t.z, t.w};
+                    const V4 t = lsum[64 * k + lane];
+                    const real v4[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-                    for (int i = 0; i < 4; i++)
-                        c[4 * k + i] = node8 ? (double)group8_total_f32(v4[i])
-                                             : (double)__int_as_float(__builtin_amdgcn_readlane(
-                                                   __float_as_int(wave_total_f32(v4[i])), 63));
+                    for (int i = 0; i < 4; i++) c[4 * k + i] = cubic_total(v4[i], node8);
                 }
-                smooth = local_cubic(c, (double)((me.x - lcentre(0)) * (float)box_inv),
-                                     (double)((me.y - lcentre(1)) * (float)box_inv), (double)((me.z - lcentre(2)) * (float)box_inv));
+                smooth = local_cubic(c, (double)((me.x - lcentre(0)) * box_inv), (double)((me.y - lcentre(1)) * box_inv),
+                                     (double)((me.z - lcentre(2)) * box_inv));
             }
         }
         a.phi[cell] = -a.G * (acc_far + acc_near + smooth);
@@ -2155,7 +2193,7 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     a.box = g->topo.box;
     a.ewald = precision == BH_FP64 ? (const void *)e->d_t64c : (const void *)e->d_t32;
     a.ewald_near = precision == BH_FP32 && e->near_radius > 0.0 ? e->d_near : nullptr;
-    const bool cubic = precision == BH_FP32 && g->group_cells >= 64;
+    const bool cubic = g->group_cells >= 64;
     a.ewald_local_hmax = cubic ? ewald_local_hmax(e, kLocalSpreadNode) : 0.0;
     a.ewald_local_hoct = cubic ? ewald_local_hmax(e, kLocalSpreadOctant) : 0.0;
     a.ewald_sp = e->sp;
@@ -2167,6 +2205,9 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     if (precision == BH_FP64) {
         if (fused_gm(g) == 2)
             hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64, 2>), grid, block, 0, s, a);
+        else if (a.ewald_local_hmax > 0.0)
+            hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64, 1, true>), grid, block, 0, s,
+                               a);
         else
             hipLaunchKernelGGL((walk_potential_periodic_kernel<double, kPeriodicWaves64, 1>), grid, block, 0, s, a);
     } else {

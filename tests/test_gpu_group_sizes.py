@@ -11,7 +11,7 @@ group_cells cells; the paper's own group is a 32-cell warp), through the C ABI.
   sum (fp64 1e-12, fp32 1e-5) with the oracle's counts;
 * per-group theta arrays, the paper's cube test with the monopole far field,
   accelerations and the no-allocation entry point at 32 and 128 cells;
-* the periodic walk at 32, 128 and 512 cells (fp32: on the random grid the
+* the periodic walk at 32, 128 and 512 cells (on the random grid the
   finest level sums the Ewald term's smooth part through the octant's cubic,
   the next through bottom-node cubics, the coarser pair by pair; 32-cell
   groups always pair by pair) against the oracle's O10 with the same
@@ -223,8 +223,7 @@ def test_periodic(G, precision):
     lv = np.asarray(g.level)[np.asarray(g.leaf_blocks)]
     hg_all = g.box_size / (g.nbase * 8 * 2.0 ** lv[np.arange(ng) // per])
     fp32 = precision == B.BH_FP32
-    axis_all = np.array([local_axis(h, B.EWALD_LOCAL_BUDGET, g.box_size) if fp32 and G >= 64 else 0.0
-                         for h in hg_all])
+    axis_all = np.array([local_axis(h, B.EWALD_LOCAL_BUDGET, g.box_size) if G >= 64 else 0.0 for h in hg_all])
     if G not in _periodic_oracle:  # a few random groups and one of each cell size, shared by both precisions
         rng = np.random.default_rng(G)
         sizes = [rng.choice(np.flatnonzero(hg_all == h)) for h in np.unique(hg_all)]
@@ -248,7 +247,7 @@ def test_periodic(G, precision):
     print("[periodic G=%d precision %d] %d groups, cubic placements %s, largest diff/tolerance %.2e"
           % (G, precision, clean.sum(), np.unique(ax[clean]).tolist(), ratio[clean].max()))
     assert np.all(ratio[clean] <= 1.0), ratio
-    if fp32 and G >= 64:
+    if G >= 64:
         assert len(np.unique(axis_all)) == 3  # octant, bottom node and pair by pair all occur on this grid
     B.bh_ewald_destroy(table)
 

@@ -19,7 +19,7 @@ O9 and O10, through the C ABI.
   table rows (Hessian and third derivatives at half the walk's precision, see
   STORE_EPS).  Three tiers: the table errors bounded from |D^(4)|, the same
   bound with the lookup's errors measured at random points, and a regression
-  guard at 4x the largest difference the library gives today; the fp32 walks
+  guard at 4x the largest difference the library gives today; the walks
   again with a wide error budget for the group-centre cubic of D (every group
   of cells of side <= 0.071 sums D through one cubic about its octant's
   centre) and with a budget that sends the MacLaurin grid's groups through one
@@ -171,10 +171,12 @@ REGRESSION_MAX_DIFF = {
     ("random_amr", B.BH_FP32, 0.5): 7.98e-7, ("maclaurin_l1", B.BH_FP32, 0.5): 1.13e-7,
     ("random_amr", B.BH_FP64, 0.8): 1.59e-6, ("maclaurin_l1", B.BH_FP64, 0.8): 2.39e-7,
     ("random_amr", B.BH_FP32, 0.8): 1.53e-6, ("maclaurin_l1", B.BH_FP32, 0.8): 2.58e-7,
-    # fp32 with the wide budget: every group through the group-centre cubic (random_amr's cells of side 1/16 reach
+    # the wide budget: every group through the group-centre cubic (random_amr's cells of side 1/16 reach
     # |delta| = 0.18 L, hence its larger differences, about 1% of their bound)
     ("random_amr", B.BH_FP32, 0.5, "wide"): 7.24e-4, ("maclaurin_l1", B.BH_FP32, 0.5, "wide"): 4.28e-7,
     ("random_amr", B.BH_FP32, 0.8, "wide"): 7.67e-4, ("maclaurin_l1", B.BH_FP32, 0.8, "wide"): 1.38e-6,
+    ("random_amr", B.BH_FP64, 0.5, "wide"): 7.24e-4, ("maclaurin_l1", B.BH_FP64, 0.5, "wide"): 4.40e-7,
+    ("random_amr", B.BH_FP64, 0.8, "wide"): 7.67e-4, ("maclaurin_l1", B.BH_FP64, 0.8, "wide"): 1.37e-6,
     # fp32 with the bottom-node budget: maclaurin_l1 through one cubic per bottom node, random_amr pair by pair
     ("random_amr", B.BH_FP32, 0.5, "node"): 7.98e-7, ("maclaurin_l1", B.BH_FP32, 0.5, "node"): 1.13e-7,
     ("random_amr", B.BH_FP32, 0.8, "node"): 1.52e-6, ("maclaurin_l1", B.BH_FP32, 0.8, "node"): 2.67e-7,
@@ -202,7 +204,7 @@ def _oracle_groups(name, theta):
 
 @pytest.mark.parametrize("name", list(GRIDS))
 @pytest.mark.parametrize("precision,budget", [(B.BH_FP64, None), (B.BH_FP32, None), (B.BH_FP32, WIDE_BUDGET),
-                                              (B.BH_FP32, NODE_BUDGET)])
+                                              (B.BH_FP32, NODE_BUDGET), (B.BH_FP64, WIDE_BUDGET)])
 @pytest.mark.parametrize("theta", [0.5, 0.8])
 def test_periodic_walk_equals_oracle(name, precision, budget, theta):
     g, bh, rho, table, t = setup(name)
@@ -231,7 +233,7 @@ def test_periodic_walk_equals_oracle(name, precision, budget, theta):
     # the groups summing D through a group-centre cubic (about the octant's centre or each bottom node's): their
     # bounds at the cubic's reach
     hg = _group_h(g, gs)[ok]
-    axis = np.array([local_axis(h, eff, g.box_size) if precision == B.BH_FP32 else 0.0 for h in hg])
+    axis = np.array([local_axis(h, eff, g.box_size) for h in hg])
     loc = axis > 0
     if budget == WIDE_BUDGET or (budget == NODE_BUDGET and name == "maclaurin_l1"):
         assert loc.all() and (budget == WIDE_BUDGET or np.all(axis == AXIS_NODE))
@@ -264,7 +266,8 @@ def test_periodic_walk_equals_oracle(name, precision, budget, theta):
     assert np.max(np.abs(p[ok] - ref[ok])) <= 4.0 * REGRESSION_MAX_DIFF[key]
 
 
-@pytest.mark.parametrize("precision,budget", [(B.BH_FP64, None), (B.BH_FP32, None), (B.BH_FP32, WIDE_BUDGET)])
+@pytest.mark.parametrize("precision,budget", [(B.BH_FP64, None), (B.BH_FP32, None), (B.BH_FP32, WIDE_BUDGET),
+                                              (B.BH_FP64, WIDE_BUDGET)])
 def test_periodic_walk_in_a_box_of_side_2_5(precision, budget):
     """The random grid scaled to a box of side 2.5 (the same densities, so every mass grows by 2.5^3): the table,
     the walk and the group-centre cubics in units of L, against the oracle's O10 within each group's bound."""
@@ -296,7 +299,7 @@ def test_periodic_walk_in_a_box_of_side_2_5(precision, budget):
     p = phi.cpu().numpy().reshape(-1)[np.concatenate([_group_cells(q) for q in gs])].reshape(len(gs), 64)
     _, _, _, m = t.cells()
     hg = _group_h(g, gs)[ok]
-    axis = np.array([local_axis(h, eff, g.box_size) if precision == B.BH_FP32 else 0.0 for h in hg])
+    axis = np.array([local_axis(h, eff, g.box_size) for h in hg])
     if budget == WIDE_BUDGET:
         assert np.all(axis > 0)
     exported = B.bh_ewald_export(bh.ctx, table, N_TABLE)
