@@ -402,6 +402,16 @@ int bh_batch_info(const bh_batch *batch, int *n_grids, int64_t *n_groups);
  * conditions are reported by bh_batch_check. */
 int bh_batch_solve(bh_ctx *ctx, bh_batch *batch, const double *const *rho_dev, double *const *phi_dev, double theta,
                    const float *const *theta_group_dev, int precision, double G);
+/* bh_batch_solve for grids that all lie in the periodic box of `table`
+ * (bh_walk_potential_periodic's walk and sums, its group-centre cubics within
+ * the table's budget), in one persistent launch.  Every grid's box must be the
+ * table's (to 1e-12, BH_EINVAL otherwise).  The batch's own kernel variant and
+ * launch settings for isolated solves do not apply; graphs are for isolated
+ * solves only.  Results equal bh_walk_potential_periodic on each grid, bit for
+ * bit.  Errors as bh_batch_solve; BH_EDEVICE (table on another device). */
+int bh_batch_solve_periodic(bh_ctx *ctx, bh_batch *batch, const bh_ewald *table, const double *const *rho_dev,
+                            double *const *phi_dev, double theta, const float *const *theta_group_dev, int precision,
+                            double G);
 /* Record the same solve as a graph (nothing runs yet); bh_batch_replay launches
  * it on the context's stream.  The graph keeps the buffers and parameters given
  * here; the moments' flags are cleared by a kernel inside the graph, not by a

@@ -85,6 +85,7 @@ _SIGS = {
     "bh_batch_destroy": (ctypes.c_int, [P]),
     "bh_batch_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64)]),
     "bh_batch_solve": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64]),
+    "bh_batch_solve_periodic": (ctypes.c_int, [P, P, P, P, P, f64, P, ctypes.c_int, f64]),
     "bh_batch_capture": (ctypes.c_int, [P, P, P, P, f64, P, ctypes.c_int, f64]),
     "bh_batch_replay": (ctypes.c_int, [P, P]),
     "bh_batch_check": (ctypes.c_int, [P, P]),
@@ -506,6 +507,11 @@ def _batch_args(rho, phi, theta_group):
 def bh_batch_solve(ctx, batch, rho, phi, theta=0.5, theta_group=None, precision=BH_FP32, G=1.0):
     r, p, tg = _batch_args(rho, phi, theta_group)
     _check(_lib.bh_batch_solve(ctx, batch, r, p, float(theta), tg, int(precision), float(G)), ctx)
+
+
+def bh_batch_solve_periodic(ctx, batch, table, rho, phi, theta=0.5, theta_group=None, precision=BH_FP32, G=1.0):
+    r, p, tg = _batch_args(rho, phi, theta_group)
+    _check(_lib.bh_batch_solve_periodic(ctx, batch, table, r, p, float(theta), tg, int(precision), float(G)), ctx)
 
 
 def bh_batch_capture(ctx, batch, rho, phi, theta=0.5, theta_group=None, precision=BH_FP32, G=1.0):

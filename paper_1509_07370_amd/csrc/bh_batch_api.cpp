@@ -72,15 +72,17 @@ int upload_order(bh_ctx *ctx, bh_batch *b, const std::vector<int2> &order) {
     return BH_OK;
 }
 
-// moments of every grid, then the persistent fused launch, all on stream s
+// moments of every grid, then the persistent fused launch, all on stream s; with a table, the periodic walk
 int enqueue_solve(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const *phi, double theta,
-                  const float *const *theta_group, int precision, double G, hipStream_t s) {
+                  const float *const *theta_group, int precision, double G, hipStream_t s,
+                  const bh_ewald *table = nullptr) {
     const int n = (int)b->grids.size();
     for (int k = 0; k < n; k++) {
         const bh_grid *g = b->grids[k];
         const float *tg = theta_group ? theta_group[k] : nullptr;
         b->h_desc[k] = bh::fused_args(g, b->moments[k], theta, tg, precision, G, phi[k],
                                       b->d_counts + 2 * b->group_base[k], 1);
+        if (table) bh::periodic_args(b->h_desc[k], g, b->moments[k], table, precision);
         if (b->stack_limit > 0 && b->stack_limit < b->h_desc[k].k8_threshold)
             b->h_desc[k].k8_threshold = b->stack_limit;
     }
@@ -89,15 +91,22 @@ int enqueue_solve(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *co
     HIPX(ctx, bh::launch_batch_reset(b->d_desc, n, b->d_counter, s), "batch reset kernel");
     for (int k = 0; k < n; k++)
         HIPX(ctx, bh::launch_moments(b->grids[k], b->moments[k], rho[k], s, 1), "moments kernels");
-    const int waves = b->waves > 0 ? b->waves : bh::fused_waves_per_simd(precision);
+    const bool local = table && b->h_desc[0].ewald_local_hmax > 0.0;
+    const int waves = table ? bh::periodic_waves_per_simd(precision, local)
+                            : (b->waves > 0 ? b->waves : bh::fused_waves_per_simd(precision));
     int per_cu = b->workgroups_per_cu > 0 ? b->workgroups_per_cu : waves;
     int64_t wgs = (int64_t)b->cus * per_cu;
     const int64_t need = (b->total + 3) / 4;
     if (wgs > need) wgs = need;
     if (wgs < 1) wgs = 1;
-    HIPX(ctx, bh::launch_batch_walk_potential(b->d_desc, b->d_order, b->total, b->d_counter, precision, waves,
-                                              (int)wgs, s),
-         "batch walk + potential kernel");
+    if (table)
+        HIPX(ctx, bh::launch_batch_walk_potential_periodic(b->d_desc, b->d_order, b->total, b->d_counter, precision,
+                                                           local, (int)wgs, s),
+             "batch periodic walk + potential kernel");
+    else
+        HIPX(ctx, bh::launch_batch_walk_potential(b->d_desc, b->d_order, b->total, b->d_counter, precision, waves,
+                                                  (int)wgs, s),
+             "batch walk + potential kernel");
     return BH_OK;
 }
 
@@ -234,6 +243,21 @@ int bh_batch_solve(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *c
     if ((rc = check_args(ctx, b, rho, phi, theta, theta_group, precision, G))) return rc;
     b->precision = precision;
     return enqueue_solve(ctx, b, rho, phi, theta, theta_group, precision, G, ctx->stream);
+}
+
+int bh_batch_solve_periodic(bh_ctx *ctx, bh_batch *b, const bh_ewald *table, const double *const *rho,
+                            double *const *phi, double theta, const float *const *theta_group, int precision,
+                            double G) {
+    int rc = require_gpu(ctx);
+    if (rc) return rc;
+    if (!table) return fail(ctx, BH_EINVAL, "table handle is NULL");
+    if ((rc = check_args(ctx, b, rho, phi, theta, theta_group, precision, G))) return rc;
+    if (table->device != ctx->device) return fail(ctx, BH_EDEVICE, "the table lives on another device");
+    for (const bh_grid *g : b->grids)
+        if (std::fabs(g->topo.box - table->L) > 1e-12 * table->L)
+            return fail(ctx, BH_EINVAL, "every grid's box must be the table's");
+    b->precision = precision;
+    return enqueue_solve(ctx, b, rho, phi, theta, theta_group, precision, G, ctx->stream, table);
 }
 
 int bh_batch_capture(bh_ctx *ctx, bh_batch *b, const double *const *rho, double *const *phi, double theta,

@@ -248,6 +248,13 @@ hipError_t launch_batch_walk_potential(const WalkArgs *grids, const int2 *order,
                                        hipStream_t s);
 int fused_waves_per_simd(int precision);
 bool fused_variant_exists(int precision, int waves);
+// The periodic box's fields of a fused walk's arguments (table, near series, group-centre cubics, S).
+void periodic_args(WalkArgs &a, const bh_grid *g, const bh_moments *m, const bh_ewald *e, int precision);
+// Persistent periodic walk over a batch whose grids share one box; local: the cubic kernels.
+int periodic_waves_per_simd(int precision, bool local);
+hipError_t launch_batch_walk_potential_periodic(const WalkArgs *grids, const int2 *order, int64_t total,
+                                                unsigned long long *counter, int precision, bool local,
+                                                int workgroups, hipStream_t s);
 hipError_t launch_walk(const bh_grid *g, const bh_moments *m, bh_lists *L, double theta, const float *theta_group,
                        int precision, bool fill, hipStream_t s);
 hipError_t launch_scan(const bh_grid *g, const bh_moments *m, bh_lists *L, hipStream_t s);

@@ -2186,10 +2186,7 @@ __global__ __launch_bounds__(256, WAVES) void walk_potential_periodic_kernel(Wal
     fused_group<real, TilesPeriodic<real, LOCAL>, 2, GM>(a, u, w, lane, sm);
 }
 
-hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
-                                          const float *theta_group, int precision, double G, double *phi,
-                                          int32_t *counts, hipStream_t s) {
-    WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
+void periodic_args(WalkArgs &a, const bh_grid *g, const bh_moments *m, const bh_ewald *e, int precision) {
     a.box = g->topo.box;
     a.ewald = precision == BH_FP64 ? (const void *)e->d_t64c : (const void *)e->d_t32;
     a.ewald_near = precision == BH_FP32 && e->near_radius > 0.0 ? e->d_near : nullptr;
@@ -2199,6 +2196,13 @@ hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m,
     a.ewald_sp = e->sp;
     a.ewald_n = e->n;
     a.node_s = m->d_s;
+}
+
+hipError_t launch_walk_potential_periodic(const bh_grid *g, const bh_moments *m, const bh_ewald *e, double theta,
+                                          const float *theta_group, int precision, double G, double *phi,
+                                          int32_t *counts, hipStream_t s) {
+    WalkArgs a = fused_args(g, m, theta, theta_group, precision, G, phi, counts, m->walk_epoch);
+    periodic_args(a, g, m, e, precision);
     hipError_t e0 = attach_schedule(g, m, a, s);
     if (e0 != hipSuccess) return e0;
     const dim3 grid = fused_blocks(g), block(256);
@@ -2296,11 +2300,10 @@ hipError_t launch_walk_accel(const bh_grid *g, const bh_moments *m, double theta
 // empty, so uneven grids and groups balance themselves; with `order` sorted
 // by decreasing cost the longest groups start first.  Every wave exits once
 // the counter passes `total`.
-template <typename real, int WAVES>
-__global__ __launch_bounds__(256, WAVES) void batch_walk_potential_kernel(
-    const WalkArgs *__restrict__ grids, const int2 *__restrict__ order, int64_t total,
-    unsigned long long *__restrict__ counter) {
-    __shared__ FusedSmem<real, 1> sm;
+template <typename real, typename TL, int MAC>
+__device__ __forceinline__ void batch_queue(const WalkArgs *__restrict__ grids, const int2 *__restrict__ order,
+                                            int64_t total, unsigned long long *__restrict__ counter,
+                                            FusedSmem<real, 1> &sm) {
     const int w = wave_index();
     const int lane = threadIdx.x & 63;
     while (true) {
@@ -2313,8 +2316,26 @@ __global__ __launch_bounds__(256, WAVES) void batch_walk_potential_kernel(
         q = ((unsigned long long)qhi << 32) | qlo;
         if (q >= (unsigned long long)total) break;
         const int2 item = order[q];
-        fused_group<real, Tiles<real>, 0, 1>(grids[item.x], item.y, w, lane, sm);
+        fused_group<real, TL, MAC, 1>(grids[item.x], item.y, w, lane, sm);
     }
+}
+
+template <typename real, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void batch_walk_potential_kernel(
+    const WalkArgs *__restrict__ grids, const int2 *__restrict__ order, int64_t total,
+    unsigned long long *__restrict__ counter) {
+    __shared__ FusedSmem<real, 1> sm;
+    batch_queue<real, Tiles<real>, 0>(grids, order, total, counter, sm);
+}
+
+// The same queue over grids in one periodic box (nearest-image walk, the
+// periodic sums of TilesPeriodic; LOCAL: the group-centre cubics compiled in).
+template <typename real, int WAVES, bool LOCAL>
+__global__ __launch_bounds__(256, WAVES) void batch_walk_potential_periodic_kernel(
+    const WalkArgs *__restrict__ grids, const int2 *__restrict__ order, int64_t total,
+    unsigned long long *__restrict__ counter) {
+    __shared__ FusedSmem<real, 1> sm;
+    batch_queue<real, TilesPeriodic<real, LOCAL>, 2>(grids, order, total, counter, sm);
 }
 
 // Clears the queue counter and the device flags of every grid in a batch
@@ -2390,6 +2411,32 @@ hipError_t launch_batch_walk_potential(const WalkArgs *grids, const int2 *order,
 }
 
 int fused_waves_per_simd(int precision) { return precision == BH_FP64 ? kFusedDefaultWaves64 : kFusedDefaultWaves32; }
+
+int periodic_waves_per_simd(int precision, bool local) {
+    return precision == BH_FP64 ? kPeriodicWaves64 : (local ? kPeriodicWavesCubic : kPeriodicWaves32);
+}
+
+hipError_t launch_batch_walk_potential_periodic(const WalkArgs *grids, const int2 *order, int64_t total,
+                                                unsigned long long *counter, int precision, bool local,
+                                                int workgroups, hipStream_t s) {
+    const dim3 grid(workgroups), block(256);
+#define BH_BATCH_PERIODIC(T, W, LOC)                                                                         \
+    hipLaunchKernelGGL((batch_walk_potential_periodic_kernel<T, W, LOC>), grid, block, 0, s, grids, order, total, \
+                       counter)
+    if (precision == BH_FP64) {
+        if (local)
+            BH_BATCH_PERIODIC(double, kPeriodicWaves64, true);
+        else
+            BH_BATCH_PERIODIC(double, kPeriodicWaves64, false);
+    } else {
+        if (local)
+            BH_BATCH_PERIODIC(float, kPeriodicWavesCubic, true);
+        else
+            BH_BATCH_PERIODIC(float, kPeriodicWaves32, false);
+    }
+#undef BH_BATCH_PERIODIC
+    return hipGetLastError();
+}
 
 bool fused_variant_exists(int precision, int waves) {
     return precision == BH_FP64 ? (waves == 2 || waves == 4) : (waves == 4 || waves == 6 || waves == 8);

@@ -1,4 +1,5 @@
-"""Batched solves: many grids in one persistent launch, queue orders, graph replay.
+"""Batched solves: many grids in one persistent launch, queue orders, graph replay,
+and the same for grids in one periodic box.
 
 Each group is computed exactly as bh_walk_potential computes it, so every
 grid's potential must equal its single-grid solve bit for bit, whatever the
@@ -46,6 +47,38 @@ def _reference(solvers, rho, theta, precision):
         s.solve_fused(r, theta, None, precision, 1.0, phi)
         out.append(phi)
     return out
+
+
+@pytest.mark.parametrize("precision", [B.BH_FP32, B.BH_FP64])
+def test_periodic_batch_equals_single_grid_solves(batch, precision):
+    """bh_batch_solve_periodic: every grid of the batch in the same periodic box (side 1, one 33^3 table, its
+    default budget for the group-centre cubics): potentials and counts equal bh_walk_potential_periodic's on each
+    grid, bit for bit; a table of another box is refused."""
+    grids, solvers, ctx, handles, b, rho = batch
+    table = B.bh_ewald_create(ctx, 1.0, 33)
+    ref, ref_counts = [], []
+    for s_, r in zip(solvers, rho):
+        t = B.bh_ewald_create(s_.ctx, 1.0, 33)
+        phi = torch.empty_like(r)
+        cn = torch.zeros((s_.info["n_groups"], 2), dtype=torch.int32, device="cuda")
+        s_.solve_periodic(r, t, 0.6, None, precision, 1.0, phi, cn)
+        torch.cuda.synchronize()
+        B.bh_ewald_destroy(t)
+        ref.append(phi)
+        ref_counts.append(cn.cpu().numpy())
+    phi = [torch.full_like(r, float("nan")) for r in rho]
+    B.bh_batch_solve_periodic(ctx, b, table, rho, phi, 0.6, None, precision, 1.0)
+    B.bh_batch_check(ctx, b)
+    counts = B.bh_batch_counts(ctx, b)
+    base = np.concatenate([[0], np.cumsum([c.shape[0] for c in ref_counts])])
+    for k, (p, q) in enumerate(zip(phi, ref)):
+        assert torch.equal(p, q), k
+        assert np.array_equal(counts[base[k]:base[k + 1]], ref_counts[k]), k
+    other = B.bh_ewald_create(ctx, 2.0, 9)
+    with pytest.raises(B.BHError):
+        B.bh_batch_solve_periodic(ctx, b, other, rho, phi, 0.6, None, precision, 1.0)
+    B.bh_ewald_destroy(other)
+    B.bh_ewald_destroy(table)
 
 
 @pytest.mark.parametrize("precision", [B.BH_FP32, B.BH_FP64])
