@@ -187,6 +187,31 @@ def run_batched(args, dev):
     log("separate solves fp32 %.2f ms, fp64 %.2f ms; one batched launch fp32 %.2f ms, fp64 %.2f ms" % (
         ms_sep["fp32"], ms_sep["fp64"], ms_eager, ms_eager64))
 
+    # the same grids in one periodic box (every grid lies in the unit box): separate periodic solves against one
+    # batched periodic launch, fp32, the same theta, the table's default budget for the group-centre cubics
+    table = B.bh_ewald_create(ctx, 1.0, EWALD_POINTS)
+    phi_b = [torch.empty_like(r) for r in rho]
+    ms_list = [B.bh_build_moments(ctx, h, r) for h, r in zip(handles, rho)]
+
+    def separate_periodic():
+        for h, r, p_, m in zip(handles, rho, phi, ms_list):
+            B.bh_build_moments(ctx, h, r, m)
+            B.bh_walk_potential_periodic(ctx, h, m, table, theta, None, B.BH_FP32, 1.0, p_, None)
+    ms_sep_per = timed(separate_periodic, 2)
+    ms_batch_per = timed(lambda: B.bh_batch_solve_periodic(ctx, batch, table, rho, phi_b, theta, None, B.BH_FP32,
+                                                           1.0), 2)
+    B.bh_batch_check(ctx, batch)
+    same_per = all(bool(torch.equal(a, b_)) for a, b_ in zip(phi, phi_b))
+    for m in ms_list:
+        B.bh_moments_destroy(m)
+    B.bh_ewald_destroy(table)
+    del phi_b
+    periodic_batched = dict(theta=theta, separate_fp32_ms=ms_sep_per, batched_fp32_ms=ms_batch_per,
+                            batched_mcells_per_s=ncells / ms_batch_per / 1e3,
+                            speedup_vs_separate=ms_sep_per / ms_batch_per, same_bits_as_separate=same_per)
+    log("periodic box: separate solves fp32 %.2f ms, one batched launch %.2f ms (%.2fx), same bits %s" % (
+        ms_sep_per, ms_batch_per, ms_sep_per / ms_batch_per, same_per))
+
     t0 = time.time()
     best, best_ms, table = B.bh_batch_autotune(ctx, batch, rho, phi, theta, None, B.BH_FP32, 1.0, reps=3)
     log("autotuner: %d candidates in %.1f s, best %s at %.2f ms" % (len(table), time.time() - t0, best, best_ms))
@@ -264,6 +289,7 @@ def run_batched(args, dev):
         "cpu_baseline": cpu,
         "topology_ms": topo_ms,
         "sweep": sweep,
+        "periodic_batched": periodic_batched,
     }
     print(json.dumps(out), flush=True)
     B.bh_batch_destroy(batch)
